@@ -1,0 +1,258 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these re-type the oracle's own formulas: each compares it with a
+closed form, an independent library routine (SVD, LAPACK CS decomposition),
+an exactness lemma, an invariance or a bound stated in the paper.
+"""
+import numpy as np
+import pytest
+from scipy.linalg import cossin, null_space
+
+from oracle import rgsvd as O
+from oracle.philox import STREAM_G1
+from paper_2404_09459_amd import inputs as I
+
+
+def _tiny_gmp(m, p, n, seed):
+    rng = np.random.default_rng(seed)
+    return rng.standard_normal((m, n)), rng.standard_normal((p, n))
+
+
+# ------------------------------------------------------- basis extraction ---
+@pytest.mark.parametrize("m,n,q", [(40, 12, 0), (12, 40, 1), (30, 30, 2)])
+def test_lemma_c2_full_sketch_is_exact(m, n, q):
+    """Lemma c2: with l = min(m, n) the basis reproduces G exactly."""
+    G = np.random.default_rng(m * n).standard_normal((m, n))
+    Q = O.basis_fixed(G, min(m, n), q, 5, STREAM_G1)
+    assert np.linalg.norm(G - Q @ (Q.T @ G)) <= 1e-13 * np.linalg.norm(G)
+    assert np.linalg.norm(Q.T @ Q - np.eye(Q.shape[1])) <= 1e-14
+
+
+def test_adaptive_reaches_exactness_and_residual_identity():
+    """Algorithm 1 run to l = min(m, n) is exact (Lemma c2); its cumulative
+    residual equals the directly measured ||(I - QQ^T) G||_F."""
+    G = np.random.default_rng(1).standard_normal((50, 23))
+    Q, hist = O.basis_adaptive(G, 1e-300, 5, 9, STREAM_G1)
+    assert Q.shape[1] == 23
+    assert np.linalg.norm(G - Q @ (Q.T @ G)) <= 1e-13 * np.linalg.norm(G)
+    # residual identity after each block
+    Q2, hist2 = O.basis_adaptive(G, 1e-300, 5, 9, STREAM_G1, lmax=15)
+    direct = np.linalg.norm(G - Q2 @ (Q2.T @ G))
+    assert abs(hist2[-1] - direct) <= 1e-10 * np.linalg.norm(G)
+
+
+def test_adaptive_first_block_is_fixed_sketch_prefix():
+    """Global column indexing: the first adaptive block equals the fixed
+    sketch with l = b and no power iteration."""
+    G = np.random.default_rng(2).standard_normal((60, 40))
+    Qa, _ = O.basis_adaptive(G, 1e-300, 8, 11, STREAM_G1, lmax=8)
+    Qf = O.basis_fixed(G, 8, 0, 11, STREAM_G1)
+    assert np.allclose(Qa, Qf, atol=1e-13)
+
+
+def test_adaptive_stops_on_exact_low_rank():
+    j = np.arange(6)
+    G1, _ = I.lowrank_pair(80, 80, 60, 6, 0.5 ** j, 0.5 ** j, 3, noise_entry=0.0)
+    Q, hist = O.basis_adaptive(G1, 1e-10, 4, 2, STREAM_G1)
+    assert Q.shape[1] == 8 and hist[-1] < 1e-10
+
+
+def test_theorem_projector_expected_residual_bound():
+    """Theorem "projector": E||(I - Q1 Q1^T) G1||_F^2 <=
+    eta (1 + k/(p-1)) sum_{j>k} phi_j^2, eta = sigma_max(G1^T G1 + G2^T G2),
+    q = 0.  Mean over 200 seeds on a GMP with decaying GSVs."""
+    rng = np.random.default_rng(7)
+    n, m, p = 14, 20, 18
+    alpha = np.sort(0.6 ** np.arange(n))[::-1]
+    alpha = alpha / np.sqrt(1 + alpha ** 2)          # in (0,1), decaying
+    beta = np.sqrt(1 - alpha ** 2)
+    R = rng.standard_normal((n, n))
+    U = np.linalg.qr(rng.standard_normal((m, n)))[0]
+    V = np.linalg.qr(rng.standard_normal((p, n)))[0]
+    G1 = (U * alpha) @ R
+    G2 = (V * beta) @ R
+    eta = np.linalg.eigvalsh(G1.T @ G1 + G2.T @ G2).max()
+    k, ov = 4, 3
+    bound = eta * (1 + k / (ov - 1)) * np.sum(alpha[k:] ** 2)
+    res = [np.linalg.norm(G1 - (Q := O.basis_fixed(G1, k + ov, 0, s, STREAM_G1)) @ (Q.T @ G1)) ** 2
+           for s in range(200)]
+    assert np.mean(res) <= bound
+    # and the bound is not vacuous here
+    assert np.mean(res) < np.linalg.norm(G1) ** 2
+
+
+# ------------------------------------------------------------ small step ---
+@pytest.mark.parametrize("m,p,n", [(7, 9, 6), (5, 8, 10), (12, 4, 9), (6, 6, 6)])
+def test_full_gsvd_matches_lapack_cs_decomposition(m, p, n):
+    """alpha of the deterministic GSVD (Algorithm 2 with Q_i = I) equals the
+    cosines of LAPACK's CS decomposition (xORCSD via scipy.linalg.cossin) of
+    the orthogonal completion of the stacked QR factor."""
+    G1, G2 = _tiny_gmp(m, p, n, m + 10 * p + 100 * n)
+    ref = O.full_gsvd(G1, G2)
+    L, _ = np.linalg.qr(np.vstack([G1, G2]))
+    X = np.hstack([L, null_space(L.T)])                 # (m+p) square orthogonal
+    _, cs, _ = cossin(X, p=m, q=n)
+    cos = np.sort(np.linalg.svd(cs[:m, :n], compute_uv=False))[::-1]
+    alpha = np.sort(ref["alpha"])[::-1]
+    assert np.allclose(alpha[:len(cos)], cos, atol=1e-12)
+    assert np.allclose(alpha[len(cos):], 0.0, atol=1e-12)
+    assert np.allclose(ref["alpha"] ** 2 + ref["beta"] ** 2, 1.0, atol=1e-13)
+
+
+def test_special_case_second_matrix_identity():
+    """G2 = I_n: alpha_i / beta_i are the singular values of G1 (Van Loan)."""
+    G1 = np.random.default_rng(4).standard_normal((11, 7))
+    ref = O.full_gsvd(G1, np.eye(7))
+    s = np.linalg.svd(G1, compute_uv=False)
+    assert np.allclose(ref["alpha"] / ref["beta"], s, rtol=1e-12)
+
+
+@pytest.mark.parametrize("c", [0.3, 1.0, 2.5])
+def test_special_case_scaled_pair(c):
+    """G1 = c G2: every alpha = c/sqrt(1+c^2), theta = arctan(c) - pi/4,
+    all P equal and D = 1."""
+    G2 = np.random.default_rng(5).standard_normal((9, 6))
+    ref = O.full_gsvd(c * G2, G2)
+    assert np.allclose(ref["alpha"], c / np.sqrt(1 + c * c), atol=1e-13)
+    assert np.allclose(ref["theta"], np.arctan(c) - np.pi / 4, atol=1e-13)
+    assert np.allclose(ref["P1"], 1 / 6, atol=1e-13)
+    assert abs(ref["D1"] - 1) < 1e-13 and abs(ref["D2"] - 1) < 1e-13
+
+
+def test_special_case_disjoint_supports():
+    """G1 = [A 0], G2 = [0 B]: alpha in {1, 0}, split by the supports."""
+    rng = np.random.default_rng(6)
+    G1 = np.hstack([rng.standard_normal((8, 3)), np.zeros((8, 4))])
+    G2 = np.hstack([np.zeros((9, 3)), rng.standard_normal((9, 4))])
+    ref = O.full_gsvd(G1, G2)
+    assert np.allclose(ref["alpha"], [1, 1, 1, 0, 0, 0, 0], atol=1e-13)
+    assert np.allclose(ref["theta"][:3], np.pi / 4) and np.allclose(ref["theta"][3:], -np.pi / 4)
+
+
+def test_swap_pair_mirrors_everything():
+    """Swapping G1 and G2 swaps alpha and beta, reverses the order and maps
+    theta -> -theta, P1 <-> P2, D1 <-> D2."""
+    G1, G2 = _tiny_gmp(8, 10, 6, 8)
+    a = O.full_gsvd(G1, G2)
+    b = O.full_gsvd(G2, G1)
+    assert np.allclose(a["alpha"], b["beta"][::-1], atol=1e-13)
+    assert np.allclose(a["theta"], -b["theta"][::-1], atol=1e-13)
+    assert np.allclose(a["P1"], b["P2"][::-1], atol=1e-13)
+    assert abs(a["D1"] - b["D2"]) < 1e-13 and abs(a["D2"] - b["D1"]) < 1e-13
+
+
+def test_invariance_under_left_orthogonal_and_right_nonsingular():
+    """alpha is invariant under G_i -> O_i G_i and (G1, G2) -> (G1 M, G2 M)."""
+    rng = np.random.default_rng(9)
+    G1, G2 = _tiny_gmp(10, 8, 6, 10)
+    O1 = np.linalg.qr(rng.standard_normal((10, 10)))[0]
+    O2 = np.linalg.qr(rng.standard_normal((8, 8)))[0]
+    M = rng.standard_normal((6, 6)) + 3 * np.eye(6)
+    a = O.full_gsvd(G1, G2)["alpha"]
+    assert np.allclose(O.full_gsvd(O1 @ G1, O2 @ G2)["alpha"], a, atol=1e-12)
+    assert np.allclose(O.full_gsvd(G1 @ M, G2 @ M)["alpha"], a, atol=1e-11)
+
+
+@pytest.mark.parametrize("m,p,n", [(9, 7, 6), (6, 9, 8), (10, 10, 5)])
+def test_randomized_equals_deterministic_on_tiny_gmp(m, p, n):
+    """With l_i = min(m_i, n) and t = n the randomized GSVD is the
+    deterministic one (Lemma c2 plus eq. (gsvd-reduced))."""
+    G1, G2 = _tiny_gmp(m, p, n, 3 * m + p + n)
+    ref = O.full_gsvd(G1, G2)
+    r = O.rgsvd(G1, G2, k=n, oversample=0, q=0, seed=17,
+                l1=min(m, n), l2=min(p, n), t=n)
+    assert np.allclose(r["alpha"], ref["alpha"], atol=1e-12)
+    assert np.allclose(r["beta"], ref["beta"], atol=1e-12)
+    for key in ("theta", "P1", "P2"):
+        assert np.allclose(r[key], ref[key], atol=1e-12)
+    assert abs(r["D1"] - ref["D1"]) < 1e-12 and abs(r["D2"] - ref["D2"]) < 1e-12
+
+
+def test_planted_closed_form_noiseless():
+    """G_i = U_i diag(s_i) Z^T with s1 = 0.8^j, s2 = 0.7^j: alpha_j =
+    1/sqrt(1 + (7/8)^(2j)) and theta_j = arctan((8/7)^j) - pi/4 (sorted)."""
+    j = np.arange(20)
+    G1, G2 = I.lowrank_pair(1000, 800, 300, 20, 0.8 ** j, 0.7 ** j, 101, noise_entry=0.0)
+    r = O.rgsvd(G1, G2, 20, 10, 1, 1)
+    a_star = np.sort(1 / np.sqrt(1 + (7 / 8) ** (2 * j)))[::-1]
+    th_star = np.sort(np.arctan((8 / 7) ** j) - np.pi / 4)[::-1]
+    assert np.max(np.abs(r["alpha"] - a_star)) < 1e-13
+    assert np.max(np.abs(r["theta"] - th_star)) < 1e-13
+    assert np.max(np.abs(r["alpha"] ** 2 + r["beta"] ** 2 - 1)) < 1e-14
+
+
+def test_planted_with_noise_and_reconstruction():
+    w = I.small_fp64_pair()
+    r = O.rgsvd(w["G1"], w["G2"], w["k"], w["oversample"], w["q"], w["seed"])
+    j = np.arange(20)
+    a_star = np.sort(1 / np.sqrt(1 + (7 / 8) ** (2 * j)))[::-1]
+    assert np.max(np.abs(r["alpha"] - a_star)) < 5e-5
+    # reconstruction of the dominant part, orthonormal U, V
+    G1, G2 = w["G1"], w["G2"]
+    e1 = np.linalg.norm(G1 - (r["U"] * r["alpha"]) @ r["R"]) / np.linalg.norm(G1)
+    e2 = np.linalg.norm(G2 - (r["V"] * r["beta"]) @ r["R"]) / np.linalg.norm(G2)
+    assert e1 < 1e-3 and e2 < 1e-3
+    assert np.allclose(r["U"].T @ r["U"], np.eye(20), atol=1e-12)
+    assert np.allclose(r["V"].T @ r["V"], np.eye(20), atol=1e-12)
+    # alpha descending, theta non-increasing within [-pi/4, pi/4]
+    assert np.all(np.diff(r["alpha"]) <= 1e-15)
+    assert np.all(np.abs(r["theta"]) <= np.pi / 4 + 1e-15)
+    # the paper's beta = sqrt(1 - alpha^2) agrees to sqrt(u)
+    assert np.max(np.abs(r["beta"] - r["beta_paper"])) < 1e-7
+
+
+def test_paper_generator_full_mode():
+    """Real version of the paper's synthetic GMP (Sec. 4.1), tall shape, full
+    mode t = n with l_i = rank: GSV errors at the paper's 1e-10 level."""
+    G1, G2, a_star, b_star = I.planted_gmp(90, 70, 40, seed=11)
+    rank = int(round(0.6 * 40))
+    r = O.rgsvd(G1, G2, k=40, oversample=0, q=1, seed=3, l1=rank, l2=rank, t=40)
+    assert np.linalg.norm(np.sort(r["alpha"])[::-1] - a_star) < 1e-10
+    assert np.linalg.norm(np.sort(r["beta"]) - np.sort(b_star)) < 1e-10
+
+
+def test_perturbation_bound_corollary_and_theorem_exp():
+    """Corollary (error bounds) and Theorem exp (i): for the compressed pair
+    G~ = diag(Q1Q1^T, Q2Q2^T) G of a GMP, max|d alpha| <= E and
+    |d theta| <= arcsin(2E), E = sqrt(2)||dG||_F min(||G^+||, ||G~^+||)."""
+    rng = np.random.default_rng(12)
+    m, p, n = 14, 12, 10
+    G1 = rng.standard_normal((m, n)) * (0.1 ** np.arange(n))
+    G2 = rng.standard_normal((p, n)) * (0.1 ** np.arange(n))[::-1]
+    exact = O.full_gsvd(G1, G2)
+    r = O.rgsvd(G1, G2, k=n, oversample=0, q=0, seed=4, l1=7, l2=7, t=n)
+    Q1, Q2 = r["Q1"], r["Q2"]
+    Gt = np.vstack([Q1 @ (Q1.T @ G1), Q2 @ (Q2.T @ G2)])
+    G = np.vstack([G1, G2])
+    dG = Gt - G
+    E = np.sqrt(2) * np.linalg.norm(dG) * min(np.linalg.norm(np.linalg.pinv(G), 2),
+                                              np.linalg.norm(np.linalg.pinv(Gt), 2))
+    assert E < 0.5
+    assert np.max(np.abs(r["alpha"] - exact["alpha"])) <= E
+    assert np.max(np.abs(r["theta"] - exact["theta"])) <= np.arcsin(min(1.0, 2 * E))
+
+
+# ------------------------------------------------------------ quantities ---
+def test_quantities_theta_parametrisation():
+    """Proof of Theorem exp: with theta_nu = alpha_nu and beta^2 = 1 - alpha^2,
+    P_{2,nu} = (1 - theta^2)/(n - tr Theta^2) and D from the logs of theta."""
+    alpha = np.array([0.99, 0.8, 0.6, 0.3, 0.05])
+    beta = np.sqrt(1 - alpha ** 2)
+    q = O.quantities(alpha, beta)
+    n = len(alpha)
+    tr = np.sum(alpha ** 2)
+    assert np.allclose(q["P2"], (1 - alpha ** 2) / (n - tr), atol=1e-15)
+    D1 = -np.sum(alpha ** 2 / tr * (2 * np.log(alpha) - np.log(tr))) / np.log(n)
+    D2 = -np.sum((1 - alpha ** 2) / (n - tr) * (np.log(1 - alpha ** 2) - np.log(n - tr))) / np.log(n)
+    assert abs(q["D1"] - D1) < 1e-14 and abs(q["D2"] - D2) < 1e-14
+    assert np.allclose(q["theta"], np.arctan(alpha / beta) - np.pi / 4, atol=1e-15)
+    assert abs(np.sum(q["P1"]) - 1) < 1e-15 and 0 <= q["D1"] <= 1
+
+
+def test_quantities_edge_cases():
+    q = O.quantities(np.array([1.0, 0.0]), np.array([0.0, 1.0]))
+    assert q["theta"][0] == np.pi / 4 and q["theta"][1] == -np.pi / 4
+    assert np.isinf(q["rho"][0])
+    assert q["D1"] == 0.0 and q["D2"] == 0.0            # one genelet carries all
+    q1 = O.quantities(np.array([0.6]), np.array([0.8]))
+    assert q1["D1"] == 0.0                               # t = 1
