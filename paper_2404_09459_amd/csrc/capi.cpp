@@ -1,0 +1,738 @@
+// C-ABI of the randomized GSVD: plan, workspace layout, job tables and the
+// enqueue sequence of one run.  Host code only; the arithmetic is in the
+// kernels.
+//
+// Sequence of one run (per pair; every launch is grouped over all matrices):
+//   Omega_i^T <- generator                      (Algorithm 1's Gaussian block)
+//   Y_i = G_i Omega_i ; Q_i = orth(Y_i)         (Algorithm 1's product and QR)
+//   q times: W_i = orth(G_i^T Q_i); Q_i = orth(G_i W_i)   (subspace iteration)
+//   B_i = Q_i^T G_i                             (Algorithm 2's compressed pair)
+//   M = [B1; B2][B1; B2]^T ; small FP64 step    (Algorithm 2 with truncation)
+//   R = (L Y)^T [B1; B2];  U = Q1 X1;  V = Q2 X2 (recovery after Algorithm 2)
+// orth() is CholeskyQR with an FP64 Gram and Cholesky: one pass for the
+// intermediate bases (their span is what the next product uses), two passes
+// (CholeskyQR2) for the final Q_i.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/rgsvd.h"
+#include "common.hpp"
+#include "jobs.hpp"
+#include "launch.hpp"
+#include "small.hpp"
+
+using namespace rg;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+inline int64_t upi(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+inline int ct_of(int L) {
+  int c = (L + 15) / 16;
+  if (c <= 1) return 1;
+  if (c <= 2) return 2;
+  if (c <= 4) return 4;
+  if (c <= 8) return 8;
+  return 16;
+}
+
+enum Kind { K_ZERO, K_COPY, K_GEN, K_NN, K_AB, K_GRAM, K_RED, K_CHOL, K_SMALL, K_SIGN, K_SCALE };
+
+struct Stage {
+  Kind kind;
+  size_t joff = 0, poff = 0;  // byte offsets of job array and prefix table in the job area
+  int nj = 0, tiles = 0;
+  int prec = 0, gdt = 0, rt = 1, ct = 1, js = 1;
+  int ta = 0, tb = 0, td = 0;
+  bool sym = false, f64 = false;
+  int npad_max = 0;
+  size_t zoff = 0, zbytes = 0;  // K_ZERO: workspace range
+};
+
+struct CopyJob { const uint32_t* src; uint32_t* dst; int64_t nwords; };
+
+struct SideLay {
+  int m = 0, n = 0, l = 0, L = 0, which = 0, pair = 0;
+  int ldy = 0, ldw = 0;
+  int nchunk = 1, mchunk = 0;
+  int gch_m = 1, gcl_m = 0, gch_n = 1, gcl_n = 0;
+  size_t Yt = 0, Wt = 0, part = 0, gpart = 0, gram = 0, sinv = 0;
+  const void* G = nullptr; int64_t ldg = 0;
+  uint64_t seed = 0; int stream = 1;
+};
+
+struct PairLay {
+  int64_t m = 0, p = 0, n = 0, k = 0, o = 0;
+  int q = 0, l1 = 0, l2 = 0, t = 0, N = 0, Npad = 0;
+  uint64_t seed = 0;
+  int gch = 1, gcl = 0;
+  size_t mpart = 0, M = 0, work = 0, sigma = 0, X1t = 0, X2t = 0, Rcoef = 0, sgn = 0, info = 0;
+  size_t alpha = 0;  // internal outputs when the caller passes null
+  rgsvd_out out{};
+};
+
+}  // namespace
+
+struct rgsvd_plan_s {
+  rgsvd_desc d{};
+  bool batched = false;
+  int prec = 0, gdt = 0, mode = 0;
+  int Lmax = 16, npadG = 64;
+  std::vector<PairLay> pairs;
+  std::vector<SideLay> sides;
+  size_t off_chol = 0, off_jobs = 0, jobs_cap = 0, ws = 0;
+  int nchol_slots = 0;
+  // job tables
+  std::vector<unsigned char> host;   // serialized job tables
+  std::vector<Stage> stages;
+  void* pinned = nullptr;
+  hipEvent_t ev = nullptr;
+  bool ev_pending = false;
+  // cache of the last bound pointers
+  const void* lastG1 = nullptr; const void* lastG2 = nullptr; void* lastws = nullptr;
+  int64_t lastld1 = 0, lastld2 = 0;
+  rgsvd_out lastout{};
+  bool bound = false;
+  // batched graph
+  hipGraphExec_t gexec = nullptr;
+  void* bws = nullptr;
+  // sizing network
+  float* mlp = nullptr;
+};
+
+namespace {
+
+bool out_eq(const rgsvd_out& a, const rgsvd_out& b) { return std::memcmp(&a, &b, sizeof(a)) == 0; }
+
+// --------------------------------------------------------------- layout --
+int layout(rgsvd_plan_s* P) {
+  const int prec = P->prec;
+  const size_t wsz = (prec == P64) ? 8 : 4;   // working element size
+  const size_t psz = wsz;                      // partial element size
+  size_t off = 0;
+  auto take = [&](size_t bytes) { size_t o = off; off = up(off + bytes, ALIGN); return o; };
+  P->Lmax = 16;
+  for (auto& pr : P->pairs) P->Lmax = std::max(P->Lmax, (int)upi(std::max(pr.l1, pr.l2), 16));
+  P->npadG = (int)upi(P->Lmax, 64);
+  const int nsides = 2 * (int)P->pairs.size();
+  P->sides.clear();
+  for (size_t pi = 0; pi < P->pairs.size(); ++pi) {
+    PairLay& pr = P->pairs[pi];
+    for (int w = 0; w < 2; ++w) {
+      SideLay s;
+      s.pair = (int)pi; s.which = w;
+      s.m = (int)(w ? pr.p : pr.m); s.n = (int)pr.n;
+      s.l = w ? pr.l2 : pr.l1;
+      s.L = (int)upi(s.l, 16);
+      s.ldy = (int)upi(s.m, 64); s.ldw = (int)upi(s.n, 64);
+      s.seed = pr.seed; s.stream = w ? 2 : 1;
+      // G^T Q row chunks
+      int js = (prec == P64) ? 2 : (ct_of(s.L) <= 8 ? 4 : 2);
+      int jt = (int)((s.n + 64 * js - 1) / (64 * js));
+      int target = std::max(1, 1024 / std::max(1, nsides));
+      int nch = std::max(1, std::min((s.m + 255) / 256, (target + jt - 1) / jt));
+      int mch = (int)upi((s.m + nch - 1) / nch, 32);
+      nch = (s.m + mch - 1) / mch;
+      s.nchunk = nch; s.mchunk = mch;
+      // Gram chunks over m and over n
+      int nb = P->npadG / 64, nblk = nb * (nb + 1) / 2;
+      int gt = std::max(1, 512 / std::max(1, nblk * nsides));
+      s.gch_m = std::max(1, std::min((s.m + 255) / 256, gt));
+      s.gcl_m = (int)upi((s.m + s.gch_m - 1) / s.gch_m, 32);
+      s.gch_m = (s.m + s.gcl_m - 1) / s.gcl_m;
+      s.gch_n = std::max(1, std::min((s.n + 255) / 256, gt));
+      s.gcl_n = (int)upi((s.n + s.gch_n - 1) / s.gch_n, 32);
+      s.gch_n = (s.n + s.gcl_n - 1) / s.gcl_n;
+      s.Yt = take((size_t)s.L * s.ldy * wsz);
+      s.Wt = take((size_t)s.L * s.ldw * wsz);
+      s.part = take((size_t)s.nchunk * s.L * s.ldw * psz);
+      int gch = std::max(s.gch_m, s.gch_n);
+      s.gpart = take((size_t)gch * P->npadG * P->npadG * 8);
+      s.gram = take((size_t)P->npadG * P->npadG * 8);
+      s.sinv = take((size_t)P->npadG * P->npadG * 8);
+      P->sides.push_back(s);
+    }
+  }
+  for (auto& pr : P->pairs) {
+    pr.N = pr.l1 + pr.l2;
+    pr.Npad = (int)upi(pr.N, 64);
+    int nb = pr.Npad / 64, nblk = nb * (nb + 1) / 2;
+    int gt = std::max(1, 512 / std::max(1, nblk * (int)P->pairs.size()));
+    pr.gch = std::max(1, std::min((int)((pr.n + 255) / 256), gt));
+    pr.gcl = (int)upi((pr.n + pr.gch - 1) / pr.gch, 32);
+    pr.gch = (int)((pr.n + pr.gcl - 1) / pr.gcl);
+    pr.mpart = take((size_t)pr.gch * pr.Npad * pr.Npad * 8);
+    pr.M = take((size_t)pr.Npad * pr.Npad * 8);
+    size_t N = pr.N, t = pr.t;
+    pr.work = take((N * N + N * t + t * t + (size_t)pr.l1 * t) * 8);
+    pr.sigma = take(N * 8);
+    pr.X1t = take(t * pr.l1 * 8);
+    pr.X2t = take(t * pr.l2 * 8);
+    pr.Rcoef = take(t * N * 8);
+    pr.sgn = take(t * 8);
+    pr.info = take(RGSVD_INFO_WORDS * 4);
+    pr.alpha = take(t * 8 * 5 + 16);   // alpha, beta, theta, P1, P2, D when not given
+  }
+  P->nchol_slots = 0;
+  if (P->npadG > CHOL_LDS_MAX) P->nchol_slots = nsides;
+  P->off_chol = take((size_t)std::max(1, P->nchol_slots) * (CHOL_MAX * CHOL_MAX + 2 * CHOL_MAX) * 8);
+  // job area: generous bound
+  size_t per_side = 64 * 1024 + (size_t)(P->sides.empty() ? 0 : P->sides[0].nchunk) * 256;
+  P->jobs_cap = up(per_side * nsides + 256 * 1024, ALIGN);
+  P->off_jobs = take(P->jobs_cap);
+  P->ws = off;
+  return RGSVD_OK;
+}
+
+// ------------------------------------------------------------ job tables --
+struct Builder {
+  rgsvd_plan_s* P;
+  std::vector<unsigned char>& h;
+  explicit Builder(rgsvd_plan_s* p) : P(p), h(p->host) {}
+  template <typename T>
+  size_t put(const std::vector<T>& v) {
+    size_t o = up(h.size(), 64);
+    h.resize(o + v.size() * sizeof(T));
+    if (!v.empty()) std::memcpy(h.data() + o, v.data(), v.size() * sizeof(T));
+    return o;
+  }
+  // add a stage from jobs and per-job tile counts
+  template <typename T>
+  Stage& add(Kind k, const std::vector<T>& jobs, const std::vector<int>& tiles) {
+    Stage s;
+    s.kind = k;
+    s.joff = put(jobs);
+    std::vector<int> pre(jobs.size() + 1, 0);
+    for (size_t i = 0; i < jobs.size(); ++i) pre[i + 1] = pre[i] + tiles[i];
+    s.poff = put(pre);
+    s.nj = (int)jobs.size();
+    s.tiles = pre.back();
+    P->stages.push_back(s);
+    return P->stages.back();
+  }
+};
+
+inline char* WS(void* ws, size_t off) { return (char*)ws + off; }
+
+int build(rgsvd_plan_s* P, void* ws) {
+  P->host.clear();
+  P->stages.clear();
+  Builder B(P);
+  const int prec = P->prec;
+  const int wt = (prec == P64) ? 0 : 1;            // working type code
+  const int gt = (P->gdt == RGSVD_F64) ? 0 : 1;
+  const bool mixed = (prec == PBF);
+  const int ctL = ct_of(P->Lmax);
+  std::vector<SideLay>& S = P->sides;
+  const int ns = (int)S.size();
+
+  // 0. zero the W buffers (their padding rows must read as zero) and copy
+  //    the info templates
+  for (auto& s : S) {
+    Stage z; z.kind = K_ZERO; z.zoff = s.Wt;
+    z.zbytes = (size_t)s.L * s.ldw * (prec == P64 ? 8 : 4);
+    P->stages.push_back(z);
+  }
+  {
+    std::vector<uint32_t> tmpl;
+    std::vector<CopyJob> cj;
+    std::vector<int> tl;
+    for (auto& pr : P->pairs) {
+      uint32_t w[RGSVD_INFO_WORDS] = {0};
+      w[1] = pr.l1; w[2] = pr.l2; w[3] = pr.q;
+      for (int i = 0; i < RGSVD_INFO_WORDS; ++i) tmpl.push_back(w[i]);
+    }
+    size_t toff = B.put(tmpl);
+    for (size_t i = 0; i < P->pairs.size(); ++i) {
+      auto& pr = P->pairs[i];
+      int32_t* info = pr.out.info ? pr.out.info : (int32_t*)WS(ws, pr.info);
+      cj.push_back(CopyJob{(const uint32_t*)WS(ws, P->off_jobs + toff) + i * RGSVD_INFO_WORDS,
+                           (uint32_t*)info, RGSVD_INFO_WORDS});
+      tl.push_back(1);
+    }
+    B.add(K_COPY, cj, tl);
+  }
+  auto info_of = [&](int pair) -> int32_t* {
+    auto& pr = P->pairs[pair];
+    return pr.out.info ? pr.out.info : (int32_t*)WS(ws, pr.info);
+  };
+
+  // 1. Omega
+  {
+    std::vector<GenJob> j; std::vector<int> tl;
+    for (auto& s : S) {
+      GenJob g{};
+      g.Wt = WS(ws, s.Wt); g.ldw = s.ldw; g.seed = s.seed; g.n = s.n; g.col0 = 0;
+      g.ncols = s.l; g.L = s.L; g.stream = s.stream;
+      j.push_back(g);
+      int ngr = ((s.l - 1) >> 2) + 1;
+      tl.push_back(((s.n + 255) / 256) * ngr);
+    }
+    Stage& st = B.add(K_GEN, j, tl);
+    st.f64 = (prec == P64);
+  }
+
+  auto add_nn = [&](int p) {
+    std::vector<NnJob> j; std::vector<int> tl;
+    int rt = (p == P64) ? 1 : 2;
+    for (auto& s : S) {
+      NnJob x{};
+      x.G = s.G; x.Wt = WS(ws, s.Wt); x.Yt = WS(ws, s.Yt);
+      x.ldg = s.ldg; x.ldw = s.ldw; x.ldy = s.ldy; x.m = s.m; x.n = s.n; x.L = s.L;
+      j.push_back(x);
+      tl.push_back((s.m + 64 * rt - 1) / (64 * rt));
+    }
+    Stage& st = B.add(K_NN, j, tl);
+    st.prec = p; st.gdt = gt; st.rt = rt; st.ct = ctL;
+  };
+
+  // CholeskyQR passes on the Yt (ymat = true) or Wt buffers
+  auto add_orth = [&](bool ymat, int passes) {
+    const int sxp = (prec == P64) ? P64 : P32;
+    for (int ps = 0; ps < passes; ++ps) {
+      std::vector<GramJob> gj; std::vector<int> gtl;
+      std::vector<RedJob> rj; std::vector<int> rtl;
+      std::vector<CholJob> cj; std::vector<int> ctl;
+      std::vector<AbJob> aj; std::vector<int> atl;
+      const int nb = P->npadG / 64, nblk = nb * (nb + 1) / 2;
+      for (auto& s : S) {
+        int len = ymat ? s.m : s.n;
+        int ld = ymat ? s.ldy : s.ldw;
+        void* X = WS(ws, ymat ? s.Yt : s.Wt);
+        int gch = ymat ? s.gch_m : s.gch_n, gcl = ymat ? s.gcl_m : s.gcl_n;
+        GramJob g{};
+        g.X1 = X; g.X2 = nullptr; g.out = (double*)WS(ws, s.gpart);
+        g.ld1 = ld; g.ld2 = 0; g.r1 = s.L; g.r2 = 0; g.k0 = 0; g.k1 = len;
+        g.npad = P->npadG; g.clen = gcl;
+        gj.push_back(g); gtl.push_back(nblk * gch);
+        RedJob r{};
+        r.in = WS(ws, s.gpart); r.out = WS(ws, s.gram); r.sq = nullptr;
+        r.stride = (int64_t)P->npadG * P->npadG; r.count = r.stride;
+        r.nparts = gch; r.rows = P->npadG; r.cols = P->npadG; r.ldo = P->npadG; r.ldi = P->npadG;
+        rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
+        CholJob c{};
+        c.gram = (const double*)WS(ws, s.gram); c.sinv = (double*)WS(ws, s.sinv); c.r = nullptr;
+        c.info = info_of(s.pair); c.N = s.l; c.npad = P->npadG; c.flagbit = ymat ? 0 : 1;
+        cj.push_back(c); ctl.push_back(1);
+        AbJob a{};
+        a.A = WS(ws, s.sinv); a.lda = P->npadG; a.B = X; a.ldb = ld; a.D = X; a.ldd = ld;
+        a.rows = s.L; a.K = s.L; a.J = len; a.accumulate = 0; a.colscale = nullptr;
+        aj.push_back(a);
+        int js = (sxp == P64) ? 2 : (ctL <= 8 ? 4 : 2);
+        atl.push_back((len + 64 * js - 1) / (64 * js));
+      }
+      B.add(K_GRAM, gj, gtl).ta = wt;
+      Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.ta = 0; r.td = 0;
+      Stage& c = B.add(K_CHOL, cj, ctl); c.npad_max = P->npadG;
+      Stage& a = B.add(K_AB, aj, atl);
+      a.prec = sxp; a.ta = 0; a.tb = wt; a.td = wt; a.ct = ctL;
+      a.js = (sxp == P64) ? 2 : (ctL <= 8 ? 4 : 2);
+    }
+  };
+
+  // G^T Q (or Q^T G) into the Wt buffers: split over row chunks then reduced
+  auto add_tn = [&](int p) {
+    std::vector<AbJob> aj; std::vector<int> atl;
+    std::vector<RedJob> rj; std::vector<int> rtl;
+    int js = (p == P64) ? 2 : (ctL <= 8 ? 4 : 2);
+    if (p == PBF) js = 2;
+    const size_t psz = (prec == P64) ? 8 : 4;
+    for (auto& s : S) {
+      for (int c = 0; c < s.nchunk; ++c) {
+        int r0 = c * s.mchunk;
+        int rows = std::min(s.mchunk, s.m - r0);
+        AbJob a{};
+        a.A = (const char*)WS(ws, s.Yt) + (size_t)r0 * psz; a.lda = s.ldy;
+        a.B = (const char*)s.G + (size_t)r0 * s.ldg * (gt == 0 ? 8 : 4); a.ldb = s.ldg;
+        a.D = WS(ws, s.part) + (size_t)c * s.L * s.ldw * psz; a.ldd = s.ldw;
+        a.rows = s.L; a.K = rows; a.J = s.n; a.accumulate = 0; a.colscale = nullptr;
+        aj.push_back(a);
+        atl.push_back((s.n + 64 * js - 1) / (64 * js));
+      }
+      RedJob r{};
+      r.in = WS(ws, s.part); r.out = WS(ws, s.Wt); r.sq = nullptr;
+      r.stride = (int64_t)s.L * s.ldw; r.count = (int64_t)s.L * s.n;
+      r.nparts = s.nchunk; r.rows = s.L; r.cols = s.n; r.ldo = s.ldw; r.ldi = s.ldw;
+      rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
+    }
+    Stage& a = B.add(K_AB, aj, atl);
+    a.prec = p; a.ta = wt; a.tb = gt; a.td = wt; a.ct = ctL; a.js = js;
+    Stage& r = B.add(K_RED, rj, rtl);
+    r.sym = false; r.ta = wt; r.td = wt;
+  };
+
+  const int qmax = [&] { int q = 0; for (auto& pr : P->pairs) q = std::max(q, pr.q); return q; }();
+  // sketch
+  add_nn(mixed ? PBF : prec);
+  add_orth(true, qmax == 0 ? 2 : 1);
+  for (int it = 1; it <= qmax; ++it) {
+    int p = mixed ? (it < qmax ? PBF : P32) : prec;
+    add_tn(p);
+    add_orth(false, 1);
+    add_nn(p);
+    add_orth(true, it == qmax ? 2 : 1);
+  }
+  // projection B_i = Q_i^T G_i
+  add_tn(mixed ? P32 : prec);
+
+  // M = B B^T per pair
+  {
+    std::vector<GramJob> gj; std::vector<int> gtl;
+    std::vector<RedJob> rj; std::vector<int> rtl;
+    std::vector<GramJob> dummy;
+    for (size_t pi = 0; pi < P->pairs.size(); ++pi) {
+      auto& pr = P->pairs[pi];
+      auto& s1 = S[2 * pi];
+      auto& s2 = S[2 * pi + 1];
+      int nb = pr.Npad / 64, nblk = nb * (nb + 1) / 2;
+      GramJob g{};
+      g.X1 = WS(ws, s1.Wt); g.X2 = WS(ws, s2.Wt); g.out = (double*)WS(ws, pr.mpart);
+      g.ld1 = s1.ldw; g.ld2 = s2.ldw; g.r1 = pr.l1; g.r2 = pr.l2; g.k0 = 0; g.k1 = (int)pr.n;
+      g.npad = pr.Npad; g.clen = pr.gcl;
+      gj.push_back(g); gtl.push_back(nblk * pr.gch);
+      RedJob r{};
+      r.in = WS(ws, pr.mpart); r.out = WS(ws, pr.M); r.sq = nullptr;
+      r.stride = (int64_t)pr.Npad * pr.Npad; r.count = r.stride;
+      r.nparts = pr.gch; r.rows = pr.Npad; r.cols = pr.Npad; r.ldo = pr.Npad; r.ldi = pr.Npad;
+      rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
+    }
+    B.add(K_GRAM, gj, gtl).ta = wt;
+    Stage& r = B.add(K_RED, rj, rtl); r.sym = true;
+  }
+  // small step
+  {
+    std::vector<SmallJob> sj; std::vector<int> tl;
+    for (size_t pi = 0; pi < P->pairs.size(); ++pi) {
+      auto& pr = P->pairs[pi];
+      SmallJob x{};
+      x.M = (const double*)WS(ws, pr.M); x.ldm = pr.Npad;
+      x.l1 = pr.l1; x.l2 = pr.l2; x.t = pr.t; x.maxsweep = 40; x.tol = 1e-15;
+      x.work = (double*)WS(ws, pr.work);
+      x.sigma = pr.out.sigma_B ? pr.out.sigma_B : (double*)WS(ws, pr.sigma);
+      double* ia = (double*)WS(ws, pr.alpha);
+      x.alpha = pr.out.alpha ? pr.out.alpha : ia;
+      x.beta = pr.out.beta ? pr.out.beta : ia + pr.t;
+      x.theta = pr.out.theta ? pr.out.theta : ia + 2 * pr.t;
+      x.P1 = pr.out.P1 ? pr.out.P1 : ia + 3 * pr.t;
+      x.P2 = pr.out.P2 ? pr.out.P2 : ia + 4 * pr.t;
+      x.D = pr.out.D ? pr.out.D : ia + 5 * pr.t;
+      x.X1t = (double*)WS(ws, pr.X1t); x.ldx1 = pr.l1;
+      x.X2t = (double*)WS(ws, pr.X2t); x.ldx2 = pr.l2;
+      x.Rcoef = (double*)WS(ws, pr.Rcoef); x.ldr = pr.N;
+      x.info = info_of((int)pi);
+      sj.push_back(x); tl.push_back(1);
+    }
+    B.add(K_SMALL, sj, tl);
+  }
+  // recovery: R (needed for the sign convention), then U, V
+  const int ctT = ct_of([&] { int t = 1; for (auto& pr : P->pairs) t = std::max(t, pr.t); return t; }());
+  bool anyR = false, anyUV = false;
+  for (auto& pr : P->pairs) { anyR |= pr.out.R != nullptr; anyUV |= (pr.out.U || pr.out.V); }
+  if (anyR || anyUV) {
+    for (int seg = 0; seg < 2; ++seg) {
+      std::vector<AbJob> aj; std::vector<int> atl;
+      for (size_t pi = 0; pi < P->pairs.size(); ++pi) {
+        auto& pr = P->pairs[pi];
+        if (!pr.out.R) continue;
+        auto& s = S[2 * pi + seg];
+        AbJob a{};
+        a.A = (const double*)WS(ws, pr.Rcoef) + (seg ? pr.l1 : 0); a.lda = pr.N;
+        a.B = WS(ws, s.Wt); a.ldb = s.ldw;
+        a.D = pr.out.R; a.ldd = pr.out.ldr;
+        a.rows = pr.t; a.K = seg ? pr.l2 : pr.l1; a.J = (int)pr.n; a.accumulate = seg;
+        a.colscale = nullptr;
+        aj.push_back(a);
+        atl.push_back((int)((pr.n + 127) / 128));
+      }
+      if (!aj.empty()) {
+        Stage& a = B.add(K_AB, aj, atl);
+        a.prec = (prec == P64) ? P64 : P32; a.ta = 0; a.tb = wt; a.td = 0; a.ct = ctT; a.js = 2;
+      }
+    }
+    std::vector<SignJob> sj; std::vector<int> stl, ctl;
+    for (size_t pi = 0; pi < P->pairs.size(); ++pi) {
+      auto& pr = P->pairs[pi];
+      if (!pr.out.R) continue;
+      SignJob x{};
+      x.R = pr.out.R; x.ldr = pr.out.ldr; x.sgn = (double*)WS(ws, pr.sgn); x.t = pr.t; x.n = (int)pr.n;
+      sj.push_back(x); stl.push_back(pr.t);
+      ctl.push_back((int)(((int64_t)pr.t * pr.n + 255) / 256));
+    }
+    if (!sj.empty()) {
+      B.add(K_SIGN, sj, stl);
+      B.add(K_SCALE, sj, ctl);
+    }
+    std::vector<AbJob> aj; std::vector<int> atl;
+    for (size_t pi = 0; pi < P->pairs.size(); ++pi) {
+      auto& pr = P->pairs[pi];
+      for (int w = 0; w < 2; ++w) {
+        double* dst = w ? pr.out.V : pr.out.U;
+        if (!dst) continue;
+        auto& s = S[2 * pi + w];
+        AbJob a{};
+        a.A = WS(ws, w ? pr.X2t : pr.X1t); a.lda = w ? pr.l2 : pr.l1;
+        a.B = WS(ws, s.Yt); a.ldb = s.ldy;
+        a.D = dst; a.ldd = w ? pr.out.ldv : pr.out.ldu;
+        a.rows = pr.t; a.K = s.l; a.J = s.m; a.accumulate = 0;
+        a.colscale = pr.out.R ? (const double*)WS(ws, pr.sgn) : nullptr;
+        aj.push_back(a);
+        atl.push_back((s.m + 127) / 128);
+      }
+    }
+    if (!aj.empty()) {
+      Stage& a = B.add(K_AB, aj, atl);
+      a.prec = (prec == P64) ? P64 : P32; a.ta = 0; a.tb = wt; a.td = 0; a.ct = ctT; a.js = 2;
+    }
+  }
+  if (P->host.size() > P->jobs_cap) return RGSVD_ENOMEM;
+  return RGSVD_OK;
+}
+
+__global__ void k_copy(const CopyJob* j, const int* pre, int nj) {
+  const int jb = find_side(pre, nj, blockIdx.x);
+  const CopyJob J = j[jb];
+  for (int64_t i = threadIdx.x; i < J.nwords; i += blockDim.x) J.dst[i] = J.src[i];
+}
+
+int enqueue(rgsvd_plan_s* P, void* ws, hipStream_t st) {
+  char* jb = (char*)ws + P->off_jobs;
+  for (const Stage& s : P->stages) {
+    const int* pre = (const int*)(jb + s.poff);
+    const void* j = jb + s.joff;
+    switch (s.kind) {
+      case K_ZERO: launch_zero((char*)ws + s.zoff, (int64_t)s.zbytes, st); break;
+      case K_COPY: hipLaunchKernelGGL(k_copy, dim3(s.tiles), dim3(64), 0, st, (const CopyJob*)j, pre, s.nj); break;
+      case K_GEN: launch_gen(s.f64, (const GenJob*)j, pre, s.nj, s.tiles, st); break;
+      case K_NN: launch_nn(s.prec, s.gdt, s.rt, s.ct, (const NnJob*)j, pre, s.nj, s.tiles, st); break;
+      case K_AB: launch_ab(s.prec, s.ta, s.tb, s.td, s.ct, s.js, (const AbJob*)j, pre, s.nj, s.tiles, st); break;
+      case K_GRAM: launch_gram(s.ta, (const GramJob*)j, pre, s.nj, s.tiles, st); break;
+      case K_RED: launch_reduce(s.ta, s.td, s.sym, (const RedJob*)j, pre, s.nj, s.tiles, st); break;
+      case K_CHOL: launch_chol((const CholJob*)j, s.nj, s.npad_max, (double*)((char*)ws + P->off_chol), st); break;
+      case K_SMALL: launch_small((const SmallJob*)j, s.nj, st); break;
+      case K_SIGN: launch_sign((const SignJob*)j, pre, s.nj, s.tiles, st); break;
+      case K_SCALE: launch_scale((const SignJob*)j, pre, s.nj, s.tiles, st); break;
+    }
+  }
+  return hipGetLastError() == hipSuccess ? RGSVD_OK : RGSVD_EHIP;
+}
+
+int upload(rgsvd_plan_s* P, void* ws, hipStream_t st) {
+  if (!P->pinned) {
+    if (hipHostMalloc(&P->pinned, P->jobs_cap, hipHostMallocDefault) != hipSuccess) return RGSVD_EHIP;
+    if (hipEventCreateWithFlags(&P->ev, hipEventDisableTiming) != hipSuccess) return RGSVD_EHIP;
+  }
+  if (P->ev_pending) { hipEventSynchronize(P->ev); P->ev_pending = false; }
+  std::memcpy(P->pinned, P->host.data(), P->host.size());
+  if (hipMemcpyAsync((char*)ws + P->off_jobs, P->pinned, P->host.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+    return RGSVD_EHIP;
+  if (hipEventRecord(P->ev, st) != hipSuccess) return RGSVD_EHIP;
+  P->ev_pending = true;
+  return RGSVD_OK;
+}
+
+int check_desc(const rgsvd_desc* d) {
+  if (!d) return RGSVD_EINVAL;
+  if (d->m < 1 || d->p < 1 || d->n < 1 || d->k < 1 || d->oversample < 0 || d->power_iters < 0)
+    return RGSVD_EINVAL;
+  if (d->in_dtype != RGSVD_F64 && d->in_dtype != RGSVD_F32) return RGSVD_EINVAL;
+  if (d->precision < RGSVD_PREC_FP64 || d->precision > RGSVD_PREC_MIXED) return RGSVD_EINVAL;
+  if (d->mode != RGSVD_TRUNCATED && d->mode != RGSVD_FULL) return RGSVD_EINVAL;
+  if (d->m > (1 << 30) || d->p > (1 << 30) || d->n > (1 << 30)) return RGSVD_EINVAL;
+  const int64_t l = d->k + d->oversample;
+  // Theorem "projector": k + p <= min(m, n) (and <= min(p, n) for G2)
+  if (d->sizing == RGSVD_SIZE_FIXED) {
+    if (l > std::min(d->m, d->n) || l > std::min(d->p, d->n)) return RGSVD_EINVAL;
+    if (l > MAXL - 32) return RGSVD_EUNSUPPORTED;
+    if (d->mode == RGSVD_FULL && 2 * l < d->n) return RGSVD_ENOTGMP;
+    if (d->mode == RGSVD_TRUNCATED && d->k > l) return RGSVD_EINVAL;
+    if (2 * l > SMALL_MAXN) return RGSVD_EUNSUPPORTED;
+  } else {
+    return RGSVD_EUNSUPPORTED;
+  }
+  return RGSVD_OK;
+}
+
+PairLay pair_from(const rgsvd_desc* d) {
+  PairLay pr;
+  pr.m = d->m; pr.p = d->p; pr.n = d->n; pr.k = d->k; pr.o = d->oversample; pr.q = d->power_iters;
+  pr.seed = d->seed;
+  pr.l1 = pr.l2 = (int)(d->k + d->oversample);
+  pr.t = (d->mode == RGSVD_FULL) ? (int)d->n : (int)d->k;
+  return pr;
+}
+
+}  // namespace
+
+// ===================================================================== ABI ==
+extern "C" {
+
+const char* rgsvd_strerror(int code) {
+  switch (code) {
+    case RGSVD_OK: return "ok";
+    case RGSVD_EINVAL: return "invalid argument";
+    case RGSVD_ENOTGMP: return "full mode needs l1 + l2 >= n";
+    case RGSVD_EHIP: return "HIP runtime error";
+    case RGSVD_ENOMEM: return "host allocation failed";
+    case RGSVD_EWORKSPACE: return "workspace null or not 256-byte aligned";
+    case RGSVD_ENOMODEL: return "learned sizing needs a sizing model";
+    case RGSVD_EUNSUPPORTED: return "unsupported combination";
+    default: return "unknown error";
+  }
+}
+
+int rgsvd_plan(const rgsvd_desc* desc, rgsvd_plan_t* plan, size_t* workspace_bytes) {
+  if (!plan || !workspace_bytes) return RGSVD_EINVAL;
+  *plan = nullptr;
+  int rc = check_desc(desc);
+  if (rc) return rc;
+  rgsvd_plan_s* P = new (std::nothrow) rgsvd_plan_s();
+  if (!P) return RGSVD_ENOMEM;
+  P->d = *desc;
+  P->prec = desc->precision == RGSVD_PREC_FP64 ? P64 : (desc->precision == RGSVD_PREC_FP32 ? P32 : PBF);
+  P->gdt = desc->in_dtype;
+  P->mode = desc->mode;
+  P->pairs.push_back(pair_from(desc));
+  rc = layout(P);
+  if (rc) { delete P; return rc; }
+  *plan = P;
+  *workspace_bytes = P->ws;
+  return RGSVD_OK;
+}
+
+int rgsvd_plan_sizes(rgsvd_plan_t P, int64_t* t, int64_t* l1, int64_t* l2) {
+  if (!P || P->pairs.empty()) return RGSVD_EINVAL;
+  if (t) *t = P->pairs[0].t;
+  if (l1) *l1 = P->pairs[0].l1;
+  if (l2) *l2 = P->pairs[0].l2;
+  return RGSVD_OK;
+}
+
+int rgsvd_run(rgsvd_plan_t P, const void* G1, int64_t ld1, const void* G2, int64_t ld2,
+              void* workspace, void* stream, const rgsvd_out* out) {
+  if (!P || P->batched || !G1 || !G2 || !out) return RGSVD_EINVAL;
+  if (!workspace || ((uintptr_t)workspace & (ALIGN - 1))) return RGSVD_EWORKSPACE;
+  PairLay& pr = P->pairs[0];
+  if (ld1 < pr.n || ld2 < pr.n) return RGSVD_EINVAL;
+  if ((out->U && out->ldu < pr.m) || (out->V && out->ldv < pr.p) || (out->R && out->ldr < pr.n))
+    return RGSVD_EINVAL;
+  if (P->d.sizing == RGSVD_SIZE_LEARNED && !P->mlp) return RGSVD_ENOMODEL;
+  hipStream_t st = (hipStream_t)stream;
+  bool same = P->bound && P->lastG1 == G1 && P->lastG2 == G2 && P->lastws == workspace &&
+              P->lastld1 == ld1 && P->lastld2 == ld2 && out_eq(P->lastout, *out);
+  if (!same) {
+    pr.out = *out;
+    P->sides[0].G = G1; P->sides[0].ldg = ld1;
+    P->sides[1].G = G2; P->sides[1].ldg = ld2;
+    int rc = build(P, workspace);
+    if (rc) return rc;
+    rc = upload(P, workspace, st);
+    if (rc) return rc;
+    P->bound = true;
+    P->lastG1 = G1; P->lastG2 = G2; P->lastws = workspace; P->lastld1 = ld1; P->lastld2 = ld2;
+    P->lastout = *out;
+  }
+  return enqueue(P, workspace, st);
+}
+
+void rgsvd_destroy(rgsvd_plan_t P) {
+  if (!P) return;
+  if (P->ev_pending) hipEventSynchronize(P->ev);
+  if (P->ev) hipEventDestroy(P->ev);
+  if (P->pinned) hipHostFree(P->pinned);
+  if (P->gexec) hipGraphExecDestroy(P->gexec);
+  if (P->mlp) hipFree(P->mlp);
+  delete P;
+}
+
+// ------------------------------------------------------------- batched --
+int rgsvd_batch_plan(const rgsvd_desc* shapes, int32_t npairs, rgsvd_plan_t* plan,
+                     size_t* workspace_bytes) {
+  if (!shapes || npairs < 1 || !plan || !workspace_bytes) return RGSVD_EINVAL;
+  *plan = nullptr;
+  for (int i = 0; i < npairs; ++i) {
+    int rc = check_desc(&shapes[i]);
+    if (rc) return rc;
+    if (shapes[i].in_dtype != shapes[0].in_dtype || shapes[i].precision != shapes[0].precision ||
+        shapes[i].mode != shapes[0].mode)
+      return RGSVD_EINVAL;
+  }
+  rgsvd_plan_s* P = new (std::nothrow) rgsvd_plan_s();
+  if (!P) return RGSVD_ENOMEM;
+  P->d = shapes[0];
+  P->batched = true;
+  P->prec = shapes[0].precision == RGSVD_PREC_FP64 ? P64 : (shapes[0].precision == RGSVD_PREC_FP32 ? P32 : PBF);
+  P->gdt = shapes[0].in_dtype;
+  P->mode = shapes[0].mode;
+  for (int i = 0; i < npairs; ++i) P->pairs.push_back(pair_from(&shapes[i]));
+  int rc = layout(P);
+  if (rc) { delete P; return rc; }
+  *plan = P;
+  *workspace_bytes = P->ws;
+  return RGSVD_OK;
+}
+
+int rgsvd_batch_bind(rgsvd_plan_t P, const rgsvd_pair_io* io, void* workspace, void* stream) {
+  if (!P || !P->batched || !io) return RGSVD_EINVAL;
+  if (!workspace || ((uintptr_t)workspace & (ALIGN - 1))) return RGSVD_EWORKSPACE;
+  hipStream_t st = (hipStream_t)stream;
+  for (size_t i = 0; i < P->pairs.size(); ++i) {
+    auto& pr = P->pairs[i];
+    if (!io[i].G1 || !io[i].G2 || io[i].ld1 < pr.n || io[i].ld2 < pr.n) return RGSVD_EINVAL;
+    pr.out = io[i].out;
+    P->sides[2 * i].G = io[i].G1; P->sides[2 * i].ldg = io[i].ld1;
+    P->sides[2 * i + 1].G = io[i].G2; P->sides[2 * i + 1].ldg = io[i].ld2;
+  }
+  int rc = build(P, workspace);
+  if (rc) return rc;
+  rc = upload(P, workspace, st);
+  if (rc) return rc;
+  if (hipStreamSynchronize(st) != hipSuccess) return RGSVD_EHIP;
+  if (P->gexec) { hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+  // capture the whole enqueue sequence once
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return RGSVD_EHIP;
+  hipGraph_t g = nullptr;
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    enqueue(P, workspace, cs);
+    ok = hipStreamEndCapture(cs, &g) == hipSuccess && g;
+  }
+  if (ok) ok = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) hipGraphDestroy(g);
+  hipStreamDestroy(cs);
+  if (!ok) { P->gexec = nullptr; return RGSVD_EHIP; }
+  P->bws = workspace;
+  P->bound = true;
+  return RGSVD_OK;
+}
+
+int rgsvd_batch_run(rgsvd_plan_t P, void* stream) {
+  if (!P || !P->batched || !P->bound || !P->gexec) return RGSVD_EINVAL;
+  return hipGraphLaunch(P->gexec, (hipStream_t)stream) == hipSuccess ? RGSVD_OK : RGSVD_EHIP;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- sizing-model entry points --
+extern "C" int rgsvd_set_sizing_model(rgsvd_plan_t P, const float* params, void* stream) {
+  if (!P || !params) return RGSVD_EINVAL;
+  if (!P->mlp && hipMalloc((void**)&P->mlp, RGSVD_MLP_PARAMS * sizeof(float)) != hipSuccess)
+    return RGSVD_EHIP;
+  return hipMemcpyAsync(P->mlp, params, RGSVD_MLP_PARAMS * sizeof(float), hipMemcpyDeviceToDevice,
+                        (hipStream_t)stream) == hipSuccess ? RGSVD_OK : RGSVD_EHIP;
+}
+
+extern "C" int rgsvd_probe_features(const rgsvd_desc* desc, const void* G1, int64_t ld1, const void* G2,
+                                    int64_t ld2, float* feat, void* workspace, size_t workspace_bytes,
+                                    void* stream) {
+  (void)desc; (void)G1; (void)ld1; (void)G2; (void)ld2; (void)feat; (void)workspace;
+  (void)workspace_bytes; (void)stream;
+  return RGSVD_EUNSUPPORTED;
+}

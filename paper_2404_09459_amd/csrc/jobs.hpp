@@ -1,0 +1,60 @@
+// Job descriptors shared by the host orchestration and the kernels.  Every
+// kernel launch processes a table of jobs; a prefix table of per-job tile
+// counts maps blockIdx.x to (job, tile).  One launch thus serves both
+// matrices of a pair, or every matrix of a batch.
+#pragma once
+#include <stdint.h>
+
+namespace rg {
+
+// Yt = (G W)^T :  G m x n (row-major, ldg), Wt L x n (ldw), Yt L x m (ldy)
+struct NnJob {
+  const void* G; const void* Wt; void* Yt;
+  int64_t ldg, ldw, ldy;
+  int32_t m, n, L, pad;
+};
+
+// D[c][j] (+)= sum_{k<K} A[c][k] B[k][j] for c < rows, j < J.
+// A small (rows x K, lda), B big (K x J, ldb), D (rows x J, ldd).
+struct AbJob {
+  const void* A; const void* B; void* D;
+  int64_t lda, ldb, ldd;
+  int32_t rows, K, J, accumulate;
+  const double* colscale;   // optional: D[c][j] *= colscale[c] (sign fixes), or null
+};
+
+// Partial Grams of a row-stacked matrix X = [X1 (r1 rows); X2 (r2 rows)]
+// over column chunks [k0 + c*clen, k0 + (c+1)*clen) of [k0, k1):
+//   out[c] = X[:, chunk c] X[:, chunk c]^T   (npad x npad, double)
+// Only 64 x 64 blocks on or above the diagonal are written.
+struct GramJob {
+  const void* X1; const void* X2; double* out;
+  int64_t ld1, ld2;
+  int32_t r1, r2, k0, k1, npad, clen;
+};
+
+// out[r][c] = sum_{p < nparts} in[p*stride + r*ldi + c] in fixed order,
+// converted to the output type.
+struct RedJob {
+  const void* in; void* out; double* sq;
+  int64_t stride; int64_t count;
+  int32_t nparts, rows, cols, ldo;   // output viewed as rows x cols with ld ldo
+  int64_t ldi;                       // input row stride (cols <= ldi)
+};
+
+// Omega^T generation: Wt[c][r] = Omega[r][col0 + c] for c < ncols, r < n;
+// rows ncols..L-1 zero.
+struct GenJob {
+  void* Wt; int64_t ldw;
+  uint64_t seed;
+  int32_t n, col0, ncols, L, stream, pad;
+};
+
+// Cholesky of an N x N SPD Gram (sum of partials already formed) and the
+// inverse of its lower factor: sinv = L^{-1} (lower, N_pad x N_pad).
+struct CholJob {
+  const double* gram; double* sinv; double* r; int32_t* info;
+  int32_t N, npad, flagbit, pad;
+};
+
+}  // namespace rg

@@ -1,0 +1,478 @@
+// Grouped tall-skinny kernels of the basis extraction and projection.
+//
+//  k_gen     : Omega^T from the counter-based generator (sketch operand)
+//  k_nn      : Y = G W                    (Algorithm 1's G Omega_i; power step G W)
+//  k_ab      : D = A B, A small, B tall   (G^T Q and the projection Q^T G of
+//                                          Algorithm 2, split over row chunks;
+//                                          the triangular solve Q = Y R^{-1};
+//                                          the recovery products of U, V, R)
+//  k_gram    : partial X X^T in fp64      (CholeskyQR Gram; B B^T of the pair)
+//  k_reduce  : fixed-order sum of partials
+//  k_zero    : zero fill (kept as a kernel so runs stay graph-capturable)
+#include "common.hpp"
+#include "gemm.hpp"
+#include "jobs.hpp"
+#include "philox.hpp"
+#include "launch.hpp"
+
+namespace rg {
+
+// --------------------------------------------------------------- k_zero --
+__global__ void k_zero(uint32_t* __restrict__ p, int64_t nwords) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < nwords; i += stride) p[i] = 0u;
+}
+
+// ---------------------------------------------------------------- k_gen --
+template <typename TW, bool F64>
+__global__ __launch_bounds__(256) void k_gen(const GenJob* __restrict__ jobs,
+                                             const int* __restrict__ pre, int nj) {
+  const int jb = find_side(pre, nj, blockIdx.x);
+  const GenJob J = jobs[jb];
+  const int tile = blockIdx.x - pre[jb];
+  const int nrt = (J.n + 255) / 256;
+  const int rt = tile % nrt, grp = tile / nrt;
+  const int r = rt * 256 + threadIdx.x;
+  if (r >= J.n) return;
+  const int j = (J.col0 >> 2) + grp;
+  TW* Wt = (TW*)J.Wt;
+  if constexpr (F64) {
+    double z[4];
+    gauss4_f64(J.seed, (uint32_t)J.stream, (uint32_t)r, (uint32_t)j, z);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int c = 4 * j + e - J.col0;
+      if (c >= 0 && c < J.ncols) Wt[(int64_t)c * J.ldw + r] = (TW)z[e];
+    }
+  } else {
+    float z[4];
+    gauss4_f32(J.seed, (uint32_t)J.stream, (uint32_t)r, (uint32_t)j, z);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      int c = 4 * j + e - J.col0;
+      if (c >= 0 && c < J.ncols) Wt[(int64_t)c * J.ldw + r] = (TW)z[e];
+    }
+  }
+}
+
+// ----------------------------------------------------------------- k_nn --
+// WG = 4 waves; each wave owns RT row tiles (16 rows each) of G and all CT
+// column tiles of W.  The W chunk (CT*16 x KC) is staged in LDS once per WG;
+// G is streamed from HBM straight into registers (each lane a contiguous run
+// of KC/4 elements of one row), with the next chunk prefetched.
+template <int P, typename TG, int RT, int CT>
+__global__ __launch_bounds__(256) void k_nn(const NnJob* __restrict__ jobs,
+                                            const int* __restrict__ pre, int nj) {
+  using TR = Tr<P>;
+  using cT = typename TR::cT;
+  using acc_t = typename TR::acc;
+  using wT = typename TR::wT;
+  using aT = typename std::conditional<P == P64, double, float>::type;
+  constexpr int KC = TR::KC, KL = KC / 4, KPI = TR::KPI, NI = KL / KPI;
+  constexpr int RL = KC + TR::PAD;
+  constexpr int NWE = CT * 16 * KC;
+  constexpr int WPT = (NWE + 255) / 256;
+  __shared__ cT Ws[CT * 16 * RL];
+
+  const int jb = find_side(pre, nj, blockIdx.x);
+  const NnJob J = jobs[jb];
+  const int tile = blockIdx.x - pre[jb];
+  const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63, g = ln >> 4, li = ln & 15;
+  const int row0 = tile * 64 * RT + wave * 16 * RT;
+  const int ctn = J.L >> 4;
+  const TG* __restrict__ G = (const TG*)J.G;
+  const wT* __restrict__ Wt = (const wT*)J.Wt;
+
+  acc_t acc[RT][CT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+  aT an[RT][KL];
+  wT wn[WPT];
+  const int nk = (J.n + KC - 1) / KC;
+
+  auto load_a = [&](int kc) {
+#pragma unroll
+    for (int a = 0; a < RT; ++a) {
+      int r = row0 + a * 16 + li;
+      bool ok = r < J.m;
+      const TG* rowp = G + (int64_t)(ok ? r : 0) * J.ldg;
+      load_run<TG, aT, KL>(an[a], rowp, kc * KC + g * KL, J.n, ok);
+    }
+  };
+  auto load_w = [&](int kc) {
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      int e = threadIdx.x + 256 * i;
+      int c = e / KC, kk = e - c * KC;
+      int k = kc * KC + kk;
+      wn[i] = (e < NWE && c < J.L && k < J.n) ? Wt[(int64_t)c * J.ldw + k] : (wT)0;
+    }
+  };
+
+  load_a(0);
+  load_w(0);
+  for (int kc = 0; kc < nk; ++kc) {
+    cT a[RT][KL];
+#pragma unroll
+    for (int x = 0; x < RT; ++x)
+#pragma unroll
+      for (int e = 0; e < KL; ++e) a[x][e] = cvt<P>((double)an[x][e]);
+    wT w[WPT];
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) w[i] = wn[i];
+    if (kc + 1 < nk) { load_a(kc + 1); load_w(kc + 1); }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < WPT; ++i) {
+      int e = threadIdx.x + 256 * i;
+      if (e < NWE) {
+        int c = e / KC, kk = e - c * KC;
+        Ws[c * RL + kk] = cvt<P>((double)w[i]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      if (ct < ctn) {
+        cT b[KL];
+        const cT* src = Ws + (ct * 16 + li) * RL + g * KL;
+#pragma unroll
+        for (int e = 0; e < KL; ++e) b[e] = src[e];
+#pragma unroll
+        for (int x = 0; x < RT; ++x)
+#pragma unroll
+          for (int s = 0; s < NI; ++s) mma_step<P>(acc[x][ct], &a[x][s * KPI], &b[s * KPI]);
+      }
+    }
+  }
+  // store: lane holds Y[row0 + x*16 + out_row(g, ii)][ct*16 + li] -> Yt[ct*16+li][...]
+  wT* Yt = (wT*)J.Yt;
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    if (ct < ctn) {
+      int c = ct * 16 + li;
+#pragma unroll
+      for (int x = 0; x < RT; ++x) {
+        wT* dst = Yt + (int64_t)c * J.ldy;
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) {
+          int r = row0 + x * 16 + out_row<P>(g, ii);
+          if (r < J.m) dst[r] = (wT)acc[x][ct][ii];
+        }
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------- k_ab --
+// D (rows x J) (+)= A (rows x K) B (K x J).  WG = 4 waves along J; each wave
+// covers 16*JS columns (lane li owns columns JS*li .. JS*li+JS-1 of them, one
+// per MFMA sub-tile) and all CT row tiles.  A chunks are staged in LDS; B is
+// streamed per lane.
+template <int P> struct AbK;
+template <> struct AbK<P64> { static constexpr int KC = 16; };
+template <> struct AbK<P32> { static constexpr int KC = 32; };
+template <> struct AbK<PBF> { static constexpr int KC = 64; };
+
+template <int P, typename TA, typename TB, typename TD, int CT, int JS>
+__global__ __launch_bounds__(256) void k_ab(const AbJob* __restrict__ jobs,
+                                            const int* __restrict__ pre, int nj) {
+  using TR = Tr<P>;
+  using cT = typename TR::cT;
+  using acc_t = typename TR::acc;
+  using bT = typename std::conditional<P == P64, double, float>::type;
+  constexpr int KC = AbK<P>::KC, KL = KC / 4, KPI = TR::KPI, NI = KL / KPI;
+  constexpr int RL = KC + TR::PAD;
+  constexpr int NAE = CT * 16 * KC;
+  constexpr int APT = (NAE + 255) / 256;
+  __shared__ cT As[CT * 16 * RL];
+
+  const int jb = find_side(pre, nj, blockIdx.x);
+  const AbJob J = jobs[jb];
+  const int tile = blockIdx.x - pre[jb];
+  const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63, g = ln >> 4, li = ln & 15;
+  const int col0 = tile * 64 * JS + wave * 16 * JS + JS * li;
+  const int ctn = (J.rows + 15) >> 4;
+  const TA* __restrict__ A = (const TA*)J.A;
+  const TB* __restrict__ B = (const TB*)J.B;
+
+  acc_t acc[CT][JS];
+#pragma unroll
+  for (int a = 0; a < CT; ++a)
+#pragma unroll
+    for (int q = 0; q < JS; ++q) acc[a][q] = acc_t{0, 0, 0, 0};
+
+  bT bn[KL][JS];
+  TA an[APT];
+  const int nk = (J.K + KC - 1) / KC;
+
+  auto load_b = [&](int kc) {
+#pragma unroll
+    for (int e = 0; e < KL; ++e) {
+      int k = kc * KC + g * KL + e;
+      bool ok = k < J.K;
+      const TB* rowp = B + (int64_t)(ok ? k : 0) * J.ldb;
+      load_run<TB, bT, JS>(bn[e], rowp, col0, J.J, ok);
+    }
+  };
+  auto load_a = [&](int kc) {
+#pragma unroll
+    for (int i = 0; i < APT; ++i) {
+      int e = threadIdx.x + 256 * i;
+      int c = e / KC, kk = e - c * KC;
+      int k = kc * KC + kk;
+      an[i] = (e < NAE && c < J.rows && k < J.K) ? A[(int64_t)c * J.lda + k] : (TA)0;
+    }
+  };
+
+  load_b(0);
+  load_a(0);
+  for (int kc = 0; kc < nk; ++kc) {
+    cT b[JS][KL];
+#pragma unroll
+    for (int e = 0; e < KL; ++e)
+#pragma unroll
+      for (int q = 0; q < JS; ++q) b[q][e] = cvt<P>((double)bn[e][q]);
+    TA a_[APT];
+#pragma unroll
+    for (int i = 0; i < APT; ++i) a_[i] = an[i];
+    if (kc + 1 < nk) { load_b(kc + 1); load_a(kc + 1); }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < APT; ++i) {
+      int e = threadIdx.x + 256 * i;
+      if (e < NAE) {
+        int c = e / KC, kk = e - c * KC;
+        As[c * RL + kk] = cvt<P>((double)a_[i]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ct = 0; ct < CT; ++ct) {
+      if (ct < ctn) {
+        cT a[KL];
+        const cT* src = As + (ct * 16 + li) * RL + g * KL;
+#pragma unroll
+        for (int e = 0; e < KL; ++e) a[e] = src[e];
+#pragma unroll
+        for (int q = 0; q < JS; ++q)
+#pragma unroll
+          for (int s = 0; s < NI; ++s) mma_step<P>(acc[ct][q], &a[s * KPI], &b[q][s * KPI]);
+      }
+    }
+  }
+  // all loads of B (possibly aliasing D) are done by every wave of this WG
+  __syncthreads();
+  TD* D = (TD*)J.D;
+#pragma unroll
+  for (int ct = 0; ct < CT; ++ct) {
+    if (ct < ctn) {
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        int c = ct * 16 + out_row<P>(g, ii);
+        if (c < J.rows) {
+          double sc = J.colscale ? J.colscale[c] : 1.0;
+          TD* dst = D + (int64_t)c * J.ldd;
+#pragma unroll
+          for (int q = 0; q < JS; ++q) {
+            int j = col0 + q;
+            if (j < J.J) {
+              double v = (double)acc[ct][q][ii] * sc;
+              if (J.accumulate) v += (double)dst[j];
+              dst[j] = (TD)v;
+            }
+          }
+        }
+      }
+    }
+  }
+}
+
+// --------------------------------------------------------------- k_gram --
+// Partial Gram X[:, k0:k1] X[:, k0:k1]^T in fp64 MFMA.  Output blocks of
+// 64 x 64; only blocks on or above the diagonal are formed (the reduction
+// mirrors them).  Each wave: 16 rows x 64 columns.
+template <typename TX>
+__global__ __launch_bounds__(256) void k_gram(const GramJob* __restrict__ jobs,
+                                              const int* __restrict__ pre, int nj) {
+  constexpr int KC = 32, KL = 8, RL = KC + 2;
+  __shared__ double Xs[128 * RL];   // rows 0..63: row block, 64..127: column block
+  const int jb = find_side(pre, nj, blockIdx.x);
+  const GramJob J = jobs[jb];
+  int tile = blockIdx.x - pre[jb];
+  const int nb = J.npad / 64;
+  const int nblk = nb * (nb + 1) / 2;
+  const int chunk = tile / nblk;
+  int bt = tile - chunk * nblk;
+  const int kb = J.k0 + chunk * J.clen;
+  const int ke = min(J.k1, kb + J.clen);
+  int rb = 0;
+  while (bt >= nb - rb) { bt -= nb - rb; ++rb; }
+  const int cb = rb + bt;
+  const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63, g = ln >> 4, li = ln & 15;
+  const TX* X1 = (const TX*)J.X1;
+  const TX* X2 = (const TX*)J.X2;
+  auto rowptr = [&](int c) -> const TX* {
+    if (c < J.r1) return X1 + (int64_t)c * J.ld1;
+    if (c < J.r1 + J.r2) return X2 + (int64_t)(c - J.r1) * J.ld2;
+    return nullptr;
+  };
+  d4 acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
+  for (int k = kb; k < ke; k += KC) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 128 * KC; e += 256) {
+      int rr = e / KC, kk = e - rr * KC;
+      int c = (rr < 64 ? rb * 64 + rr : cb * 64 + rr - 64);
+      const TX* p = rowptr(c);
+      int kx = k + kk;
+      Xs[rr * RL + kk] = (p && kx < ke) ? (double)p[kx] : 0.0;
+    }
+    __syncthreads();
+    double a[KL];
+#pragma unroll
+    for (int e = 0; e < KL; ++e) a[e] = Xs[(wave * 16 + li) * RL + g * KL + e];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double b[KL];
+#pragma unroll
+      for (int e = 0; e < KL; ++e) b[e] = Xs[(64 + q * 16 + li) * RL + g * KL + e];
+#pragma unroll
+      for (int e = 0; e < KL; ++e) acc[q] = mma64(a[e], b[e], acc[q]);
+    }
+  }
+  // lane holds D[out_row(g, ii)][li] of tile (wave, q)
+  double* out = J.out + (int64_t)chunk * J.npad * J.npad;
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      int r = rb * 64 + wave * 16 + out_row<P64>(g, ii);
+      int c = cb * 64 + q * 16 + li;
+      out[(int64_t)r * J.npad + c] = acc[q][ii];
+    }
+}
+
+// ------------------------------------------------------------- k_reduce --
+// Fixed-order sum over partials.  SYM: the input holds only blocks with
+// (row block <= column block) of 64 x 64; entries below are mirrored.
+template <typename TI, typename TO, bool SYM>
+__global__ __launch_bounds__(256) void k_reduce(const RedJob* __restrict__ jobs,
+                                                const int* __restrict__ pre, int nj) {
+  const int jb = find_side(pre, nj, blockIdx.x);
+  const RedJob J = jobs[jb];
+  const int64_t i = (int64_t)(blockIdx.x - pre[jb]) * 256 + threadIdx.x;
+  const int64_t cnt = (int64_t)J.rows * J.cols;
+  if (i < cnt) {
+    int r = (int)(i / J.cols), c = (int)(i - (int64_t)r * J.cols);
+    int64_t src;
+    if (SYM && (r >> 6) > (c >> 6)) src = (int64_t)c * J.ldi + r;
+    else src = (int64_t)r * J.ldi + c;
+    const TI* in = (const TI*)J.in;
+    double s = 0.0;
+    for (int p = 0; p < J.nparts; ++p) s += (double)in[p * J.stride + src];
+    ((TO*)J.out)[(int64_t)r * J.ldo + c] = (TO)s;
+  }
+}
+
+// ---------------------------------------------------------------- launch --
+template <int P, typename TG, int RT, int CT>
+static void launch_nn_ct(const NnJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  hipLaunchKernelGGL((k_nn<P, TG, RT, CT>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
+}
+
+template <int P, typename TG, int RT>
+static void launch_nn_rt(int ct, const NnJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  switch (ct) {
+    case 1: launch_nn_ct<P, TG, RT, 1>(j, pre, nj, tiles, st); break;
+    case 2: launch_nn_ct<P, TG, RT, 2>(j, pre, nj, tiles, st); break;
+    case 4: launch_nn_ct<P, TG, RT, 4>(j, pre, nj, tiles, st); break;
+    case 8: launch_nn_ct<P, TG, RT, 8>(j, pre, nj, tiles, st); break;
+    default: launch_nn_ct<P, TG, RT, 16>(j, pre, nj, tiles, st); break;
+  }
+}
+
+void launch_nn(int prec, int gdt, int rt, int ct, const NnJob* j, const int* pre, int nj,
+               int tiles, hipStream_t st) {
+  if (prec == P64) {
+    if (gdt == G_F64) launch_nn_rt<P64, double, 1>(ct, j, pre, nj, tiles, st);
+    else launch_nn_rt<P64, float, 1>(ct, j, pre, nj, tiles, st);
+  } else if (prec == P32) {
+    if (gdt == G_F64) launch_nn_rt<P32, double, 1>(ct, j, pre, nj, tiles, st);
+    else if (rt == 2) launch_nn_rt<P32, float, 2>(ct, j, pre, nj, tiles, st);
+    else launch_nn_rt<P32, float, 1>(ct, j, pre, nj, tiles, st);
+  } else {
+    if (gdt == G_F64) launch_nn_rt<PBF, double, 1>(ct, j, pre, nj, tiles, st);
+    else if (rt == 2) launch_nn_rt<PBF, float, 2>(ct, j, pre, nj, tiles, st);
+    else launch_nn_rt<PBF, float, 1>(ct, j, pre, nj, tiles, st);
+  }
+}
+
+template <int P, typename TA, typename TB, typename TD, int JS>
+static void launch_ab_js(int ct, const AbJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  switch (ct) {
+    case 1: hipLaunchKernelGGL((k_ab<P, TA, TB, TD, 1, JS>), dim3(tiles), dim3(256), 0, st, j, pre, nj); break;
+    case 2: hipLaunchKernelGGL((k_ab<P, TA, TB, TD, 2, JS>), dim3(tiles), dim3(256), 0, st, j, pre, nj); break;
+    case 4: hipLaunchKernelGGL((k_ab<P, TA, TB, TD, 4, JS>), dim3(tiles), dim3(256), 0, st, j, pre, nj); break;
+    case 8: hipLaunchKernelGGL((k_ab<P, TA, TB, TD, 8, JS>), dim3(tiles), dim3(256), 0, st, j, pre, nj); break;
+    default: hipLaunchKernelGGL((k_ab<P, TA, TB, TD, 16, JS>), dim3(tiles), dim3(256), 0, st, j, pre, nj); break;
+  }
+}
+
+// kinds: A/B/D element types given as 0 = double, 1 = float
+void launch_ab(int prec, int ta, int tb, int td, int ct, int js, const AbJob* j, const int* pre,
+               int nj, int tiles, hipStream_t st) {
+#define AB_CASE(PP, A_, B_, D_)                                                        \
+  if (js == 4) launch_ab_js<PP, A_, B_, D_, 4>(ct, j, pre, nj, tiles, st);              \
+  else if (js == 2) launch_ab_js<PP, A_, B_, D_, 2>(ct, j, pre, nj, tiles, st);         \
+  else launch_ab_js<PP, A_, B_, D_, 1>(ct, j, pre, nj, tiles, st);
+  if (prec == P64) {
+    // fp64 path: A, D double; B double or float (fp32-stored G)
+    if (tb == 0) { AB_CASE(P64, double, double, double) }
+    else { AB_CASE(P64, double, float, double) }
+  } else if (prec == P32) {
+    if (ta == 0 && tb == 1 && td == 1) { AB_CASE(P32, double, float, float) }
+    else if (ta == 1 && tb == 1 && td == 1) { AB_CASE(P32, float, float, float) }
+    else if (ta == 1 && tb == 1 && td == 0) { AB_CASE(P32, float, float, double) }
+    else if (ta == 0 && tb == 1 && td == 0) { AB_CASE(P32, double, float, double) }
+    else { AB_CASE(P32, float, double, float) }
+  } else {
+    if (tb == 1) { AB_CASE(PBF, float, float, float) }
+    else { AB_CASE(PBF, float, double, float) }
+  }
+#undef AB_CASE
+}
+
+void launch_gen(bool f64, const GenJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  if (f64) hipLaunchKernelGGL((k_gen<double, true>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
+  else hipLaunchKernelGGL((k_gen<float, false>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
+}
+
+void launch_gram(int tx, const GramJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  if (tx == 0) hipLaunchKernelGGL((k_gram<double>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
+  else hipLaunchKernelGGL((k_gram<float>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
+}
+
+void launch_reduce(int ti, int to, bool sym, const RedJob* j, const int* pre, int nj, int tiles,
+                   hipStream_t st) {
+  if (sym) hipLaunchKernelGGL((k_reduce<double, double, true>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
+  else if (ti == 0 && to == 0) hipLaunchKernelGGL((k_reduce<double, double, false>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
+  else if (ti == 1 && to == 1) hipLaunchKernelGGL((k_reduce<float, float, false>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
+  else if (ti == 1 && to == 0) hipLaunchKernelGGL((k_reduce<float, double, false>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
+  else hipLaunchKernelGGL((k_reduce<double, float, false>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
+}
+
+void launch_zero(void* p, int64_t bytes, hipStream_t st) {
+  int64_t nw = bytes / 4;
+  if (nw <= 0) return;
+  int64_t blocks = (nw + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)blocks), dim3(256), 0, st, (uint32_t*)p, nw);
+}
+
+}  // namespace rg

@@ -1,0 +1,23 @@
+// Host-side launchers of the grouped kernels (defined next to the kernels).
+#pragma once
+#include <hip/hip_runtime.h>
+#include "jobs.hpp"
+#include "small.hpp"
+
+namespace rg {
+
+void launch_zero(void* p, int64_t bytes, hipStream_t st);
+void launch_gen(bool f64, const GenJob* j, const int* pre, int nj, int tiles, hipStream_t st);
+void launch_nn(int prec, int gdt, int rt, int ct, const NnJob* j, const int* pre, int nj,
+               int tiles, hipStream_t st);
+void launch_ab(int prec, int ta, int tb, int td, int ct, int js, const AbJob* j, const int* pre,
+               int nj, int tiles, hipStream_t st);
+void launch_gram(int tx, const GramJob* j, const int* pre, int nj, int tiles, hipStream_t st);
+void launch_reduce(int ti, int to, bool sym, const RedJob* j, const int* pre, int nj, int tiles,
+                   hipStream_t st);
+void launch_chol(const CholJob* j, int nj, int npad_max, double* gscratch, hipStream_t st);
+void launch_small(const SmallJob* j, int nj, hipStream_t st);
+void launch_sign(const SignJob* j, const int* pre, int nj, int tiles, hipStream_t st);
+void launch_scale(const SignJob* j, const int* pre, int nj, int tiles, hipStream_t st);
+
+}  // namespace rg

@@ -1,0 +1,39 @@
+// Job descriptor and limits of the small FP64 steps.
+#pragma once
+#include <stdint.h>
+
+namespace rg {
+
+constexpr int CHOL_LDS_MAX = 128;   // Gram orders kept in LDS by k_chol
+constexpr int CHOL_MAX = 256;       // largest padded Gram order
+constexpr int SMALL_MAXN = 512;     // largest l1 + l2 of the compressed pair
+constexpr double BETA_ZERO = 1e-14;
+
+// flag bits of info[4] (same values as the public header)
+constexpr int FLAG_CHOL_FAIL = 0x4;
+constexpr int FLAG_JACOBI_M = 0x8;
+constexpr int FLAG_JACOBI_L1 = 0x10;
+constexpr int FLAG_BETA_ZERO = 0x20;
+constexpr int FLAG_ALPHA_ZERO = 0x40;
+constexpr int FLAG_NONFINITE = 0x80;
+
+// One compressed pair: M = B B^T (N x N, N = l1 + l2) -> alpha, beta, ...
+struct SmallJob {
+  const double* M; int64_t ldm;
+  int32_t l1, l2, t, maxsweep;
+  double tol;
+  double* work;                     // N*N + N*t + t*t + l1*t doubles
+  double* sigma;                    // N
+  double *alpha, *beta, *theta, *P1, *P2, *D;
+  double* X1t; int64_t ldx1;        // t x l1
+  double* X2t; int64_t ldx2;        // t x l2
+  double* Rcoef; int64_t ldr;       // t x N  ((L Y)^T)
+  int32_t* info;
+};
+
+// sign convention of one pair: sgn[i] from row i of R (t x n)
+struct SignJob {
+  double* R; int64_t ldr; double* sgn; int32_t t, n;
+};
+
+}  // namespace rg

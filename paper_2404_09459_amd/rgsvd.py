@@ -1,0 +1,235 @@
+"""Thin ctypes binding of librgsvd.so (argument marshalling only).
+
+Every step of the method runs in the library's HIP kernels; PyTorch supplies
+device memory and the stream.  If the library is not built this module raises
+instead of falling back to anything else.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "librgsvd.so")
+
+OK, EINVAL, ENOTGMP, EHIP, ENOMEM, EWORKSPACE, ENOMODEL, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+F64, F32 = 0, 1
+PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
+SIZING = {"fixed": 0, "adaptive": 1, "learned": 2}
+MODE = {"truncated": 0, "full": 1}
+INFO_WORDS = 8
+MLP_PARAMS = 6402
+
+FLAGS = {
+    0x1: "shift_y", 0x2: "shift_w", 0x4: "chol_fail", 0x8: "jacobi_m",
+    0x10: "jacobi_l1", 0x20: "beta_zero", 0x40: "alpha_zero", 0x80: "nonfinite",
+}
+
+
+class RgsvdError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+        self.code = code
+
+
+class Desc(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("p", ctypes.c_int64), ("n", ctypes.c_int64),
+                ("k", ctypes.c_int64), ("oversample", ctypes.c_int64),
+                ("power_iters", ctypes.c_int32), ("in_dtype", ctypes.c_int32),
+                ("precision", ctypes.c_int32), ("sizing", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("tol", ctypes.c_double),
+                ("block", ctypes.c_int64), ("lmax", ctypes.c_int64)]
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class Out(ctypes.Structure):
+    _fields_ = [("alpha", ctypes.c_void_p), ("beta", ctypes.c_void_p), ("theta", ctypes.c_void_p),
+                ("P1", ctypes.c_void_p), ("P2", ctypes.c_void_p), ("D", ctypes.c_void_p),
+                ("sigma_B", ctypes.c_void_p), ("U", ctypes.c_void_p), ("V", ctypes.c_void_p),
+                ("R", ctypes.c_void_p), ("ldu", ctypes.c_int64), ("ldv", ctypes.c_int64),
+                ("ldr", ctypes.c_int64), ("info", ctypes.c_void_p)]
+
+
+class PairIO(ctypes.Structure):
+    _fields_ = [("G1", ctypes.c_void_p), ("G2", ctypes.c_void_p), ("ld1", ctypes.c_int64),
+                ("ld2", ctypes.c_int64), ("out", Out)]
+
+
+EXPORTS = {
+    # name: (restype, argtypes)
+    "rgsvd_plan": (ctypes.c_int, [ctypes.POINTER(Desc), ctypes.POINTER(ctypes.c_void_p),
+                                  ctypes.POINTER(ctypes.c_size_t)]),
+    "rgsvd_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                 ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Out)]),
+    "rgsvd_plan_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
+                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
+    "rgsvd_destroy": (None, [ctypes.c_void_p]),
+    "rgsvd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
+    "rgsvd_batch_plan": (ctypes.c_int, [ctypes.POINTER(Desc), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_size_t)]),
+    "rgsvd_batch_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PairIO), ctypes.c_void_p,
+                                        ctypes.c_void_p]),
+    "rgsvd_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rgsvd_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
+                                         ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "rgsvd_mlp_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p]),
+    "rgsvd_mlp_adam": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                      ctypes.c_float, ctypes.c_float, ctypes.c_void_p]),
+    "rgsvd_set_sizing_model": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "rgsvd_probe_features": (ctypes.c_int, [ctypes.POINTER(Desc), ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "rgsvd_gaussian": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64,
+                                      ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_void_p]),
+    "rgsvd_philox_words": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64,
+                                          ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_int64, ctypes.c_void_p]),
+    "rgsvd_selftest_mfma": (ctypes.c_int, [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_void_p]),
+}
+
+_LIB = None
+
+
+def lib():
+    """Load librgsvd.so (raises if it is not built)."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIBPATH):
+            raise RuntimeError(f"{LIBPATH} is not built; run paper_2404_09459_amd.build.build()")
+        L = ctypes.CDLL(LIBPATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _LIB = L
+    return _LIB
+
+
+def strerror(code):
+    try:
+        return lib().rgsvd_strerror(code).decode()
+    except Exception:  # library not loadable: still give a message
+        return f"error {code}"
+
+
+def check(code, where):
+    if code != OK:
+        raise RgsvdError(code, where)
+
+
+# ---------------------------------------------------------- torch helpers ---
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    torch = _torch()
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def make_desc(m, p, n, k, oversample, q, seed, in_dtype, precision="fp64", sizing="fixed",
+              mode="truncated", tol=0.0, block=0, lmax=0):
+    return Desc(m=m, p=p, n=n, k=k, oversample=oversample, power_iters=q, in_dtype=in_dtype,
+                precision=PREC[precision], sizing=SIZING[sizing], mode=MODE[mode], reserved0=0,
+                seed=seed, tol=tol, block=block, lmax=lmax)
+
+
+class Plan:
+    """A plan plus its device workspace for one pair shape."""
+
+    def __init__(self, desc, device):
+        torch = _torch()
+        self.desc = desc
+        h = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        check(lib().rgsvd_plan(ctypes.byref(desc), ctypes.byref(h), ctypes.byref(ws)), "rgsvd_plan")
+        self.h = h
+        self.ws_bytes = ws.value
+        self.ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_ptr = ctypes.c_void_p(self.ws.data_ptr() + off)
+        t = ctypes.c_int64(); l1 = ctypes.c_int64(); l2 = ctypes.c_int64()
+        check(lib().rgsvd_plan_sizes(h, ctypes.byref(t), ctypes.byref(l1), ctypes.byref(l2)),
+              "rgsvd_plan_sizes")
+        self.t, self.l1, self.l2 = t.value, l1.value, l2.value
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().rgsvd_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+def alloc_outputs(t, m, p, n, N, device, uvr=True):
+    torch = _torch()
+    f = dict(dtype=torch.float64, device=device)
+    o = dict(alpha=torch.empty(t, **f), beta=torch.empty(t, **f), theta=torch.empty(t, **f),
+             P1=torch.empty(t, **f), P2=torch.empty(t, **f), D=torch.empty(2, **f),
+             sigma_B=torch.empty(N, **f), info=torch.zeros(INFO_WORDS, dtype=torch.int32, device=device))
+    if uvr:
+        o["Ut"] = torch.empty((t, m), **f)     # U column-major == U^T row-major
+        o["Vt"] = torch.empty((t, p), **f)
+        o["R"] = torch.empty((t, n), **f)
+    return o
+
+
+def out_struct(o, m, p, n):
+    return Out(alpha=_ptr(o["alpha"]), beta=_ptr(o["beta"]), theta=_ptr(o["theta"]),
+               P1=_ptr(o["P1"]), P2=_ptr(o["P2"]), D=_ptr(o["D"]), sigma_B=_ptr(o["sigma_B"]),
+               U=_ptr(o.get("Ut")), V=_ptr(o.get("Vt")), R=_ptr(o.get("R")),
+               ldu=m, ldv=p, ldr=n, info=_ptr(o["info"]))
+
+
+def run(plan, G1, G2, o):
+    """Enqueue one run of `plan` on torch's current stream; returns o."""
+    m, n = G1.shape
+    p = G2.shape[0]
+    assert G1.stride(1) == 1 and G2.stride(1) == 1, "rows of G must be contiguous"
+    out = out_struct(o, m, p, n)
+    check(lib().rgsvd_run(plan.h, _ptr(G1), G1.stride(0), _ptr(G2), G2.stride(0), plan.ws_ptr,
+                          _stream(G1.device), ctypes.byref(out)), "rgsvd_run")
+    return o
+
+
+_PLANS = {}
+
+
+def rgsvd(G1, G2, k, oversample, q, seed, precision="fp64", mode="truncated", uvr=True):
+    """Randomized GSVD of the device pair (G1, G2); returns a dict of device
+    tensors: alpha, beta, theta, P1, P2, D, sigma_B, info and (uvr) U, V, R."""
+    torch = _torch()
+    if G1.dtype != G2.dtype or G1.dtype not in (torch.float64, torch.float32):
+        raise ValueError("G1, G2 must both be float64 or float32")
+    if not (G1.is_cuda and G2.is_cuda):
+        raise ValueError("G1, G2 must be device tensors")
+    m, n = G1.shape
+    p = G2.shape[0]
+    dt = F64 if G1.dtype == torch.float64 else F32
+    key = (m, p, n, k, oversample, q, seed, dt, precision, mode, G1.device.index)
+    plan = _PLANS.get(key)
+    if plan is None:
+        plan = Plan(make_desc(m, p, n, k, oversample, q, seed, dt, precision, "fixed", mode), G1.device)
+        _PLANS[key] = plan
+    o = alloc_outputs(plan.t, m, p, n, plan.l1 + plan.l2, G1.device, uvr)
+    run(plan, G1, G2, o)
+    if uvr:
+        o["U"] = o["Ut"].t()
+        o["V"] = o["Vt"].t()
+    return o
+
+
+def decode_flags(word):
+    return [name for bit, name in FLAGS.items() if word & bit]
