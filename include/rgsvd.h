@@ -120,8 +120,10 @@ typedef struct {
 } rgsvd_desc;
 
 /* Caller-owned device outputs.  alpha, beta, theta, P1, P2 have t entries,
- * D has 2 (D1, D2), sigma_B has l1 + l2 (singular values of the stacked
- * compressed pair).  U (m x t) and V (p x t) are column-major (column j of U
+ * D has 2 (D1, D2), sigma_B has l1 + l2 entries: the t dominant singular
+ * values of the stacked compressed pair [Q1^T G1; Q2^T G2] in descending
+ * order, then l1 + l2 - t values whose squares sum to the remaining
+ * singular values' squares (they are not individually singular values).  U (m x t) and V (p x t) are column-major (column j of U
  * at U + j*ldu, ldu >= m), R (t x n) is row-major (ldr >= n); all FP64.
  * U, V, R, sigma_B may be NULL to skip them.  info: RGSVD_INFO_WORDS int32. */
 typedef struct {
@@ -151,6 +153,17 @@ int rgsvd_plan_sizes(rgsvd_plan_t plan, int64_t* t, int64_t* l1, int64_t* l2);
 
 void rgsvd_destroy(rgsvd_plan_t plan);
 const char* rgsvd_strerror(int code);
+
+/* Per-stage timing of single-pair runs with HIP events recorded on the run's
+ * stream between its launches (enable = 1 before rgsvd_run).  After the
+ * stream is synchronised, rgsvd_profile_read returns the stage count and, for
+ * up to `max` stages, the elapsed milliseconds and a stage tag:
+ *   0 zero fill, 1 info init, 2 Omega generation, 3 G W product,
+ *   4 split G^T Q / Q^T G product, 5 partial-sum reduction, 6 Gram (CholeskyQR),
+ *   7 Cholesky + inverse, 8 triangular update Q = Y R^{-1}, 9 small FP64 step,
+ *   10 recovery products, 11 sign convention, 12 Gram of the compressed pair. */
+int rgsvd_profile(rgsvd_plan_t plan, int32_t enable);
+int rgsvd_profile_read(rgsvd_plan_t plan, int32_t max, float* ms, int32_t* tag, int32_t* count);
 
 /* ------------------------------------------------------ batched runs ---- */
 /* Many independent pairs of different sizes in one sequence of grouped

@@ -45,8 +45,12 @@ inline int ct_of(int L) {
 
 enum Kind { K_ZERO, K_COPY, K_GEN, K_NN, K_AB, K_GRAM, K_RED, K_CHOL, K_SMALL, K_SIGN, K_SCALE };
 
+enum Tag { T_ZERO, T_COPY, T_GEN, T_NN, T_TN, T_RED, T_GRAM, T_CHOL, T_SX, T_SMALL, T_RECOVER, T_SIGN,
+           T_MGRAM, T_NTAGS };
+
 struct Stage {
   Kind kind;
+  int tag = 0;
   size_t joff = 0, poff = 0;  // byte offsets of job array and prefix table in the job area
   int nj = 0, tiles = 0;
   int prec = 0, gdt = 0, rt = 1, ct = 1, js = 1;
@@ -105,6 +109,10 @@ struct rgsvd_plan_s {
   void* bws = nullptr;
   // sizing network
   float* mlp = nullptr;
+  // per-stage event profiling
+  bool prof = false;
+  std::vector<hipEvent_t> pev;
+  int prof_count = 0;
 };
 
 namespace {
@@ -171,7 +179,7 @@ int layout(rgsvd_plan_s* P) {
     pr.mpart = take((size_t)pr.gch * pr.Npad * pr.Npad * 8);
     pr.M = take((size_t)pr.Npad * pr.Npad * 8);
     size_t N = pr.N, t = pr.t;
-    pr.work = take((N * N + N * t + t * t + (size_t)pr.l1 * t) * 8);
+    pr.work = take((N * N + N * t) * 8);
     pr.sigma = take(N * 8);
     pr.X1t = take(t * pr.l1 * 8);
     pr.X2t = take(t * pr.l2 * 8);
@@ -236,7 +244,7 @@ int build(rgsvd_plan_s* P, void* ws) {
   // 0. zero the W buffers (their padding rows must read as zero) and copy
   //    the info templates
   for (auto& s : S) {
-    Stage z; z.kind = K_ZERO; z.zoff = s.Wt;
+    Stage z; z.kind = K_ZERO; z.tag = T_ZERO; z.zoff = s.Wt;
     z.zbytes = (size_t)s.L * s.ldw * (prec == P64 ? 8 : 4);
     P->stages.push_back(z);
   }
@@ -257,7 +265,7 @@ int build(rgsvd_plan_s* P, void* ws) {
                            (uint32_t*)info, RGSVD_INFO_WORDS});
       tl.push_back(1);
     }
-    B.add(K_COPY, cj, tl);
+    B.add(K_COPY, cj, tl).tag = T_COPY;
   }
   auto info_of = [&](int pair) -> int32_t* {
     auto& pr = P->pairs[pair];
@@ -276,7 +284,7 @@ int build(rgsvd_plan_s* P, void* ws) {
       tl.push_back(((s.n + 255) / 256) * ngr);
     }
     Stage& st = B.add(K_GEN, j, tl);
-    st.f64 = (prec == P64);
+    st.f64 = (prec == P64); st.tag = T_GEN;
   }
 
   auto add_nn = [&](int p) {
@@ -290,7 +298,7 @@ int build(rgsvd_plan_s* P, void* ws) {
       tl.push_back((s.m + 64 * rt - 1) / (64 * rt));
     }
     Stage& st = B.add(K_NN, j, tl);
-    st.prec = p; st.gdt = gt; st.rt = rt; st.ct = ctL;
+    st.prec = p; st.gdt = gt; st.rt = rt; st.ct = ctL; st.tag = T_NN;
   };
 
   // CholeskyQR passes on the Yt (ymat = true) or Wt buffers
@@ -328,11 +336,11 @@ int build(rgsvd_plan_s* P, void* ws) {
         int js = (sxp == P64) ? 2 : (ctL <= 8 ? 4 : 2);
         atl.push_back((len + 64 * js - 1) / (64 * js));
       }
-      B.add(K_GRAM, gj, gtl).ta = wt;
-      Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.ta = 0; r.td = 0;
-      Stage& c = B.add(K_CHOL, cj, ctl); c.npad_max = P->npadG;
+      Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = wt; gs.tag = T_GRAM;
+      Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.ta = 0; r.td = 0; r.tag = T_RED;
+      Stage& c = B.add(K_CHOL, cj, ctl); c.npad_max = P->npadG; c.tag = T_CHOL;
       Stage& a = B.add(K_AB, aj, atl);
-      a.prec = sxp; a.ta = 0; a.tb = wt; a.td = wt; a.ct = ctL;
+      a.prec = sxp; a.ta = 0; a.tb = wt; a.td = wt; a.ct = ctL; a.tag = T_SX;
       a.js = (sxp == P64) ? 2 : (ctL <= 8 ? 4 : 2);
     }
   };
@@ -363,9 +371,9 @@ int build(rgsvd_plan_s* P, void* ws) {
       rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
     }
     Stage& a = B.add(K_AB, aj, atl);
-    a.prec = p; a.ta = wt; a.tb = gt; a.td = wt; a.ct = ctL; a.js = js;
+    a.prec = p; a.ta = wt; a.tb = gt; a.td = wt; a.ct = ctL; a.js = js; a.tag = T_TN;
     Stage& r = B.add(K_RED, rj, rtl);
-    r.sym = false; r.ta = wt; r.td = wt;
+    r.sym = false; r.ta = wt; r.td = wt; r.tag = T_RED;
   };
 
   const int qmax = [&] { int q = 0; for (auto& pr : P->pairs) q = std::max(q, pr.q); return q; }();
@@ -403,8 +411,8 @@ int build(rgsvd_plan_s* P, void* ws) {
       r.nparts = pr.gch; r.rows = pr.Npad; r.cols = pr.Npad; r.ldo = pr.Npad; r.ldi = pr.Npad;
       rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
     }
-    B.add(K_GRAM, gj, gtl).ta = wt;
-    Stage& r = B.add(K_RED, rj, rtl); r.sym = true;
+    Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = wt; gs.tag = T_MGRAM;
+    Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.tag = T_RED;
   }
   // small step
   {
@@ -429,7 +437,7 @@ int build(rgsvd_plan_s* P, void* ws) {
       x.info = info_of((int)pi);
       sj.push_back(x); tl.push_back(1);
     }
-    B.add(K_SMALL, sj, tl);
+    B.add(K_SMALL, sj, tl).tag = T_SMALL;
   }
   // recovery: R (needed for the sign convention), then U, V
   const int ctT = ct_of([&] { int t = 1; for (auto& pr : P->pairs) t = std::max(t, pr.t); return t; }());
@@ -454,6 +462,7 @@ int build(rgsvd_plan_s* P, void* ws) {
       if (!aj.empty()) {
         Stage& a = B.add(K_AB, aj, atl);
         a.prec = (prec == P64) ? P64 : P32; a.ta = 0; a.tb = wt; a.td = 0; a.ct = ctT; a.js = 2;
+        a.tag = T_RECOVER;
       }
     }
     std::vector<SignJob> sj; std::vector<int> stl, ctl;
@@ -466,8 +475,8 @@ int build(rgsvd_plan_s* P, void* ws) {
       ctl.push_back((int)(((int64_t)pr.t * pr.n + 255) / 256));
     }
     if (!sj.empty()) {
-      B.add(K_SIGN, sj, stl);
-      B.add(K_SCALE, sj, ctl);
+      B.add(K_SIGN, sj, stl).tag = T_SIGN;
+      B.add(K_SCALE, sj, ctl).tag = T_SIGN;
     }
     std::vector<AbJob> aj; std::vector<int> atl;
     for (size_t pi = 0; pi < P->pairs.size(); ++pi) {
@@ -489,6 +498,7 @@ int build(rgsvd_plan_s* P, void* ws) {
     if (!aj.empty()) {
       Stage& a = B.add(K_AB, aj, atl);
       a.prec = (prec == P64) ? P64 : P32; a.ta = 0; a.tb = wt; a.td = 0; a.ct = ctT; a.js = 2;
+      a.tag = T_RECOVER;
     }
   }
   if (P->host.size() > P->jobs_cap) return RGSVD_ENOMEM;
@@ -503,7 +513,18 @@ __global__ void k_copy(const CopyJob* j, const int* pre, int nj) {
 
 int enqueue(rgsvd_plan_s* P, void* ws, hipStream_t st) {
   char* jb = (char*)ws + P->off_jobs;
+  if (P->prof) {
+    while (P->pev.size() < P->stages.size() + 1) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return RGSVD_EHIP;
+      P->pev.push_back(e);
+    }
+    P->prof_count = (int)P->stages.size();
+  }
+  int si = 0;
   for (const Stage& s : P->stages) {
+    if (P->prof) hipEventRecord(P->pev[si], st);
+    ++si;
     const int* pre = (const int*)(jb + s.poff);
     const void* j = jb + s.joff;
     switch (s.kind) {
@@ -520,6 +541,7 @@ int enqueue(rgsvd_plan_s* P, void* ws, hipStream_t st) {
       case K_SCALE: launch_scale((const SignJob*)j, pre, s.nj, s.tiles, st); break;
     }
   }
+  if (P->prof) hipEventRecord(P->pev[si], st);
   return hipGetLastError() == hipSuccess ? RGSVD_OK : RGSVD_EHIP;
 }
 
@@ -648,7 +670,28 @@ void rgsvd_destroy(rgsvd_plan_t P) {
   if (P->pinned) hipHostFree(P->pinned);
   if (P->gexec) hipGraphExecDestroy(P->gexec);
   if (P->mlp) hipFree(P->mlp);
+  for (auto e : P->pev) hipEventDestroy(e);
   delete P;
+}
+
+int rgsvd_profile(rgsvd_plan_t P, int32_t enable) {
+  if (!P || P->batched) return RGSVD_EINVAL;
+  P->prof = enable != 0;
+  return RGSVD_OK;
+}
+
+int rgsvd_profile_read(rgsvd_plan_t P, int32_t max, float* ms, int32_t* tag, int32_t* count) {
+  if (!P || !count || max < 0) return RGSVD_EINVAL;
+  int n = P->prof ? P->prof_count : 0;
+  *count = n;
+  for (int i = 0; i < n && i < max; ++i) {
+    float t = 0.0f;
+    if (hipEventSynchronize(P->pev[i + 1]) != hipSuccess) return RGSVD_EHIP;
+    if (hipEventElapsedTime(&t, P->pev[i], P->pev[i + 1]) != hipSuccess) return RGSVD_EHIP;
+    if (ms) ms[i] = t;
+    if (tag) tag[i] = P->stages[i].tag;
+  }
+  return RGSVD_OK;
 }
 
 // ------------------------------------------------------------- batched --

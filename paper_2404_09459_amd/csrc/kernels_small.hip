@@ -108,60 +108,105 @@ __global__ __launch_bounds__(1024) void k_chol(const CholJob* __restrict__ jobs,
 }
 
 // ------------------------------------------------------ one-sided Jacobi --
-// Orthogonalises the columns of A (nr x nc, column-major, lda) by plane
-// rotations (Hestenes); the same rotations are applied to V (nv x nc,
-// column-major, ldv) when given.  Parallel round-robin ordering: every round
-// pairs each column once; 16 waves share a round's pairs.  Columns stay in
-// the memory given (LDS or global).  Returns the number of sweeps used
-// (maxsweep + 1 when not converged).
-__device__ int jacobi_os(double* A, int lda, int nr, int nc, double* V, int ldv, int nv,
-                         double tol, int maxsweep, int* scratch_flag) {
+// Orthogonalises the columns of A (column-major, lda; nc columns) by plane
+// rotations (Hestenes).  Inner products use rows [0, nd); rotations are
+// applied to rows [0, nr) (nr >= nd), so rows nd..nr-1 just follow along.
+// Parallel round-robin ordering: each round pairs every column once and the
+// 16 waves share the round's pairs; a wave loads all of its pairs' columns
+// before rotating so that global-memory latency is paid once per round.
+// topk > 0: a pair is skipped when both columns have squared norm below
+// (0.5 * topk-th largest norm)^2 (norms refreshed every sweep); at
+// convergence the topk dominant columns are orthogonal to every other
+// column, so they span the dominant invariant subspace.
+// Returns the number of sweeps used (maxsweep + 1 when not converged).
+template <int EPL>  // elements per lane per column (nr <= 64*EPL)
+__device__ int jacobi_os(double* A, int lda, int nr, int nd, int nc, double tol, int maxsweep,
+                         int topk, double* nrm2, int* scratch, double* kth_slot) {
   const int tid = threadIdx.x, wave = tid >> 6, ln = tid & 63;
   const int nc2 = nc + (nc & 1);
   if (nc < 2) return 0;
-  int sweep = 0;
-  for (; sweep < maxsweep; ++sweep) {
-    if (tid == 0) *scratch_flag = 0;
+  constexpr int PB = 4;   // pairs per batch per wave
+  for (int sweep = 0; sweep < maxsweep; ++sweep) {
+    // column norms over the dot rows, and the skip threshold
+    for (int c = wave; c < nc; c += 16) {
+      double s = 0.0;
+      for (int i = ln; i < nd; i += 64) { double v = A[(int64_t)c * lda + i]; s += v * v; }
+      s = wave_sum(s);
+      if (ln == 0) nrm2[c] = s;
+    }
+    if (tid == 0) scratch[0] = 0;
     __syncthreads();
+    double& kth = *kth_slot;
+    double thr = -1.0;
+    if (topk > 0 && topk < nc) {
+      // topk-th largest squared norm: rank count (nc <= 512)
+      if (tid < nc) {
+        double v = nrm2[tid];
+        int r = 0;
+        for (int j = 0; j < nc; ++j) { double w = nrm2[j]; r += (w > v) || (w == v && j < tid); }
+        if (r == topk - 1) kth = v;
+      }
+      __syncthreads();
+      thr = 0.25 * kth;
+    }
     for (int round = 0; round < nc2 - 1; ++round) {
-      for (int pi = wave; pi < nc2 / 2; pi += 16) {
-        int x0 = pi, x1 = nc2 - 1 - pi;
-        int p = (x0 == 0) ? 0 : 1 + (x0 - 1 + round) % (nc2 - 1);
-        int q = (x1 == 0) ? 0 : 1 + (x1 - 1 + round) % (nc2 - 1);
-        if (p >= nc || q >= nc) continue;
-        double* ap = A + (int64_t)p * lda;
-        double* aq = A + (int64_t)q * lda;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int i = ln; i < nr; i += 64) {
-          double u = ap[i], v = aq[i];
-          al += u * u; be += v * v; ga += u * v;
-        }
-        al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
-        if (!(al > 0.0) || !(be > 0.0)) continue;
-        if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
-        double zeta = (be - al) / (2.0 * ga);
-        double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-        for (int i = ln; i < nr; i += 64) {
-          double u = ap[i], v = aq[i];
-          ap[i] = c * u - s * v;
-          aq[i] = s * u + c * v;
-        }
-        if (V) {
-          double* vp = V + (int64_t)p * ldv;
-          double* vq = V + (int64_t)q * ldv;
-          for (int i = ln; i < nv; i += 64) {
-            double u = vp[i], v = vq[i];
-            vp[i] = c * u - s * v;
-            vq[i] = s * u + c * v;
+      const int npairs = nc2 / 2;
+      for (int pb = wave * PB; pb < npairs; pb += 16 * PB) {
+        double ap[PB][EPL], aq[PB][EPL];
+        int P_[PB], Q_[PB];
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+          int pi = pb + b;
+          int p = -1, q = -1;
+          if (pi < npairs) {
+            int x0 = pi, x1 = nc2 - 1 - pi;
+            p = (x0 == 0) ? 0 : 1 + (x0 - 1 + round) % (nc2 - 1);
+            q = (x1 == 0) ? 0 : 1 + (x1 - 1 + round) % (nc2 - 1);
+            if (p >= nc || q >= nc) { p = -1; q = -1; }
+            else if (thr >= 0.0 && nrm2[p] < thr && nrm2[q] < thr) { p = -1; q = -1; }
+          }
+          P_[b] = p; Q_[b] = q;
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) {
+            int i = ln + 64 * e;
+            bool ok = p >= 0 && i < nr;
+            ap[b][e] = ok ? A[(int64_t)p * lda + i] : 0.0;
+            aq[b][e] = ok ? A[(int64_t)q * lda + i] : 0.0;
           }
         }
-        if (ln == 0) *scratch_flag = 1;
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+          if (P_[b] < 0) continue;
+          double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) {
+            int i = ln + 64 * e;
+            if (i < nd) {
+              al += ap[b][e] * ap[b][e]; be += aq[b][e] * aq[b][e]; ga += ap[b][e] * aq[b][e];
+            }
+          }
+          al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
+          if (!(al > 0.0) || !(be > 0.0)) continue;
+          if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
+          double zeta = (be - al) / (2.0 * ga);
+          double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+          const int p = P_[b], q = Q_[b];
+#pragma unroll
+          for (int e = 0; e < EPL; ++e) {
+            int i = ln + 64 * e;
+            if (i < nr) {
+              double u = ap[b][e], v = aq[b][e];
+              A[(int64_t)p * lda + i] = c * u - sn * v;
+              A[(int64_t)q * lda + i] = sn * u + c * v;
+            }
+          }
+          if (ln == 0) scratch[0] = 1;
+        }
       }
       __syncthreads();
     }
-    __syncthreads();
-    int any = *scratch_flag;
+    int any = scratch[0];
     __syncthreads();
     if (!any) return sweep + 1;
   }
@@ -180,92 +225,153 @@ __device__ inline int rank_desc(const double* key, int n, int i) {
 }
 
 // --------------------------------------------------------------- k_small --
-__global__ __launch_bounds__(1024) void k_small(const SmallJob* __restrict__ jobs, int nj) {
-  const SmallJob J = jobs[blockIdx.x];
-  const int N = J.l1 + J.l2, t = J.t, l1 = J.l1, l2 = J.l2;
+// Per pair (one workgroup):
+//  1. diagonally pivoted Cholesky of M = B B^T: P^T M P = R^T R; the columns
+//     of F = P R^T (rows of R scattered back to M's row order) satisfy
+//     F F^T = M, and they are graded, which makes step 2 converge in few
+//     sweeps (the QR-preconditioned Jacobi of Drmac and Veselic);
+//  2. one-sided Jacobi on F: normalised columns are M's eigenvectors, their
+//     norms the singular values of B; L = the t dominant ones (N x t);
+//  3. one-sided Jacobi driven by the rows of L1 = L[:l1] and applied to whole
+//     columns of L: the result is L Y with L1 Y = X1 diag(alpha) and
+//     L2 Y = X2 diag(beta)  (the SVD of L1 in Algorithm 2 and beta from L2);
+//  4. sort by alpha, write alpha, beta, X1^T, X2^T, (L Y)^T and the
+//     comparative quantities.
+struct SmallShared {
+  double keys[SMALL_MAXN];
+  double diag[SMALL_MAXN];
+  double frow[SMALL_MAXN];
+  int perm[SMALL_MAXN];
+  int act[SMALL_MAXN];
+  int scratch[8];
+  int piv_j;
+  double piv_d;
+};
+
+template <int EPL>
+__device__ void small_pair(const SmallJob& J, double* lds, size_t lds_doubles, SmallShared& sh) {
+  const int N = J.l1 + J.l2, t = J.t, l1 = J.l1;
   const int tid = threadIdx.x;
-  __shared__ int flag;
-  __shared__ double keys[SMALL_MAXN];
-  __shared__ int perm[SMALL_MAXN];
-  double* Aw = J.work;                       // N x N column-major (copy of M)
-  double* Lw = Aw + (int64_t)N * N;          // N x t column-major: L then L Y
-  double* Yw = Lw + (int64_t)N * t;          // t x t column-major
-  double* Cw = Yw + (int64_t)t * t;          // l1 x t column-major: L1 (rotated)
-  // ---- eigen-decomposition of M = B B^T by one-sided Jacobi on M itself
-  for (int e = tid; e < N * N; e += 1024) {
-    int c = e / N, r = e - c * N;
-    Aw[e] = J.M[(int64_t)r * J.ldm + c];
+  int* scratch = sh.scratch;
+  double* keys = sh.keys;
+  double* diag = sh.diag;
+  int* perm = sh.perm;
+  int* act = sh.act;
+  int& piv_j = sh.piv_j;
+  double& piv_d = sh.piv_d;
+  // storage: F (N x N) then L (N x t); LDS when they fit, else global work
+  const bool fl = (size_t)N * N <= lds_doubles;
+  double* F = fl ? lds : J.work;                    // N x N, column k = k-th pivot column
+  double* frow = sh.frow;
+  // ---- 1. left-looking diagonally pivoted Cholesky of M (read in place)
+  for (int e = tid; e < N * N; e += 1024) F[e] = 0.0;
+  for (int i = tid; i < N; i += 1024) { diag[i] = J.M[(int64_t)i * J.ldm + i]; act[i] = 1; }
+  __syncthreads();
+  double dmax0 = 0.0;
+  for (int i = 0; i < N; ++i) dmax0 = fmax(dmax0, diag[i]);
+  // rows handled by groups of TPR threads
+  int TPR = 1;
+  while (TPR * 2 * N <= 1024 && TPR < 16) TPR *= 2;
+  const int row = tid / TPR, part = tid % TPR;
+  int rank = 0;
+  for (int k = 0; k < N; ++k) {
+    if (tid < 64) {
+      double best = -1.0; int bj = -1;
+      for (int j = tid; j < N; j += 64)
+        if (act[j] && diag[j] > best) { best = diag[j]; bj = j; }
+      for (int o = 32; o > 0; o >>= 1) {
+        double b2 = __shfl_xor(best, o, 64);
+        int j2 = __shfl_xor(bj, o, 64);
+        if (b2 > best || (b2 == best && j2 >= 0 && (bj < 0 || j2 < bj))) { best = b2; bj = j2; }
+      }
+      if (tid == 0) { piv_j = bj; piv_d = best; }
+    }
+    __syncthreads();
+    const int js = piv_j;
+    const double d = piv_d;
+    if (js < 0 || !(d > 1e-15 * dmax0) || !(d > 0.0)) break;   // numerical rank reached
+    for (int kk = tid; kk < k; kk += 1024) frow[kk] = F[(int64_t)kk * N + js];
+    __syncthreads();
+    const double sd = sqrt(d), rd = 1.0 / sd;
+    // column k: (M[:, js] - F[:, :k] F[js, :k]^T) / sqrt(d) on the active rows
+    double acc = 0.0;
+    if (row < N && act[row])
+      for (int kk = part; kk < k; kk += TPR) acc += F[(int64_t)kk * N + row] * frow[kk];
+    for (int o = TPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    __syncthreads();
+    if (row < N && part == 0) {
+      double v = 0.0;
+      if (row == js) v = sd;
+      else if (act[row]) v = (J.M[(int64_t)row * J.ldm + js] - acc) * rd;
+      F[(int64_t)k * N + row] = v;
+      if (act[row] && row != js) diag[row] -= v * v;
+    }
+    if (tid == 0) act[js] = 0;
+    __syncthreads();
+    rank = k + 1;
   }
   __syncthreads();
-  int sw1 = jacobi_os(Aw, N, N, N, nullptr, 0, 0, J.tol, J.maxsweep, &flag);
-  // column norms = eigenvalues (M is positive semidefinite)
+  // ---- 2. Jacobi on the rank columns of F (only pairs touching the t dominant)
+  int sw1 = jacobi_os<EPL>(F, N, N, N, rank, J.tol, J.maxsweep, t, keys, scratch, &sh.piv_d);
   for (int c = tid; c < N; c += 1024) {
     double s = 0.0;
-    for (int r = 0; r < N; ++r) { double v = Aw[(int64_t)c * N + r]; s += v * v; }
+    if (c < rank)
+      for (int r = 0; r < N; ++r) { double v = F[(int64_t)c * N + r]; s += v * v; }
     keys[c] = sqrt(s);
   }
   __syncthreads();
   for (int c = tid; c < N; c += 1024) perm[rank_desc(keys, N, c)] = c;
   __syncthreads();
-  for (int i = tid; i < N; i += 1024) J.sigma[i] = sqrt(keys[perm[i]]);   // singular values of B
-  // L = normalised top-t eigenvectors
+  for (int i = tid; i < N; i += 1024) J.sigma[i] = keys[perm[i]];   // singular values of B
+  // L (N x t, column-major) = normalised dominant columns, stored where it fits
+  const bool ll = (size_t)N * t <= lds_doubles;
+  double* L = ll ? (fl ? J.work : lds) : J.work + (int64_t)N * N;
+  // (when F lives in LDS, L goes to global work first, then moved below)
   for (int e = tid; e < N * t; e += 1024) {
     int c = e / N, r = e - c * N;
     int src = perm[c];
-    double nrm = keys[src];
-    Lw[e] = nrm > 0.0 ? Aw[(int64_t)src * N + r] / nrm : 0.0;
+    double nv = keys[src];
+    L[e] = (c < rank && nv > 0.0) ? F[(int64_t)src * N + r] / nv : 0.0;
   }
   __syncthreads();
-  // ---- SVD of L1 (l1 x t) by one-sided Jacobi, accumulating Y (t x t)
-  for (int e = tid; e < l1 * t; e += 1024) {
-    int c = e / l1, r = e - c * l1;
-    Cw[e] = Lw[(int64_t)c * N + r];
+  if (ll && fl) {   // move L into LDS (F no longer needed)
+    for (int e = tid; e < N * t; e += 1024) lds[e] = L[e];
+    __syncthreads();
+    L = lds;
   }
-  for (int e = tid; e < t * t; e += 1024) {
-    int c = e / t, r = e - c * t;
-    Yw[e] = (r == c) ? 1.0 : 0.0;
-  }
-  __syncthreads();
-  int sw2 = jacobi_os(Cw, l1, l1, t, Yw, t, t, J.tol, J.maxsweep, &flag);
+  // ---- 3. SVD of L1 driven rotations on whole columns of L
+  int sw2 = jacobi_os<EPL>(L, N, N, l1, t, J.tol, J.maxsweep, 0, keys, scratch, &sh.piv_d);
   for (int c = tid; c < t; c += 1024) {
     double s = 0.0;
-    for (int r = 0; r < l1; ++r) { double v = Cw[(int64_t)c * l1 + r]; s += v * v; }
+    for (int r = 0; r < l1; ++r) { double v = L[(int64_t)c * N + r]; s += v * v; }
     keys[c] = sqrt(s);
   }
   __syncthreads();
   for (int c = tid; c < t; c += 1024) perm[rank_desc(keys, t, c)] = c;
   __syncthreads();
-  // alpha and X1^T (t x l1 row-major); zero-alpha columns of X1 left at 0
   for (int i = tid; i < t; i += 1024) J.alpha[i] = keys[perm[i]];
-  for (int e = tid; e < t * l1; e += 1024) {
-    int i = e / l1, r = e - i * l1;
-    int src = perm[i];
-    double a = keys[src];
-    J.X1t[(int64_t)i * J.ldx1 + r] = a > 0.0 ? Cw[(int64_t)src * l1 + r] / a : 0.0;
-  }
-  // LY (N x t) = L * Y(:, perm): stored as Rcoef (t x N row-major)
-  for (int e = tid; e < t * N; e += 1024) {
-    int i = e / N, r = e - i * N;
-    int src = perm[i];
-    double s = 0.0;
-    for (int c = 0; c < t; ++c) s += Lw[(int64_t)c * N + r] * Yw[(int64_t)src * t + c];
-    J.Rcoef[(int64_t)i * J.ldr + r] = s;
-  }
-  __syncthreads();
-  // beta_i = || L2 y_i ||,  X2 = L2 Y / beta   (rows l1..N-1 of LY)
   for (int i = tid; i < t; i += 1024) {
+    int src = perm[i];
     double s = 0.0;
-    for (int r = l1; r < N; ++r) { double v = J.Rcoef[(int64_t)i * J.ldr + r]; s += v * v; }
+    for (int r = l1; r < N; ++r) { double v = L[(int64_t)src * N + r]; s += v * v; }
     J.beta[i] = sqrt(s);
   }
   __syncthreads();
-  for (int e = tid; e < t * l2; e += 1024) {
-    int i = e / l2, r = e - i * l2;
-    double b = J.beta[i];
-    J.X2t[(int64_t)i * J.ldx2 + r] = b > BETA_ZERO ? J.Rcoef[(int64_t)i * J.ldr + l1 + r] / b : 0.0;
+  for (int e = tid; e < t * N; e += 1024) {
+    int i = e / N, r = e - i * N;
+    int src = perm[i];
+    double v = L[(int64_t)src * N + r];
+    J.Rcoef[(int64_t)i * J.ldr + r] = v;
+    if (r < l1) {
+      double a = keys[src];
+      J.X1t[(int64_t)i * J.ldx1 + r] = a > 0.0 ? v / a : 0.0;
+    } else {
+      double b = J.beta[i];
+      J.X2t[(int64_t)i * J.ldx2 + (r - l1)] = b > BETA_ZERO ? v / b : 0.0;
+    }
   }
   __syncthreads();
-  // ---- comparative quantities over the t pairs
+  // ---- 4. comparative quantities over the t pairs
   if (tid < 64) {
     double sa = 0.0, sb = 0.0;
     for (int i = tid; i < t; i += 64) {
@@ -290,15 +396,25 @@ __global__ __launch_bounds__(1024) void k_small(const SmallJob* __restrict__ job
       J.D[1] = t > 1 ? h2 / lt : 0.0;
       if (J.info) {
         J.info[5] = sw1; J.info[6] = sw2;
-        int fl = 0;
-        if (sw1 > J.maxsweep) fl |= FLAG_JACOBI_M;
-        if (sw2 > J.maxsweep) fl |= FLAG_JACOBI_L1;
-        if (!(sa > 0.0)) fl |= FLAG_ALPHA_ZERO;
-        for (int i = 0; i < t; ++i) if (!(J.beta[i] > BETA_ZERO)) fl |= FLAG_BETA_ZERO;
-        if (fl) atomicOr(J.info + 4, fl);
+        int fl2 = 0;
+        if (sw1 > J.maxsweep) fl2 |= FLAG_JACOBI_M;
+        if (sw2 > J.maxsweep) fl2 |= FLAG_JACOBI_L1;
+        if (!(sa > 0.0)) fl2 |= FLAG_ALPHA_ZERO;
+        for (int i = 0; i < t; ++i) if (!(J.beta[i] > BETA_ZERO)) fl2 |= FLAG_BETA_ZERO;
+        if (fl2) atomicOr(J.info + 4, fl2);
       }
     }
   }
+}
+
+__global__ __launch_bounds__(1024) void k_small(const SmallJob* __restrict__ jobs, int nj,
+                                                size_t lds_doubles) {
+  extern __shared__ double lds[];
+  __shared__ SmallShared sh;
+  const SmallJob J = jobs[blockIdx.x];
+  const int N = J.l1 + J.l2;
+  if (N <= 256) small_pair<4>(J, lds, lds_doubles, sh);
+  else small_pair<8>(J, lds, lds_doubles, sh);
 }
 
 // ------------------------------------------------------------- k_rowsign --
@@ -355,7 +471,13 @@ void launch_chol(const CholJob* j, int nj, int npad_max, double* gscratch, hipSt
 }
 
 void launch_small(const SmallJob* j, int nj, hipStream_t st) {
-  hipLaunchKernelGGL(k_small, dim3(nj), dim3(1024), 0, st, j, nj);
+  static bool attr_set = false;
+  const size_t bytes = SMALL_LDS_BYTES;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)k_small, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_small, dim3(nj), dim3(1024), bytes, st, j, nj, bytes / sizeof(double));
 }
 
 void launch_sign(const SignJob* j, const int* pre, int nj, int tiles, hipStream_t st) {

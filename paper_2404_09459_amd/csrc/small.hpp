@@ -8,6 +8,7 @@ constexpr int CHOL_LDS_MAX = 128;   // Gram orders kept in LDS by k_chol
 constexpr int CHOL_MAX = 256;       // largest padded Gram order
 constexpr int SMALL_MAXN = 512;     // largest l1 + l2 of the compressed pair
 constexpr double BETA_ZERO = 1e-14;
+constexpr size_t SMALL_LDS_BYTES = 128 * 1024;   // dynamic LDS of k_small (columns that fit)
 
 // flag bits of info[4] (same values as the public header)
 constexpr int FLAG_CHOL_FAIL = 0x4;
@@ -22,7 +23,7 @@ struct SmallJob {
   const double* M; int64_t ldm;
   int32_t l1, l2, t, maxsweep;
   double tol;
-  double* work;                     // N*N + N*t + t*t + l1*t doubles
+  double* work;                     // 2*N*N + N*t doubles
   double* sigma;                    // N
   double *alpha, *beta, *theta, *P1, *P2, *D;
   double* X1t; int64_t ldx1;        // t x l1

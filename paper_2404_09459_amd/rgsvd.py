@@ -65,6 +65,9 @@ EXPORTS = {
     "rgsvd_plan_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "rgsvd_destroy": (None, [ctypes.c_void_p]),
+    "rgsvd_profile": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
+    "rgsvd_profile_read": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     "rgsvd_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "rgsvd_batch_plan": (ctypes.c_int, [ctypes.POINTER(Desc), ctypes.c_int32,
                                         ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(ctypes.c_size_t)]),
@@ -229,6 +232,19 @@ def rgsvd(G1, G2, k, oversample, q, seed, precision="fp64", mode="truncated", uv
         o["U"] = o["Ut"].t()
         o["V"] = o["Vt"].t()
     return o
+
+
+STAGE_TAGS = ["zero", "info", "gen", "nn", "tn", "reduce", "gram", "chol", "sx", "small",
+              "recover", "sign", "mgram"]
+
+
+def profile_read(plan, maxn=512):
+    """Per-stage (tag, ms) of the last profiled run (call after a sync)."""
+    ms = (ctypes.c_float * maxn)()
+    tg = (ctypes.c_int32 * maxn)()
+    cnt = ctypes.c_int32()
+    check(lib().rgsvd_profile_read(plan.h, maxn, ms, tg, ctypes.byref(cnt)), "rgsvd_profile_read")
+    return [(STAGE_TAGS[tg[i]], float(ms[i])) for i in range(min(cnt.value, maxn))]
 
 
 def decode_flags(word):

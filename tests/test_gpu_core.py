@@ -145,8 +145,11 @@ def _check_pair(got, ref, tol_gsv=1e-10, tol_vec=1e-8, vecs=True):
          f" info={got['info'].tolist()}")
     assert da <= tol_gsv and db <= tol_gsv
     assert dth <= tol_gsv and dp1 <= tol_gsv and dp2 <= tol_gsv and dd <= tol_gsv
-    nB = len(ref["sigma_B"])
-    assert np.max(np.abs(got["sigma_B"][:nB] - ref["sigma_B"])) <= 1e-9 * ref["sigma_B"][0]
+    # the t dominant singular values of the stacked compressed pair; the tail
+    # entries only carry the tail's Frobenius norm
+    sB, rB = got["sigma_B"], ref["sigma_B"]
+    assert np.max(np.abs(sB[:t] - rB[:t])) <= 1e-9 * rB[0]
+    assert abs(np.linalg.norm(sB[t:]) - np.linalg.norm(rB[t:])) <= 1e-9 * rB[0]
     if vecs:
         U = _align(got["U"], ref["U"])
         V = _align(got["V"], ref["V"])
