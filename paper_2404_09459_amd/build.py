@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "librgsvd.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["capi.cpp", "kernels_gemm.hip", "kernels_small.hip", "kernels_misc.hip"]
+SOURCES = ["capi.cpp", "kernels_gemm.hip", "kernels_stream.hip", "kernels_small.hip", "kernels_misc.hip"]
 FLAGS = ["-x", "hip", "-std=c++17", "-O3", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]

@@ -43,7 +43,8 @@ inline int ct_of(int L) {
   return 16;
 }
 
-enum Kind { K_ZERO, K_COPY, K_GEN, K_NN, K_AB, K_GRAM, K_RED, K_CHOL, K_SMALL, K_SIGN, K_SCALE };
+enum Kind { K_ZERO, K_COPY, K_GEN, K_NN, K_AB, K_GRAM, K_RED, K_CHOL, K_SMALL, K_SIGN, K_SCALE, K_GW, K_GTQ,
+            K_CVT };
 
 enum Tag { T_ZERO, T_COPY, T_GEN, T_NN, T_TN, T_RED, T_GRAM, T_CHOL, T_SX, T_SMALL, T_RECOVER, T_SIGN,
            T_MGRAM, T_NTAGS };
@@ -61,13 +62,14 @@ struct Stage {
 };
 
 struct CopyJob { const uint32_t* src; uint32_t* dst; int64_t nwords; };
+struct CvtJobH { const float* src; void* dst; int64_t ld; int32_t rows, cols; };
 
 struct SideLay {
   int m = 0, n = 0, l = 0, L = 0, which = 0, pair = 0;
   int ldy = 0, ldw = 0;
   int nchunk = 1, mchunk = 0;
   int gch_m = 1, gcl_m = 0, gch_n = 1, gcl_n = 0;
-  size_t Yt = 0, Wt = 0, part = 0, gpart = 0, gram = 0, sinv = 0;
+  size_t Yt = 0, Wt = 0, part = 0, gpart = 0, gram = 0, sinv = 0, Yt16 = 0, Wt16 = 0;
   const void* G = nullptr; int64_t ldg = 0;
   uint64_t seed = 0; int stream = 1;
 };
@@ -93,6 +95,7 @@ struct rgsvd_plan_s {
   std::vector<SideLay> sides;
   size_t off_chol = 0, off_jobs = 0, jobs_cap = 0, ws = 0;
   int nchol_slots = 0;
+  int wave_slots = 2048;   // concurrently resident single-wave workgroups
   // job tables
   std::vector<unsigned char> host;   // serialized job tables
   std::vector<Stage> stages;
@@ -141,11 +144,13 @@ int layout(rgsvd_plan_s* P) {
       s.L = (int)upi(s.l, 16);
       s.ldy = (int)upi(s.m, 64); s.ldw = (int)upi(s.n, 64);
       s.seed = pr.seed; s.stream = w ? 2 : 1;
-      // G^T Q row chunks
-      int js = (prec == P64) ? 2 : (ct_of(s.L) <= 8 ? 4 : 2);
-      int jt = (int)((s.n + 64 * js - 1) / (64 * js));
-      int target = std::max(1, 1024 / std::max(1, nsides));
-      int nch = std::max(1, std::min((s.m + 255) / 256, (target + jt - 1) / jt));
+      // G^T Q row chunks: enough single-wave tiles to fill the wave slots once
+      int js = (prec == P64 || P->gdt == RGSVD_F64 || s.L > 128) ? 2 : 4;
+      int jt = (int)((s.n + 16 * js - 1) / (16 * js));
+      int64_t rows_all = 0;
+      for (auto& q : P->pairs) rows_all += q.m + q.p;
+      int nch = (int)std::max<int64_t>(1, (int64_t)P->wave_slots * s.m / std::max<int64_t>(1, rows_all * jt));
+      nch = std::max(1, std::min(nch, (s.m + 255) / 256));
       int mch = (int)upi((s.m + nch - 1) / nch, 32);
       nch = (s.m + mch - 1) / mch;
       s.nchunk = nch; s.mchunk = mch;
@@ -160,6 +165,10 @@ int layout(rgsvd_plan_s* P) {
       s.gch_n = (s.n + s.gcl_n - 1) / s.gcl_n;
       s.Yt = take((size_t)s.L * s.ldy * wsz);
       s.Wt = take((size_t)s.L * s.ldw * wsz);
+      if (prec == PBF) {
+        s.Yt16 = take((size_t)s.L * s.ldy * 2);
+        s.Wt16 = take((size_t)s.L * s.ldw * 2);
+      }
       s.part = take((size_t)s.nchunk * s.L * s.ldw * psz);
       int gch = std::max(s.gch_m, s.gch_n);
       s.gpart = take((size_t)gch * P->npadG * P->npadG * 8);
@@ -247,6 +256,9 @@ int build(rgsvd_plan_s* P, void* ws) {
     Stage z; z.kind = K_ZERO; z.tag = T_ZERO; z.zoff = s.Wt;
     z.zbytes = (size_t)s.L * s.ldw * (prec == P64 ? 8 : 4);
     P->stages.push_back(z);
+    Stage y = z; y.zoff = s.Yt;
+    y.zbytes = (size_t)s.L * s.ldy * (prec == P64 ? 8 : 4);
+    P->stages.push_back(y);
   }
   {
     std::vector<uint32_t> tmpl;
@@ -287,17 +299,32 @@ int build(rgsvd_plan_s* P, void* ws) {
     st.f64 = (prec == P64); st.tag = T_GEN;
   }
 
+  // bf16 copies of the W (ymat = false) or Q (ymat = true) buffers
+  auto add_cvt = [&](bool ymat) {
+    std::vector<CvtJobH> j; std::vector<int> tl;
+    for (auto& s : S) {
+      CvtJobH c{};
+      c.src = (const float*)WS(ws, ymat ? s.Yt : s.Wt);
+      c.dst = WS(ws, ymat ? s.Yt16 : s.Wt16);
+      c.ld = ymat ? s.ldy : s.ldw; c.rows = s.L; c.cols = (int)c.ld;
+      j.push_back(c);
+      tl.push_back((int)(((int64_t)s.L * c.ld / 4 + 255) / 256));
+    }
+    B.add(K_CVT, j, tl).tag = T_ZERO;
+  };
+
   auto add_nn = [&](int p) {
+    if (p == PBF) add_cvt(false);
     std::vector<NnJob> j; std::vector<int> tl;
-    int rt = (p == P64) ? 1 : 2;
+    int rt = (p == P64 || gt == 0 || ctL > 8) ? 1 : 4;
     for (auto& s : S) {
       NnJob x{};
-      x.G = s.G; x.Wt = WS(ws, s.Wt); x.Yt = WS(ws, s.Yt);
+      x.G = s.G; x.Wt = WS(ws, p == PBF ? s.Wt16 : s.Wt); x.Yt = WS(ws, s.Yt);
       x.ldg = s.ldg; x.ldw = s.ldw; x.ldy = s.ldy; x.m = s.m; x.n = s.n; x.L = s.L;
       j.push_back(x);
-      tl.push_back((s.m + 64 * rt - 1) / (64 * rt));
+      tl.push_back((s.m + 16 * rt - 1) / (16 * rt));
     }
-    Stage& st = B.add(K_NN, j, tl);
+    Stage& st = B.add(K_GW, j, tl);
     st.prec = p; st.gdt = gt; st.rt = rt; st.ct = ctL; st.tag = T_NN;
   };
 
@@ -347,22 +374,23 @@ int build(rgsvd_plan_s* P, void* ws) {
 
   // G^T Q (or Q^T G) into the Wt buffers: split over row chunks then reduced
   auto add_tn = [&](int p) {
+    if (p == PBF) add_cvt(true);
     std::vector<AbJob> aj; std::vector<int> atl;
     std::vector<RedJob> rj; std::vector<int> rtl;
-    int js = (p == P64) ? 2 : (ctL <= 8 ? 4 : 2);
-    if (p == PBF) js = 2;
+    const int js = (p == P64 || gt == 0 || ctL > 8) ? 2 : 4;
     const size_t psz = (prec == P64) ? 8 : 4;
+    const size_t asz = (p == P64) ? 8 : (p == P32 ? 4 : 2);
     for (auto& s : S) {
       for (int c = 0; c < s.nchunk; ++c) {
         int r0 = c * s.mchunk;
         int rows = std::min(s.mchunk, s.m - r0);
         AbJob a{};
-        a.A = (const char*)WS(ws, s.Yt) + (size_t)r0 * psz; a.lda = s.ldy;
+        a.A = (const char*)WS(ws, p == PBF ? s.Yt16 : s.Yt) + (size_t)r0 * asz; a.lda = s.ldy;
         a.B = (const char*)s.G + (size_t)r0 * s.ldg * (gt == 0 ? 8 : 4); a.ldb = s.ldg;
         a.D = WS(ws, s.part) + (size_t)c * s.L * s.ldw * psz; a.ldd = s.ldw;
         a.rows = s.L; a.K = rows; a.J = s.n; a.accumulate = 0; a.colscale = nullptr;
         aj.push_back(a);
-        atl.push_back((s.n + 64 * js - 1) / (64 * js));
+        atl.push_back((s.n + 16 * js - 1) / (16 * js));
       }
       RedJob r{};
       r.in = WS(ws, s.part); r.out = WS(ws, s.Wt); r.sq = nullptr;
@@ -370,8 +398,8 @@ int build(rgsvd_plan_s* P, void* ws) {
       r.nparts = s.nchunk; r.rows = s.L; r.cols = s.n; r.ldo = s.ldw; r.ldi = s.ldw;
       rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
     }
-    Stage& a = B.add(K_AB, aj, atl);
-    a.prec = p; a.ta = wt; a.tb = gt; a.td = wt; a.ct = ctL; a.js = js; a.tag = T_TN;
+    Stage& a = B.add(K_GTQ, aj, atl);
+    a.prec = p; a.gdt = gt; a.ct = ctL; a.js = js; a.tag = T_TN;
     Stage& r = B.add(K_RED, rj, rtl);
     r.sym = false; r.ta = wt; r.td = wt; r.tag = T_RED;
   };
@@ -531,7 +559,6 @@ int enqueue(rgsvd_plan_s* P, void* ws, hipStream_t st) {
       case K_ZERO: launch_zero((char*)ws + s.zoff, (int64_t)s.zbytes, st); break;
       case K_COPY: hipLaunchKernelGGL(k_copy, dim3(s.tiles), dim3(64), 0, st, (const CopyJob*)j, pre, s.nj); break;
       case K_GEN: launch_gen(s.f64, (const GenJob*)j, pre, s.nj, s.tiles, st); break;
-      case K_NN: launch_nn(s.prec, s.gdt, s.rt, s.ct, (const NnJob*)j, pre, s.nj, s.tiles, st); break;
       case K_AB: launch_ab(s.prec, s.ta, s.tb, s.td, s.ct, s.js, (const AbJob*)j, pre, s.nj, s.tiles, st); break;
       case K_GRAM: launch_gram(s.ta, (const GramJob*)j, pre, s.nj, s.tiles, st); break;
       case K_RED: launch_reduce(s.ta, s.td, s.sym, (const RedJob*)j, pre, s.nj, s.tiles, st); break;
@@ -539,6 +566,9 @@ int enqueue(rgsvd_plan_s* P, void* ws, hipStream_t st) {
       case K_SMALL: launch_small((const SmallJob*)j, s.nj, st); break;
       case K_SIGN: launch_sign((const SignJob*)j, pre, s.nj, s.tiles, st); break;
       case K_SCALE: launch_scale((const SignJob*)j, pre, s.nj, s.tiles, st); break;
+      case K_GW: launch_gw(s.prec, s.gdt, s.rt, s.ct, (const NnJob*)j, pre, s.nj, s.tiles, st); break;
+      case K_GTQ: launch_gtq(s.prec, s.gdt, s.ct, s.js, (const AbJob*)j, pre, s.nj, s.tiles, st); break;
+      case K_CVT: launch_cvt(j, pre, s.nj, s.tiles, st); break;
     }
   }
   if (P->prof) hipEventRecord(P->pev[si], st);
@@ -581,6 +611,15 @@ int check_desc(const rgsvd_desc* d) {
   return RGSVD_OK;
 }
 
+// single-wave workgroups resident at once: compute units x 4 SIMDs x 1 wave
+int device_wave_slots() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  return cus * 4;
+}
+
 PairLay pair_from(const rgsvd_desc* d) {
   PairLay pr;
   pr.m = d->m; pr.p = d->p; pr.n = d->n; pr.k = d->k; pr.o = d->oversample; pr.q = d->power_iters;
@@ -621,6 +660,7 @@ int rgsvd_plan(const rgsvd_desc* desc, rgsvd_plan_t* plan, size_t* workspace_byt
   P->gdt = desc->in_dtype;
   P->mode = desc->mode;
   P->pairs.push_back(pair_from(desc));
+  P->wave_slots = device_wave_slots();
   rc = layout(P);
   if (rc) { delete P; return rc; }
   *plan = P;
@@ -714,6 +754,7 @@ int rgsvd_batch_plan(const rgsvd_desc* shapes, int32_t npairs, rgsvd_plan_t* pla
   P->gdt = shapes[0].in_dtype;
   P->mode = shapes[0].mode;
   for (int i = 0; i < npairs; ++i) P->pairs.push_back(pair_from(&shapes[i]));
+  P->wave_slots = device_wave_slots();
   int rc = layout(P);
   if (rc) { delete P; return rc; }
   *plan = P;

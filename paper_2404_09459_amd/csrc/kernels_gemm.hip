@@ -1,7 +1,6 @@
 // Grouped tall-skinny kernels of the basis extraction and projection.
 //
 //  k_gen     : Omega^T from the counter-based generator (sketch operand)
-//  k_nn      : Y = G W                    (Algorithm 1's G Omega_i; power step G W)
 //  k_ab      : D = A B, A small, B tall   (G^T Q and the projection Q^T G of
 //                                          Algorithm 2, split over row chunks;
 //                                          the triangular solve Q = Y R^{-1};
@@ -52,118 +51,6 @@ __global__ __launch_bounds__(256) void k_gen(const GenJob* __restrict__ jobs,
     for (int e = 0; e < 4; ++e) {
       int c = 4 * j + e - J.col0;
       if (c >= 0 && c < J.ncols) Wt[(int64_t)c * J.ldw + r] = (TW)z[e];
-    }
-  }
-}
-
-// ----------------------------------------------------------------- k_nn --
-// WG = 4 waves; each wave owns RT row tiles (16 rows each) of G and all CT
-// column tiles of W.  The W chunk (CT*16 x KC) is staged in LDS once per WG;
-// G is streamed from HBM straight into registers (each lane a contiguous run
-// of KC/4 elements of one row), with the next chunk prefetched.
-template <int P, typename TG, int RT, int CT>
-__global__ __launch_bounds__(256) void k_nn(const NnJob* __restrict__ jobs,
-                                            const int* __restrict__ pre, int nj) {
-  using TR = Tr<P>;
-  using cT = typename TR::cT;
-  using acc_t = typename TR::acc;
-  using wT = typename TR::wT;
-  using aT = typename std::conditional<P == P64, double, float>::type;
-  constexpr int KC = TR::KC, KL = KC / 4, KPI = TR::KPI, NI = KL / KPI;
-  constexpr int RL = KC + TR::PAD;
-  constexpr int NWE = CT * 16 * KC;
-  constexpr int WPT = (NWE + 255) / 256;
-  __shared__ cT Ws[CT * 16 * RL];
-
-  const int jb = find_side(pre, nj, blockIdx.x);
-  const NnJob J = jobs[jb];
-  const int tile = blockIdx.x - pre[jb];
-  const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63, g = ln >> 4, li = ln & 15;
-  const int row0 = tile * 64 * RT + wave * 16 * RT;
-  const int ctn = J.L >> 4;
-  const TG* __restrict__ G = (const TG*)J.G;
-  const wT* __restrict__ Wt = (const wT*)J.Wt;
-
-  acc_t acc[RT][CT];
-#pragma unroll
-  for (int a = 0; a < RT; ++a)
-#pragma unroll
-    for (int b = 0; b < CT; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
-
-  aT an[RT][KL];
-  wT wn[WPT];
-  const int nk = (J.n + KC - 1) / KC;
-
-  auto load_a = [&](int kc) {
-#pragma unroll
-    for (int a = 0; a < RT; ++a) {
-      int r = row0 + a * 16 + li;
-      bool ok = r < J.m;
-      const TG* rowp = G + (int64_t)(ok ? r : 0) * J.ldg;
-      load_run<TG, aT, KL>(an[a], rowp, kc * KC + g * KL, J.n, ok);
-    }
-  };
-  auto load_w = [&](int kc) {
-#pragma unroll
-    for (int i = 0; i < WPT; ++i) {
-      int e = threadIdx.x + 256 * i;
-      int c = e / KC, kk = e - c * KC;
-      int k = kc * KC + kk;
-      wn[i] = (e < NWE && c < J.L && k < J.n) ? Wt[(int64_t)c * J.ldw + k] : (wT)0;
-    }
-  };
-
-  load_a(0);
-  load_w(0);
-  for (int kc = 0; kc < nk; ++kc) {
-    cT a[RT][KL];
-#pragma unroll
-    for (int x = 0; x < RT; ++x)
-#pragma unroll
-      for (int e = 0; e < KL; ++e) a[x][e] = cvt<P>((double)an[x][e]);
-    wT w[WPT];
-#pragma unroll
-    for (int i = 0; i < WPT; ++i) w[i] = wn[i];
-    if (kc + 1 < nk) { load_a(kc + 1); load_w(kc + 1); }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < WPT; ++i) {
-      int e = threadIdx.x + 256 * i;
-      if (e < NWE) {
-        int c = e / KC, kk = e - c * KC;
-        Ws[c * RL + kk] = cvt<P>((double)w[i]);
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int ct = 0; ct < CT; ++ct) {
-      if (ct < ctn) {
-        cT b[KL];
-        const cT* src = Ws + (ct * 16 + li) * RL + g * KL;
-#pragma unroll
-        for (int e = 0; e < KL; ++e) b[e] = src[e];
-#pragma unroll
-        for (int x = 0; x < RT; ++x)
-#pragma unroll
-          for (int s = 0; s < NI; ++s) mma_step<P>(acc[x][ct], &a[x][s * KPI], &b[s * KPI]);
-      }
-    }
-  }
-  // store: lane holds Y[row0 + x*16 + out_row(g, ii)][ct*16 + li] -> Yt[ct*16+li][...]
-  wT* Yt = (wT*)J.Yt;
-#pragma unroll
-  for (int ct = 0; ct < CT; ++ct) {
-    if (ct < ctn) {
-      int c = ct * 16 + li;
-#pragma unroll
-      for (int x = 0; x < RT; ++x) {
-        wT* dst = Yt + (int64_t)c * J.ldy;
-#pragma unroll
-        for (int ii = 0; ii < 4; ++ii) {
-          int r = row0 + x * 16 + out_row<P>(g, ii);
-          if (r < J.m) dst[r] = (wT)acc[x][ct][ii];
-        }
-      }
     }
   }
 }
@@ -381,38 +268,6 @@ __global__ __launch_bounds__(256) void k_reduce(const RedJob* __restrict__ jobs,
 }
 
 // ---------------------------------------------------------------- launch --
-template <int P, typename TG, int RT, int CT>
-static void launch_nn_ct(const NnJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
-  hipLaunchKernelGGL((k_nn<P, TG, RT, CT>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
-}
-
-template <int P, typename TG, int RT>
-static void launch_nn_rt(int ct, const NnJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
-  switch (ct) {
-    case 1: launch_nn_ct<P, TG, RT, 1>(j, pre, nj, tiles, st); break;
-    case 2: launch_nn_ct<P, TG, RT, 2>(j, pre, nj, tiles, st); break;
-    case 4: launch_nn_ct<P, TG, RT, 4>(j, pre, nj, tiles, st); break;
-    case 8: launch_nn_ct<P, TG, RT, 8>(j, pre, nj, tiles, st); break;
-    default: launch_nn_ct<P, TG, RT, 16>(j, pre, nj, tiles, st); break;
-  }
-}
-
-void launch_nn(int prec, int gdt, int rt, int ct, const NnJob* j, const int* pre, int nj,
-               int tiles, hipStream_t st) {
-  if (prec == P64) {
-    if (gdt == G_F64) launch_nn_rt<P64, double, 1>(ct, j, pre, nj, tiles, st);
-    else launch_nn_rt<P64, float, 1>(ct, j, pre, nj, tiles, st);
-  } else if (prec == P32) {
-    if (gdt == G_F64) launch_nn_rt<P32, double, 1>(ct, j, pre, nj, tiles, st);
-    else if (rt == 2) launch_nn_rt<P32, float, 2>(ct, j, pre, nj, tiles, st);
-    else launch_nn_rt<P32, float, 1>(ct, j, pre, nj, tiles, st);
-  } else {
-    if (gdt == G_F64) launch_nn_rt<PBF, double, 1>(ct, j, pre, nj, tiles, st);
-    else if (rt == 2) launch_nn_rt<PBF, float, 2>(ct, j, pre, nj, tiles, st);
-    else launch_nn_rt<PBF, float, 1>(ct, j, pre, nj, tiles, st);
-  }
-}
-
 template <int P, typename TA, typename TB, typename TD, int JS>
 static void launch_ab_js(int ct, const AbJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
   switch (ct) {

@@ -54,6 +54,7 @@ __global__ __launch_bounds__(1024) void k_chol(const CholJob* __restrict__ jobs,
     }
     if (tid == 0) bad = 0;
     __syncthreads();
+    const int tx = tid & 31, ty = tid >> 5;   // 32 x 32 thread grid
     for (int k = 0; k < N; ++k) {
       double piv = W[k * np + k];
       // uniform decision
@@ -66,14 +67,16 @@ __global__ __launch_bounds__(1024) void k_chol(const CholJob* __restrict__ jobs,
         else { W[k * np + k] = d; xd[k] *= rd; }
       }
       __syncthreads();
-      const int rows = N - k - 1;
-      const int cnt = rows * N;
-      for (int e = tid; e < cnt; e += 1024) {
-        int i = k + 1 + e / N, j = e % N;
-        double f = W[k * np + i];
-        if (j >= i) W[i * np + j] -= f * W[k * np + j];
-        else if (j < k) W[i * np + j] -= f * W[k * np + j];
-        else if (j == k) W[i * np + j] -= f * xd[k];
+      const double xk = xd[k];
+      for (int i = k + 1 + ty; i < N; i += 32) {
+        const double f = W[k * np + i];
+        double* Wi = W + i * np;
+        const double* Wk = W + k * np;
+        for (int j = tx; j < N; j += 32) {
+          if (j >= i) Wi[j] -= f * Wk[j];
+          else if (j < k) Wi[j] -= f * Wk[j];
+          else if (j == k) Wi[j] -= f * xk;
+        }
       }
       __syncthreads();
     }
@@ -125,14 +128,25 @@ __device__ int jacobi_os(double* A, int lda, int nr, int nd, int nc, double tol,
   const int tid = threadIdx.x, wave = tid >> 6, ln = tid & 63;
   const int nc2 = nc + (nc & 1);
   if (nc < 2) return 0;
-  constexpr int PB = 4;   // pairs per batch per wave
+  constexpr int PB = 4;   // pairs per batch per wave (with 16 waves: 64 pairs per pass)
   for (int sweep = 0; sweep < maxsweep; ++sweep) {
     // column norms over the dot rows, and the skip threshold
-    for (int c = wave; c < nc; c += 16) {
-      double s = 0.0;
-      for (int i = ln; i < nd; i += 64) { double v = A[(int64_t)c * lda + i]; s += v * v; }
-      s = wave_sum(s);
-      if (ln == 0) nrm2[c] = s;
+    for (int c0 = wave * 4; c0 < nc; c0 += 64) {
+      double sq[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        double s = 0.0;
+        int c = c0 + b;
+        if (c < nc)
+          for (int i = ln; i < nd; i += 64) { double v = A[(int64_t)c * lda + i]; s += v * v; }
+        sq[b] = s;
+      }
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) sq[b] += __shfl_xor(sq[b], o, 64);
+      if (ln == 0)
+        for (int b = 0; b < 4; ++b) if (c0 + b < nc) nrm2[c0 + b] = sq[b];
     }
     if (tid == 0) scratch[0] = 0;
     __syncthreads();
@@ -174,9 +188,11 @@ __device__ int jacobi_os(double* A, int lda, int nr, int nd, int nc, double tol,
             aq[b][e] = ok ? A[(int64_t)q * lda + i] : 0.0;
           }
         }
+        // the 3*PB inner products of the batch, reduced together so that the
+        // shuffle latencies overlap
+        double red[3 * PB];
 #pragma unroll
         for (int b = 0; b < PB; ++b) {
-          if (P_[b] < 0) continue;
           double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
           for (int e = 0; e < EPL; ++e) {
@@ -185,7 +201,16 @@ __device__ int jacobi_os(double* A, int lda, int nr, int nd, int nc, double tol,
               al += ap[b][e] * ap[b][e]; be += aq[b][e] * aq[b][e]; ga += ap[b][e] * aq[b][e];
             }
           }
-          al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
+          red[3 * b] = al; red[3 * b + 1] = be; red[3 * b + 2] = ga;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+          for (int x = 0; x < 3 * PB; ++x) red[x] += __shfl_xor(red[x], o, 64);
+#pragma unroll
+        for (int b = 0; b < PB; ++b) {
+          if (P_[b] < 0) continue;
+          const double al = red[3 * b], be = red[3 * b + 1], ga = red[3 * b + 2];
           if (!(al > 0.0) || !(be > 0.0)) continue;
           if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
           double zeta = (be - al) / (2.0 * ga);

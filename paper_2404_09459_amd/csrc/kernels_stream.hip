@@ -1,0 +1,382 @@
+// Streaming kernels of the basis extraction: every pass over G.
+//
+//  k_gw  : Y = G W          (the sketch G Omega and the power step G W)
+//  k_gtq : partial Q^T G    (the power step G^T Q and the projection B = Q^T G
+//                            of Algorithm 2, one row chunk of G per job)
+//  k_cvt : fp32 -> bf16 copy of a small operand (mixed precision)
+//
+// Design: one wave per workgroup, no LDS and no barriers.  G is streamed from
+// HBM straight into registers (each lane a contiguous run of k values); the
+// small operand (W^T or Q^T, a few MB, L2-resident) is read as MFMA fragments
+// directly from L2 (each lane one contiguous 16-32 byte run).  Both operands
+// use the same k assignment (lane group g = lane/16 owns k = g*KL .. g*KL+KL-1
+// of each KS-wide step), so no operand is ever transposed.
+#include "common.hpp"
+#include "gemm.hpp"
+#include "jobs.hpp"
+#include "launch.hpp"
+
+namespace rg {
+
+template <int P> struct St;
+template <> struct St<P64> { using cT = double; using acc = d4; static constexpr int KL = 4, KPI = 1; };
+template <> struct St<P32> { using cT = float;  using acc = f4; static constexpr int KL = 4, KPI = 1; };
+template <> struct St<PBF> { using cT = __bf16; using acc = f4; static constexpr int KL = 8, KPI = 8; };
+
+template <int P>
+__device__ inline void mma_run(typename St<P>::acc& c, const typename St<P>::cT* a,
+                               const typename St<P>::cT* b) {
+  if constexpr (P == PBF) {
+    bf8 va, vb;
+    __builtin_memcpy(&va, a, 16);
+    __builtin_memcpy(&vb, b, 16);
+    c = mmabf(va, vb, c);
+  } else {
+#pragma unroll
+    for (int s = 0; s < 4; ++s) mma_step<P>(c, a + s, b + s);
+  }
+}
+
+template <int P, typename TS>
+__device__ inline typename St<P>::cT to_c(TS x) {
+  if constexpr (P == PBF) return (__bf16)(float)x;
+  else return (typename St<P>::cT)x;
+}
+
+// ------------------------------------------------------ memory helpers --
+// G is read through a raw buffer resource: offsets past num_records return
+// zero (no guards in the loops, no alignment requirement beyond the element
+// size).  Small operands are read through global-address-space pointers.
+typedef unsigned int u4v __attribute__((ext_vector_type(4)));
+typedef unsigned int u2v __attribute__((ext_vector_type(2)));
+template <typename T> using gptr = const T __attribute__((address_space(1)))*;
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void* base, int64_t bytes) {
+  if (bytes > 0x7ffffff0LL) bytes = 0x7ffffff0LL;
+  if (bytes < 0) bytes = 0;
+  return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)bytes, 0x00020000);
+}
+__device__ inline u4v bload16(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0);
+}
+__device__ inline u2v bload8(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0);
+}
+
+// N contiguous elements of G (type TS) at byte offset off, as float/double
+template <typename TS, typename TD, int N>
+__device__ inline void gload(TD* out, __amdgpu_buffer_rsrc_t r, int off) {
+  if constexpr (sizeof(TS) == 4) {
+    static_assert(N % 2 == 0, "");
+    if constexpr (N % 4 == 0) {
+#pragma unroll
+      for (int v = 0; v < N / 4; ++v) {
+        f4 t = __builtin_bit_cast(f4, bload16(r, off + 16 * v));
+        out[4 * v] = (TD)t[0]; out[4 * v + 1] = (TD)t[1]; out[4 * v + 2] = (TD)t[2]; out[4 * v + 3] = (TD)t[3];
+      }
+    } else {
+#pragma unroll
+      for (int v = 0; v < N / 2; ++v) {
+        f2 t = __builtin_bit_cast(f2, bload8(r, off + 8 * v));
+        out[2 * v] = (TD)t[0]; out[2 * v + 1] = (TD)t[1];
+      }
+    }
+  } else {
+    static_assert(N % 2 == 0, "");
+#pragma unroll
+    for (int v = 0; v < N / 2; ++v) {
+      d2 t = __builtin_bit_cast(d2, bload16(r, off + 16 * v));
+      out[2 * v] = (TD)t[0]; out[2 * v + 1] = (TD)t[1];
+    }
+  }
+}
+
+// KL contiguous elements of a small operand (compute type), in bounds
+template <int P>
+__device__ inline void sload(typename St<P>::cT* out, const typename St<P>::cT* p) {
+  if constexpr (P == P64) {
+    d2 a = *(gptr<d2>)p, b = *(gptr<d2>)(p + 2);
+    out[0] = a[0]; out[1] = a[1]; out[2] = b[0]; out[3] = b[1];
+  } else if constexpr (P == P32) {
+    f4 a = *(gptr<f4>)p;
+    out[0] = a[0]; out[1] = a[1]; out[2] = a[2]; out[3] = a[3];
+  } else {
+    u4v v = *(gptr<u4v>)p;
+    __builtin_memcpy(out, &v, 16);
+  }
+}
+
+// ------------------------------------------------------------------ k_gw --
+// Job: Yt (L x ldy) = (G W)^T with W given as Wt (L x ldw, compute type,
+// zero beyond column n).  Wave tile: RT*16 rows of G, all CT column tiles.
+// NB-deep register pipeline (loads issued NB-1 steps ahead).
+template <int P, typename TG, int RT, int CT, int NB = 3>
+__global__ __launch_bounds__(64) void k_gw(const NnJob* __restrict__ jobs, const int* __restrict__ pre,
+                                           int nj) {
+  using cT = typename St<P>::cT;
+  using acc_t = typename St<P>::acc;
+  using aT = typename std::conditional<P == P64, double, float>::type;
+  constexpr int KL = St<P>::KL, KS = 4 * KL;
+  const int jb = find_side(pre, nj, blockIdx.x);
+  const NnJob J = jobs[jb];
+  const int tile = blockIdx.x - pre[jb];
+  const int ln = threadIdx.x, g = ln >> 4, li = ln & 15;
+  const int row0 = tile * 16 * RT;
+  const int ctn = J.L >> 4;
+  const int esz = (int)sizeof(TG);
+  const __amdgpu_buffer_rsrc_t rs =
+      make_rsrc((const char*)J.G + (int64_t)row0 * J.ldg * esz, (int64_t)(J.m - row0) * J.ldg * esz);
+  int roff[RT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a) roff[a] = (a * 16 + li) * (int)J.ldg * esz;
+  const cT* wrow[CT];
+#pragma unroll
+  for (int b = 0; b < CT; ++b) wrow[b] = (const cT*)J.Wt + (int64_t)(b * 16 + li) * J.ldw;
+
+  acc_t acc[RT][CT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) acc[a][b] = acc_t{0, 0, 0, 0};
+
+  aT ga[NB][RT][KL];
+  cT wb[NB][CT][KL];
+  const int nsteps = (J.n + KS - 1) / KS;
+  auto load = [&](int buf, int st) {
+    const int k = st * KS + g * KL;
+#pragma unroll
+    for (int a = 0; a < RT; ++a) gload<TG, aT, KL>(ga[buf][a], rs, roff[a] + k * esz);
+#pragma unroll
+    for (int b = 0; b < CT; ++b)
+      if (b < ctn) sload<P>(wb[buf][b], wrow[b] + k);
+  };
+#pragma unroll
+  for (int b = 0; b < NB - 1; ++b)
+    if (b < nsteps) load(b, b);
+  for (int st0 = 0; st0 < nsteps; st0 += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int st = st0 + u;
+      if (st >= nsteps) break;
+      if (st + NB - 1 < nsteps) load((u + NB - 1) % NB, st + NB - 1);
+      cT av[RT][KL];
+      const int k = st * KS + g * KL;
+      const bool last = (st + 1) * KS > J.n;      // wave-uniform
+#pragma unroll
+      for (int a = 0; a < RT; ++a)
+#pragma unroll
+        for (int e = 0; e < KL; ++e) {
+          aT v = ga[u][a][e];
+          if (last && k + e >= J.n) v = (aT)0;     // user padding between rows
+          av[a][e] = to_c<P>(v);
+        }
+#pragma unroll
+      for (int b = 0; b < CT; ++b)
+        if (b < ctn)
+#pragma unroll
+          for (int a = 0; a < RT; ++a) mma_run<P>(acc[a][b], av[a], wb[u][b]);
+    }
+  }
+  // lane holds Y[row0 + a*16 + out_row(g, ii)][b*16 + li]
+  typedef typename std::conditional<P == P64, double, float>::type yT;
+  yT* Yt = (yT*)J.Yt;
+#pragma unroll
+  for (int b = 0; b < CT; ++b) {
+    if (b < ctn) {
+      yT* dst = Yt + (int64_t)(b * 16 + li) * J.ldy;
+#pragma unroll
+      for (int a = 0; a < RT; ++a) {
+        const int rb = row0 + a * 16;
+        if constexpr (P != P64) {
+          const int r = rb + 4 * g;     // out_row = 4g + ii: four consecutive rows
+          if (r + 3 < J.m) {
+            *(f4*)(dst + r) = f4{acc[a][b][0], acc[a][b][1], acc[a][b][2], acc[a][b][3]};
+          } else {
+#pragma unroll
+            for (int ii = 0; ii < 4; ++ii) if (r + ii < J.m) dst[r + ii] = acc[a][b][ii];
+          }
+        } else {
+#pragma unroll
+          for (int ii = 0; ii < 4; ++ii) {
+            const int r = rb + out_row<P>(g, ii);
+            if (r < J.m) dst[r] = acc[a][b][ii];
+          }
+        }
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------- k_gtq --
+// Job (AbJob): D (rows x J, partial, ldd) = A (rows x K) B (K x J): A = Q^T
+// columns of this row chunk in the compute type (lda, zero beyond m), B = the
+// row chunk of G (ldb, K rows; rows past K read as zero through the buffer
+// resource).  Wave tile: 16*JS columns of G (lane li owns JS consecutive
+// columns, one per MFMA sub-tile), all CT row tiles of D.
+template <int P, typename TG, int CT, int JS, int NB = 3>
+__global__ __launch_bounds__(64) void k_gtq(const AbJob* __restrict__ jobs, const int* __restrict__ pre,
+                                            int nj) {
+  using cT = typename St<P>::cT;
+  using acc_t = typename St<P>::acc;
+  using bT = typename std::conditional<P == P64, double, float>::type;
+  constexpr int KL = St<P>::KL, KS = 4 * KL;
+  const int jb = find_side(pre, nj, blockIdx.x);
+  const AbJob J = jobs[jb];
+  const int tile = blockIdx.x - pre[jb];
+  const int ln = threadIdx.x, g = ln >> 4, li = ln & 15;
+  const int col0 = tile * 16 * JS + JS * li;
+  const int ctn = (J.rows + 15) >> 4;
+  const int esz = (int)sizeof(TG);
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(J.B, (int64_t)J.K * J.ldb * esz);
+  const int coff = (col0 < J.J ? col0 : 0) * esz;
+  bool cok[JS];
+#pragma unroll
+  for (int q = 0; q < JS; ++q) cok[q] = col0 + q < J.J;
+  const cT* arow[CT];
+#pragma unroll
+  for (int b = 0; b < CT; ++b) arow[b] = (const cT*)J.A + (int64_t)(b * 16 + li) * J.lda;
+
+  acc_t acc[CT][JS];
+#pragma unroll
+  for (int a = 0; a < CT; ++a)
+#pragma unroll
+    for (int q = 0; q < JS; ++q) acc[a][q] = acc_t{0, 0, 0, 0};
+
+  bT gb[NB][KL][JS];
+  cT af[NB][CT][KL];
+  const int nsteps = (J.K + KS - 1) / KS;
+  auto load = [&](int buf, int st) {
+    const int k = st * KS + g * KL;
+#pragma unroll
+    for (int e = 0; e < KL; ++e) gload<TG, bT, JS>(gb[buf][e], rs, (k + e) * (int)J.ldb * esz + coff);
+#pragma unroll
+    for (int b = 0; b < CT; ++b)
+      if (b < ctn) sload<P>(af[buf][b], arow[b] + k);
+  };
+#pragma unroll
+  for (int b = 0; b < NB - 1; ++b)
+    if (b < nsteps) load(b, b);
+  for (int st0 = 0; st0 < nsteps; st0 += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int st = st0 + u;
+      if (st >= nsteps) break;
+      if (st + NB - 1 < nsteps) load((u + NB - 1) % NB, st + NB - 1);
+      cT bv[JS][KL];
+#pragma unroll
+      for (int e = 0; e < KL; ++e)
+#pragma unroll
+        for (int q = 0; q < JS; ++q) bv[q][e] = to_c<P>(cok[q] ? gb[u][e][q] : (bT)0);
+#pragma unroll
+      for (int b = 0; b < CT; ++b)
+        if (b < ctn)
+#pragma unroll
+          for (int q = 0; q < JS; ++q) mma_run<P>(acc[b][q], af[u][b], bv[q]);
+    }
+  }
+  typedef typename std::conditional<P == P64, double, float>::type dT;
+  dT* D = (dT*)J.D;
+#pragma unroll
+  for (int b = 0; b < CT; ++b) {
+    if (b < ctn) {
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int c = b * 16 + out_row<P>(g, ii);
+        if (c < J.rows) {
+          dT* dst = D + (int64_t)c * J.ldd;
+          if constexpr (JS == 4 && sizeof(dT) == 4) {
+            if (col0 + 4 <= J.J) {
+              *(f4*)(dst + col0) = f4{(float)acc[b][0][ii], (float)acc[b][1][ii], (float)acc[b][2][ii],
+                                      (float)acc[b][3][ii]};
+              continue;
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < JS; ++q)
+            if (col0 + q < J.J) dst[col0 + q] = (dT)acc[b][q][ii];
+        }
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------------------- k_cvt --
+// fp32 -> bf16 copy of rows x cols (ld in elements for both)
+struct CvtJob { const float* src; __bf16* dst; int64_t ld; int32_t rows, cols; };
+
+__global__ __launch_bounds__(256) void k_cvt(const CvtJob* __restrict__ jobs, const int* __restrict__ pre,
+                                             int nj) {
+  const int jb = find_side(pre, nj, blockIdx.x);
+  const CvtJob J = jobs[jb];
+  const int64_t i = ((int64_t)(blockIdx.x - pre[jb]) * 256 + threadIdx.x) * 4;
+  const int64_t tot = (int64_t)J.rows * J.ld;
+  if (i >= tot) return;
+  if (i + 4 <= tot) {
+    f4 v = *(const f4*)(J.src + i);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) J.dst[i + e] = (__bf16)v[e];
+  } else {
+    for (int64_t e = i; e < tot; ++e) J.dst[e] = (__bf16)J.src[e];
+  }
+}
+
+// ---------------------------------------------------------------- launch --
+template <int P, typename TG, int RT>
+static void gw_ct(int ct, const NnJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  switch (ct) {
+    case 1: hipLaunchKernelGGL((k_gw<P, TG, RT, 1>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
+    case 2: hipLaunchKernelGGL((k_gw<P, TG, RT, 2>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
+    case 4: hipLaunchKernelGGL((k_gw<P, TG, RT, 4>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
+    case 8: hipLaunchKernelGGL((k_gw<P, TG, RT, 8>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
+    default: hipLaunchKernelGGL((k_gw<P, TG, RT, 16>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
+  }
+}
+
+void launch_gw(int prec, int gdt, int rt, int ct, const NnJob* j, const int* pre, int nj, int tiles,
+               hipStream_t st) {
+  if (prec == P64) {
+    if (gdt == G_F64) gw_ct<P64, double, 1>(ct, j, pre, nj, tiles, st);
+    else gw_ct<P64, float, 1>(ct, j, pre, nj, tiles, st);
+  } else if (prec == P32) {
+    if (gdt == G_F64) gw_ct<P32, double, 1>(ct, j, pre, nj, tiles, st);
+    else if (rt == 4) gw_ct<P32, float, 4>(ct, j, pre, nj, tiles, st);
+    else gw_ct<P32, float, 1>(ct, j, pre, nj, tiles, st);
+  } else {
+    if (gdt == G_F64) gw_ct<PBF, double, 1>(ct, j, pre, nj, tiles, st);
+    else if (rt == 4) gw_ct<PBF, float, 4>(ct, j, pre, nj, tiles, st);
+    else gw_ct<PBF, float, 1>(ct, j, pre, nj, tiles, st);
+  }
+}
+
+template <int P, typename TG, int JS>
+static void gtq_ct(int ct, const AbJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  switch (ct) {
+    case 1: hipLaunchKernelGGL((k_gtq<P, TG, 1, JS>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
+    case 2: hipLaunchKernelGGL((k_gtq<P, TG, 2, JS>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
+    case 4: hipLaunchKernelGGL((k_gtq<P, TG, 4, JS>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
+    case 8: hipLaunchKernelGGL((k_gtq<P, TG, 8, JS>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
+    default: hipLaunchKernelGGL((k_gtq<P, TG, 16, JS>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
+  }
+}
+
+void launch_gtq(int prec, int gdt, int ct, int js, const AbJob* j, const int* pre, int nj, int tiles,
+                hipStream_t st) {
+  if (prec == P64) {
+    if (gdt == G_F64) gtq_ct<P64, double, 2>(ct, j, pre, nj, tiles, st);
+    else gtq_ct<P64, float, 2>(ct, j, pre, nj, tiles, st);
+  } else if (prec == P32) {
+    if (gdt == G_F64) gtq_ct<P32, double, 2>(ct, j, pre, nj, tiles, st);
+    else if (js == 4) gtq_ct<P32, float, 4>(ct, j, pre, nj, tiles, st);
+    else gtq_ct<P32, float, 2>(ct, j, pre, nj, tiles, st);
+  } else {
+    if (gdt == G_F64) gtq_ct<PBF, double, 2>(ct, j, pre, nj, tiles, st);
+    else if (js == 4) gtq_ct<PBF, float, 4>(ct, j, pre, nj, tiles, st);
+    else gtq_ct<PBF, float, 2>(ct, j, pre, nj, tiles, st);
+  }
+}
+
+void launch_cvt(const void* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  hipLaunchKernelGGL(k_cvt, dim3(tiles), dim3(256), 0, st, (const CvtJob*)j, pre, nj);
+}
+
+}  // namespace rg

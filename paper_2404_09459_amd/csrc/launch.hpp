@@ -8,8 +8,6 @@ namespace rg {
 
 void launch_zero(void* p, int64_t bytes, hipStream_t st);
 void launch_gen(bool f64, const GenJob* j, const int* pre, int nj, int tiles, hipStream_t st);
-void launch_nn(int prec, int gdt, int rt, int ct, const NnJob* j, const int* pre, int nj,
-               int tiles, hipStream_t st);
 void launch_ab(int prec, int ta, int tb, int td, int ct, int js, const AbJob* j, const int* pre,
                int nj, int tiles, hipStream_t st);
 void launch_gram(int tx, const GramJob* j, const int* pre, int nj, int tiles, hipStream_t st);
@@ -20,4 +18,12 @@ void launch_small(const SmallJob* j, int nj, hipStream_t st);
 void launch_sign(const SignJob* j, const int* pre, int nj, int tiles, hipStream_t st);
 void launch_scale(const SignJob* j, const int* pre, int nj, int tiles, hipStream_t st);
 
+}  // namespace rg
+
+namespace rg {
+void launch_gw(int prec, int gdt, int rt, int ct, const NnJob* j, const int* pre, int nj, int tiles,
+               hipStream_t st);
+void launch_gtq(int prec, int gdt, int ct, int js, const AbJob* j, const int* pre, int nj, int tiles,
+                hipStream_t st);
+void launch_cvt(const void* j, const int* pre, int nj, int tiles, hipStream_t st);
 }  // namespace rg
