@@ -188,7 +188,7 @@ int layout(rgsvd_plan_s* P) {
     pr.mpart = take((size_t)pr.gch * pr.Npad * pr.Npad * 8);
     pr.M = take((size_t)pr.Npad * pr.Npad * 8);
     size_t N = pr.N, t = pr.t;
-    pr.work = take((N * N + N * t) * 8);
+    pr.work = take((N * t + t * t + N * N) * 8);
     pr.sigma = take(N * 8);
     pr.X1t = take(t * pr.l1 * 8);
     pr.X2t = take(t * pr.l2 * 8);
@@ -198,7 +198,7 @@ int layout(rgsvd_plan_s* P) {
     pr.alpha = take(t * 8 * 5 + 16);   // alpha, beta, theta, P1, P2, D when not given
   }
   P->nchol_slots = 0;
-  if (P->npadG > CHOL_LDS_MAX) P->nchol_slots = nsides;
+  if (P->npadG > 128) P->nchol_slots = nsides;
   P->off_chol = take((size_t)std::max(1, P->nchol_slots) * (CHOL_MAX * CHOL_MAX + 2 * CHOL_MAX) * 8);
   // job area: generous bound
   size_t per_side = 64 * 1024 + (size_t)(P->sides.empty() ? 0 : P->sides[0].nchunk) * 256;

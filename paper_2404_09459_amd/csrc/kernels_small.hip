@@ -17,19 +17,130 @@ namespace rg {
 
 // ---------------------------------------------------------------- k_chol --
 // Row elimination on [A | I]: after N steps the left block is R (A = R^T R)
-// and the right block is R^{-T}.  The working array keeps R's upper triangle
-// and R^{-T}'s strict lower triangle in one npad x npad array; R^{-T}'s
-// diagonal is kept separately.  On a non-positive (or tiny relative) pivot
-// the Gram is shifted by s I and the factorisation restarted.
-__global__ __launch_bounds__(1024) void k_chol(const CholJob* __restrict__ jobs, int nj,
-                                               double* __restrict__ gscratch) {
-  extern __shared__ double lds[];
-  const CholJob J = jobs[blockIdx.x];
+// and the right block is R^{-T}.  One npad x npad working array keeps R's
+// upper triangle and R^{-T}'s strict lower triangle; R^{-T}'s diagonal is
+// kept separately.  On a non-positive (or tiny relative) pivot the Gram is
+// shifted by s I and the factorisation restarted.
+//
+// npad <= 128: the working array lives in registers, 32 x 32 threads owning
+// a block-cyclic 4 x 4 set of entries each, so a step only broadcasts the
+// pivot row through LDS (each thread reads the values of its own rows and
+// columns).  Larger orders use a global-memory array.
+__device__ void chol_regs(const CholJob& J, double* lds) {
   const int N = J.N, np = J.npad;
-  const bool in_lds = (np <= CHOL_LDS_MAX);
-  double* W = in_lds ? lds : gscratch + (int64_t)blockIdx.x * (CHOL_MAX * CHOL_MAX + 2 * CHOL_MAX);
-  double* xd = in_lds ? lds + np * np : W + (int64_t)np * np;
-  double* d0 = xd + np;
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  double* rowk = lds;            // scaled pivot row (np)
+  double* xd = lds + 128;        // diagonal of R^{-T} (np)
+  __shared__ double piv_s, maxd_s;
+  __shared__ int bad_s;
+  double w[4][4];
+  if (tid == 0) {
+    double md = 0.0;
+    for (int i = 0; i < N; ++i) md = fmax(md, J.gram[(int64_t)i * np + i]);
+    maxd_s = md;
+  }
+  __syncthreads();
+  const double maxdiag = maxd_s;
+  double shift = 0.0;
+  bool shifted = false;
+  for (int attempt = 0;; ++attempt) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        int i = ty + 32 * a, j = tx + 32 * b;
+        double v = 0.0;
+        if (i < N && j < N && j >= i) v = J.gram[(int64_t)i * np + j] + (i == j ? shift : 0.0);
+        w[a][b] = v;
+      }
+    for (int i = tid; i < 128; i += 1024) xd[i] = 1.0;
+    if (tid == 0) bad_s = 0;
+    __syncthreads();
+    for (int k = 0; k < N; ++k) {
+      const int ak = k >> 5, ok_ = k & 31;
+      // pivot value from its owner
+      if (ty == ok_ && tx == ok_) {
+        double pv = 0.0;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) if (a == ak && b == ak) pv = w[a][b];
+        piv_s = pv;
+      }
+      __syncthreads();
+      const double piv = piv_s;
+      const double d0k = J.gram[(int64_t)k * np + k];
+      if (!(piv > 1e-15 * d0k) || !(piv > 0.0) || !isfinite(piv)) { if (tid == 0) bad_s = 1; break; }
+      const double d = sqrt(piv), rd = 1.0 / d;
+      // owners of row k scale it and publish it
+      if (ty == ok_) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          if (a != ak) continue;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            int j = tx + 32 * b;
+            if (j < N) {
+              double v = (j == k) ? d : w[a][b] * rd;
+              w[a][b] = v;
+              rowk[j] = v;
+            }
+          }
+        }
+      }
+      if (tid == 0) xd[k] *= rd;
+      __syncthreads();
+      const double xk = xd[k];
+      double fr[4], fc[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) { int i = ty + 32 * a; fr[a] = (i < N) ? rowk[i] : 0.0; }
+#pragma unroll
+      for (int b = 0; b < 4; ++b) { int j = tx + 32 * b; fc[b] = (j < N) ? rowk[j] : 0.0; }
+#pragma unroll
+      for (int a = 0; a < 4; ++a) {
+        const int i = ty + 32 * a;
+        if (i <= k || i >= N) continue;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int j = tx + 32 * b;
+          if (j >= N) continue;
+          if (j >= i) w[a][b] -= fr[a] * fc[b];
+          else if (j < k) w[a][b] -= fr[a] * fc[b];
+          else if (j == k) w[a][b] -= fr[a] * xk;
+        }
+      }
+    }
+    __syncthreads();
+    if (!bad_s) break;
+    if (attempt >= 8 || !(maxdiag > 0.0) || !isfinite(maxdiag)) {
+      for (int e = tid; e < np * np; e += 1024) J.sinv[e] = 0.0;
+      if (tid == 0 && J.info)
+        atomicOr(J.info + 4, isfinite(maxdiag) ? (1 << J.flagbit) | FLAG_CHOL_FAIL : FLAG_NONFINITE);
+      return;
+    }
+    shift = (shift == 0.0) ? 1e-14 * maxdiag * (double)N : shift * 100.0;
+    shifted = true;
+    __syncthreads();
+  }
+  // write R^{-T} (strict lower from the array, diagonal from xd), zero elsewhere
+  for (int e = tid; e < np * np; e += 1024) J.sinv[e] = 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int i = ty + 32 * a, j = tx + 32 * b;
+      if (i < N && j < N) {
+        if (j < i) J.sinv[(int64_t)i * np + j] = w[a][b];
+        else if (j == i) J.sinv[(int64_t)i * np + j] = xd[i];
+        if (J.r) J.r[(int64_t)i * np + j] = (j >= i) ? w[a][b] : 0.0;
+      }
+    }
+  if (tid == 0 && shifted && J.info) atomicOr(J.info + 4, 1 << J.flagbit);
+}
+
+__device__ void chol_global(const CholJob& J, double* W, double* xd, double* d0) {
+  const int N = J.N, np = J.npad;
   __shared__ int bad;
   __shared__ double shift;
   __shared__ int shifted;
@@ -54,14 +165,12 @@ __global__ __launch_bounds__(1024) void k_chol(const CholJob* __restrict__ jobs,
     }
     if (tid == 0) bad = 0;
     __syncthreads();
-    const int tx = tid & 31, ty = tid >> 5;   // 32 x 32 thread grid
+    const int tx = tid & 31, ty = tid >> 5;
     for (int k = 0; k < N; ++k) {
       double piv = W[k * np + k];
-      // uniform decision
       bool brk = !(piv > 1e-15 * d0[k]) || !(piv > 0.0) || !isfinite(piv);
       if (brk) { if (tid == 0) bad = 1; break; }
       double d = sqrt(piv), rd = 1.0 / d;
-      // scale row k (R's row k and R^{-T}'s row k)
       for (int j = tid; j < N; j += 1024) {
         if (j != k) W[k * np + j] *= rd;
         else { W[k * np + k] = d; xd[k] *= rd; }
@@ -84,11 +193,9 @@ __global__ __launch_bounds__(1024) void k_chol(const CholJob* __restrict__ jobs,
     if (!bad) break;
     ++attempt;
     if (attempt > 8 || !(maxdiag > 0.0) || !isfinite(maxdiag)) {
-      // give up: zero inverse, flag
       for (int e = tid; e < np * np; e += 1024) J.sinv[e] = 0.0;
-      if (tid == 0 && J.info) {
+      if (tid == 0 && J.info)
         atomicOr(J.info + 4, isfinite(maxdiag) ? (1 << J.flagbit) | FLAG_CHOL_FAIL : FLAG_NONFINITE);
-      }
       return;
     }
     if (tid == 0) {
@@ -110,132 +217,145 @@ __global__ __launch_bounds__(1024) void k_chol(const CholJob* __restrict__ jobs,
   if (tid == 0 && shifted && J.info) atomicOr(J.info + 4, 1 << J.flagbit);
 }
 
+__global__ __launch_bounds__(1024) void k_chol(const CholJob* __restrict__ jobs, int nj,
+                                               double* __restrict__ gscratch) {
+  __shared__ double lds[256];
+  const CholJob J = jobs[blockIdx.x];
+  if (J.npad <= 128) {
+    chol_regs(J, lds);
+  } else {
+    double* W = gscratch + (int64_t)blockIdx.x * (CHOL_MAX * CHOL_MAX + 2 * CHOL_MAX);
+    chol_global(J, W, W + (int64_t)J.npad * J.npad, W + (int64_t)J.npad * J.npad + J.npad);
+  }
+}
+
 // ------------------------------------------------------ one-sided Jacobi --
-// Orthogonalises the columns of A (column-major, lda; nc columns) by plane
-// rotations (Hestenes).  Inner products use rows [0, nd); rotations are
-// applied to rows [0, nr) (nr >= nd), so rows nd..nr-1 just follow along.
-// Parallel round-robin ordering: each round pairs every column once and the
-// 16 waves share the round's pairs; a wave loads all of its pairs' columns
-// before rotating so that global-memory latency is paid once per round.
-// topk > 0: a pair is skipped when both columns have squared norm below
-// (0.5 * topk-th largest norm)^2 (norms refreshed every sweep); at
+// Orthogonalises the nc columns of A (column-major, ld lda) by plane
+// rotations (Hestenes).  Inner products use rows [0, nd); the rotations are
+// applied to rows [0, nr) (nr >= nd).  Parallel round-robin ordering: each
+// round pairs every column once.
+//
+// G lanes hold one column pair, E = ceil(nr / G) <= 16 entries of each
+// column per lane, so a pair's three inner products reduce in log2(G)
+// shuffle steps and 1024 / G pairs rotate at once.  When A fits in the
+// LDS buffer it is copied there for all sweeps; otherwise the rounds work
+// on A in global memory.
+//
+// topk > 0: a pair is skipped when both columns have squared norm below a
+// quarter of the topk-th largest (norms refreshed every sweep); at
 // convergence the topk dominant columns are orthogonal to every other
-// column, so they span the dominant invariant subspace.
-// Returns the number of sweeps used (maxsweep + 1 when not converged).
-template <int EPL>  // elements per lane per column (nr <= 64*EPL)
-__device__ int jacobi_os(double* A, int lda, int nr, int nd, int nc, double tol, int maxsweep,
-                         int topk, double* nrm2, int* scratch, double* kth_slot) {
+// column, so they span the dominant invariant subspace.  Returns the number
+// of sweeps used (maxsweep + 1 when not converged).
+template <int G>
+__device__ __attribute__((always_inline)) inline void
+jacobi_round(double* L, int ldl, int nr, int nd, int nc, int round, double thr, const double* nrm2,
+             double tol, int* rotated) {
+  constexpr int SLOTS = 1024 / G;
+  const int tid = threadIdx.x, grp = tid / G, j = tid % G;
+  const int E = (nr + G - 1) / G;
+  const int nc2 = nc + (nc & 1), npairs = nc2 / 2;
+  bool any = false;
+  for (int p0 = 0; p0 < npairs; p0 += SLOTS) {
+    const int pi = p0 + grp;
+    int p = -1, q = -1;
+    if (pi < npairs) {
+      const int x0 = pi, x1 = nc2 - 1 - pi;
+      const int u = (x0 == 0) ? 0 : 1 + (x0 - 1 + round) % (nc2 - 1);
+      const int v = (x1 == 0) ? 0 : 1 + (x1 - 1 + round) % (nc2 - 1);
+      if (u < nc && v < nc && !(thr >= 0.0 && nrm2[u] < thr && nrm2[v] < thr)) { p = u; q = v; }
+    }
+    double x[16], y[16];
+    double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const int r = j + G * e;
+      const bool ok = p >= 0 && e < E && r < nr;
+      x[e] = ok ? L[(int64_t)p * ldl + r] : 0.0;
+      y[e] = ok ? L[(int64_t)q * ldl + r] : 0.0;
+      if (r < nd) { al += x[e] * x[e]; be += y[e] * y[e]; ga += x[e] * y[e]; }
+    }
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+      al += __shfl_xor(al, o, 64);
+      be += __shfl_xor(be, o, 64);
+      ga += __shfl_xor(ga, o, 64);
+    }
+    if (p >= 0 && al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+      const double zeta = (be - al) / (2.0 * ga);
+      const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+      const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int r = j + G * e;
+        if (e < E && r < nr) {
+          L[(int64_t)p * ldl + r] = c * x[e] - s * y[e];
+          L[(int64_t)q * ldl + r] = s * x[e] + c * y[e];
+        }
+      }
+      any = true;
+    }
+  }
+  if (any) *rotated = 1;
+}
+
+// All sweeps on W (ld ldw): LDS copy or A itself.
+template <int G>
+__device__ __attribute__((always_inline)) inline int
+jacobi_sweeps(double* W, int ldw, int nr, int nd, int nc, double tol, int maxsweep, int topk, double* nrm2,
+              int* scratch, double* kth_slot) {
   const int tid = threadIdx.x, wave = tid >> 6, ln = tid & 63;
   const int nc2 = nc + (nc & 1);
-  if (nc < 2) return 0;
-  constexpr int PB = 4;   // pairs per batch per wave (with 16 waves: 64 pairs per pass)
   for (int sweep = 0; sweep < maxsweep; ++sweep) {
-    // column norms over the dot rows, and the skip threshold
-    for (int c0 = wave * 4; c0 < nc; c0 += 64) {
-      double sq[4];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        double s = 0.0;
-        int c = c0 + b;
-        if (c < nc)
-          for (int i = ln; i < nd; i += 64) { double v = A[(int64_t)c * lda + i]; s += v * v; }
-        sq[b] = s;
-      }
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) sq[b] += __shfl_xor(sq[b], o, 64);
-      if (ln == 0)
-        for (int b = 0; b < 4; ++b) if (c0 + b < nc) nrm2[c0 + b] = sq[b];
+    for (int c = wave; c < nc; c += 16) {
+      double s = 0.0;
+      for (int i = ln; i < nd; i += 64) { const double v = W[(int64_t)c * ldw + i]; s += v * v; }
+      s = wave_sum(s);
+      if (ln == 0) nrm2[c] = s;
     }
     if (tid == 0) scratch[0] = 0;
     __syncthreads();
-    double& kth = *kth_slot;
     double thr = -1.0;
     if (topk > 0 && topk < nc) {
-      // topk-th largest squared norm: rank count (nc <= 512)
       if (tid < nc) {
-        double v = nrm2[tid];
+        const double v = nrm2[tid];
         int r = 0;
-        for (int j = 0; j < nc; ++j) { double w = nrm2[j]; r += (w > v) || (w == v && j < tid); }
-        if (r == topk - 1) kth = v;
+        for (int j2 = 0; j2 < nc; ++j2) { const double w = nrm2[j2]; r += (w > v) || (w == v && j2 < tid); }
+        if (r == topk - 1) *kth_slot = v;
       }
       __syncthreads();
-      thr = 0.25 * kth;
+      thr = 0.25 * *kth_slot;
     }
     for (int round = 0; round < nc2 - 1; ++round) {
-      const int npairs = nc2 / 2;
-      for (int pb = wave * PB; pb < npairs; pb += 16 * PB) {
-        double ap[PB][EPL], aq[PB][EPL];
-        int P_[PB], Q_[PB];
-#pragma unroll
-        for (int b = 0; b < PB; ++b) {
-          int pi = pb + b;
-          int p = -1, q = -1;
-          if (pi < npairs) {
-            int x0 = pi, x1 = nc2 - 1 - pi;
-            p = (x0 == 0) ? 0 : 1 + (x0 - 1 + round) % (nc2 - 1);
-            q = (x1 == 0) ? 0 : 1 + (x1 - 1 + round) % (nc2 - 1);
-            if (p >= nc || q >= nc) { p = -1; q = -1; }
-            else if (thr >= 0.0 && nrm2[p] < thr && nrm2[q] < thr) { p = -1; q = -1; }
-          }
-          P_[b] = p; Q_[b] = q;
-#pragma unroll
-          for (int e = 0; e < EPL; ++e) {
-            int i = ln + 64 * e;
-            bool ok = p >= 0 && i < nr;
-            ap[b][e] = ok ? A[(int64_t)p * lda + i] : 0.0;
-            aq[b][e] = ok ? A[(int64_t)q * lda + i] : 0.0;
-          }
-        }
-        // the 3*PB inner products of the batch, reduced together so that the
-        // shuffle latencies overlap
-        double red[3 * PB];
-#pragma unroll
-        for (int b = 0; b < PB; ++b) {
-          double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-          for (int e = 0; e < EPL; ++e) {
-            int i = ln + 64 * e;
-            if (i < nd) {
-              al += ap[b][e] * ap[b][e]; be += aq[b][e] * aq[b][e]; ga += ap[b][e] * aq[b][e];
-            }
-          }
-          red[3 * b] = al; red[3 * b + 1] = be; red[3 * b + 2] = ga;
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-          for (int x = 0; x < 3 * PB; ++x) red[x] += __shfl_xor(red[x], o, 64);
-#pragma unroll
-        for (int b = 0; b < PB; ++b) {
-          if (P_[b] < 0) continue;
-          const double al = red[3 * b], be = red[3 * b + 1], ga = red[3 * b + 2];
-          if (!(al > 0.0) || !(be > 0.0)) continue;
-          if (!(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
-          double zeta = (be - al) / (2.0 * ga);
-          double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
-          const int p = P_[b], q = Q_[b];
-#pragma unroll
-          for (int e = 0; e < EPL; ++e) {
-            int i = ln + 64 * e;
-            if (i < nr) {
-              double u = ap[b][e], v = aq[b][e];
-              A[(int64_t)p * lda + i] = c * u - sn * v;
-              A[(int64_t)q * lda + i] = sn * u + c * v;
-            }
-          }
-          if (ln == 0) scratch[0] = 1;
-        }
-      }
+      jacobi_round<G>(W, ldw, nr, nd, nc, round, thr, nrm2, tol, scratch);
       __syncthreads();
     }
-    int any = scratch[0];
+    const int any = scratch[0];
     __syncthreads();
     if (!any) return sweep + 1;
   }
   return maxsweep + 1;
+}
+
+template <int G>
+__device__ __attribute__((always_inline)) inline int
+jacobi_os(double* A, int lda, int nr, int nd, int nc, double tol, int maxsweep, int topk, double* nrm2,
+          int* scratch, double* kth_slot, double* lds, int cap) {
+  const int tid = threadIdx.x;
+  if (nc < 2) return 0;
+  if ((int64_t)nc * nr > cap)
+    return jacobi_sweeps<G>(A, lda, nr, nd, nc, tol, maxsweep, topk, nrm2, scratch, kth_slot);
+  for (int e = tid; e < nc * nr; e += 1024) {
+    const int c = e / nr, r = e - c * nr;
+    lds[e] = A[(int64_t)c * lda + r];
+  }
+  __syncthreads();
+  const int sw = jacobi_sweeps<G>(lds, nr, nr, nd, nc, tol, maxsweep, topk, nrm2, scratch, kth_slot);
+  for (int e = tid; e < nc * nr; e += 1024) {
+    const int c = e / nr, r = e - c * nr;
+    A[(int64_t)c * lda + r] = lds[e];
+  }
+  __syncthreads();
+  return sw;
 }
 
 // rank of key[i] among n keys, descending, ties by index (for sorting)
@@ -250,18 +370,62 @@ __device__ inline int rank_desc(const double* key, int n, int i) {
 }
 
 // --------------------------------------------------------------- k_small --
-// Per pair (one workgroup):
-//  1. diagonally pivoted Cholesky of M = B B^T: P^T M P = R^T R; the columns
-//     of F = P R^T (rows of R scattered back to M's row order) satisfy
-//     F F^T = M, and they are graded, which makes step 2 converge in few
-//     sweeps (the QR-preconditioned Jacobi of Drmac and Veselic);
-//  2. one-sided Jacobi on F: normalised columns are M's eigenvectors, their
-//     norms the singular values of B; L = the t dominant ones (N x t);
-//  3. one-sided Jacobi driven by the rows of L1 = L[:l1] and applied to whole
-//     columns of L: the result is L Y with L1 Y = X1 diag(alpha) and
-//     L2 Y = X2 diag(beta)  (the SVD of L1 in Algorithm 2 and beta from L2);
-//  4. sort by alpha, write alpha, beta, X1^T, X2^T, (L Y)^T and the
-//     comparative quantities.
+// Left-looking diagonally pivoted Cholesky of a K x K PSD matrix S (read
+// from global, ld lds_): P^T S P = R^T R.  Column k of F (K x K, column-major,
+// ld K) is row k of R scattered back to S's row order, so F F^T = S and the
+// columns of F are graded (large first).  Stops at the numerical rank;
+// returns the rank.  diag/act/frow: shared scratch of K entries.
+__device__ int pivoted_cholesky(const double* S, int64_t lds_, int K, double* F, double* diag, int* act,
+                                double* frow, int* piv_j, double* piv_d, double shift) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < K * K; e += 1024) F[e] = 0.0;
+  for (int i = tid; i < K; i += 1024) { diag[i] = S[(int64_t)i * lds_ + i] + shift; act[i] = 1; }
+  __syncthreads();
+  double dmax0 = 0.0;
+  for (int i = 0; i < K; ++i) dmax0 = fmax(dmax0, diag[i]);
+  int TPR = 1;
+  while (TPR * 2 * K <= 1024 && TPR < 16) TPR *= 2;
+  const int row = tid / TPR, part = tid % TPR;
+  int rank = 0;
+  for (int k = 0; k < K; ++k) {
+    if (tid < 64) {
+      double best = -1.0; int bj = -1;
+      for (int j = tid; j < K; j += 64)
+        if (act[j] && diag[j] > best) { best = diag[j]; bj = j; }
+      for (int o = 32; o > 0; o >>= 1) {
+        double b2 = __shfl_xor(best, o, 64);
+        int j2 = __shfl_xor(bj, o, 64);
+        if (b2 > best || (b2 == best && j2 >= 0 && (bj < 0 || j2 < bj))) { best = b2; bj = j2; }
+      }
+      if (tid == 0) { *piv_j = bj; *piv_d = best; }
+    }
+    __syncthreads();
+    const int js = *piv_j;
+    const double d = *piv_d;
+    if (js < 0 || !(d > 1e-15 * dmax0) || !(d > 0.0)) break;
+    for (int kk = tid; kk < k; kk += 1024) frow[kk] = F[(int64_t)kk * K + js];
+    __syncthreads();
+    const double sd = sqrt(d), rd = 1.0 / sd;
+    double acc = 0.0;
+    if (row < K && act[row])
+      for (int kk = part; kk < k; kk += TPR) acc += F[(int64_t)kk * K + row] * frow[kk];
+    for (int o = TPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    __syncthreads();
+    if (row < K && part == 0) {
+      double v = 0.0;
+      if (row == js) v = sd;
+      else if (act[row]) v = (S[(int64_t)row * lds_ + js] + (row == js ? shift : 0.0) - acc) * rd;
+      F[(int64_t)k * K + row] = v;
+      if (act[row] && row != js) diag[row] -= v * v;
+    }
+    if (tid == 0) act[js] = 0;
+    __syncthreads();
+    rank = k + 1;
+  }
+  __syncthreads();
+  return rank;
+}
+
 struct SmallShared {
   double keys[SMALL_MAXN];
   double diag[SMALL_MAXN];
@@ -271,73 +435,37 @@ struct SmallShared {
   int scratch[8];
   int piv_j;
   double piv_d;
+  double kth;
 };
 
-template <int EPL>
-__device__ void small_pair(const SmallJob& J, double* lds, size_t lds_doubles, SmallShared& sh) {
-  const int N = J.l1 + J.l2, t = J.t, l1 = J.l1;
+// Per pair (one workgroup):
+//  1. diagonally pivoted Cholesky of M and one-sided Jacobi on its graded
+//     factor F (pairs with a dominant column only): the t dominant
+//     eigenvectors Z of M, i.e. left singular vectors of B, and sigma_B;
+//  2. L = Z (N x t), the joint basis [L1; L2] of Algorithm 2's CS step;
+//  3. Y = eigenvectors of H = L1^T L1 (+ a tiny shift, which leaves them
+//     unchanged), again by pivoted Cholesky + Jacobi;
+//  4. L Y: alpha_i = ||L1 y_i||, beta_i = ||L2 y_i|| (beta from L2 as the
+//     column norms, never sqrt(1 - alpha^2)), X1, X2, (L Y)^T, quantities.
+__device__ __attribute__((always_inline)) inline int
+jacobi_any(double* A, int lda, int nr, int nc, double tol, int maxsweep, int topk, SmallShared& sh,
+           double* lds, int cap) {
+  return nr <= 256 ? jacobi_os<16>(A, lda, nr, nr, nc, tol, maxsweep, topk, sh.keys, sh.scratch, &sh.kth, lds, cap)
+                   : jacobi_os<32>(A, lda, nr, nr, nc, tol, maxsweep, topk, sh.keys, sh.scratch, &sh.kth, lds, cap);
+}
+
+__device__ void small_pair(const SmallJob& J, double* lds, int cap, SmallShared& sh) {
+  const int l1 = J.l1, N = J.l1 + J.l2, t = J.t;
   const int tid = threadIdx.x;
-  int* scratch = sh.scratch;
   double* keys = sh.keys;
-  double* diag = sh.diag;
   int* perm = sh.perm;
-  int* act = sh.act;
-  int& piv_j = sh.piv_j;
-  double& piv_d = sh.piv_d;
-  // storage: F (N x N) then L (N x t); LDS when they fit, else global work
-  const bool fl = (size_t)N * N <= lds_doubles;
-  double* F = fl ? lds : J.work;                    // N x N, column k = k-th pivot column
-  double* frow = sh.frow;
-  // ---- 1. left-looking diagonally pivoted Cholesky of M (read in place)
-  for (int e = tid; e < N * N; e += 1024) F[e] = 0.0;
-  for (int i = tid; i < N; i += 1024) { diag[i] = J.M[(int64_t)i * J.ldm + i]; act[i] = 1; }
-  __syncthreads();
-  double dmax0 = 0.0;
-  for (int i = 0; i < N; ++i) dmax0 = fmax(dmax0, diag[i]);
-  // rows handled by groups of TPR threads
-  int TPR = 1;
-  while (TPR * 2 * N <= 1024 && TPR < 16) TPR *= 2;
-  const int row = tid / TPR, part = tid % TPR;
-  int rank = 0;
-  for (int k = 0; k < N; ++k) {
-    if (tid < 64) {
-      double best = -1.0; int bj = -1;
-      for (int j = tid; j < N; j += 64)
-        if (act[j] && diag[j] > best) { best = diag[j]; bj = j; }
-      for (int o = 32; o > 0; o >>= 1) {
-        double b2 = __shfl_xor(best, o, 64);
-        int j2 = __shfl_xor(bj, o, 64);
-        if (b2 > best || (b2 == best && j2 >= 0 && (bj < 0 || j2 < bj))) { best = b2; bj = j2; }
-      }
-      if (tid == 0) { piv_j = bj; piv_d = best; }
-    }
-    __syncthreads();
-    const int js = piv_j;
-    const double d = piv_d;
-    if (js < 0 || !(d > 1e-15 * dmax0) || !(d > 0.0)) break;   // numerical rank reached
-    for (int kk = tid; kk < k; kk += 1024) frow[kk] = F[(int64_t)kk * N + js];
-    __syncthreads();
-    const double sd = sqrt(d), rd = 1.0 / sd;
-    // column k: (M[:, js] - F[:, :k] F[js, :k]^T) / sqrt(d) on the active rows
-    double acc = 0.0;
-    if (row < N && act[row])
-      for (int kk = part; kk < k; kk += TPR) acc += F[(int64_t)kk * N + row] * frow[kk];
-    for (int o = TPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    __syncthreads();
-    if (row < N && part == 0) {
-      double v = 0.0;
-      if (row == js) v = sd;
-      else if (act[row]) v = (J.M[(int64_t)row * J.ldm + js] - acc) * rd;
-      F[(int64_t)k * N + row] = v;
-      if (act[row] && row != js) diag[row] -= v * v;
-    }
-    if (tid == 0) act[js] = 0;
-    __syncthreads();
-    rank = k + 1;
-  }
-  __syncthreads();
-  // ---- 2. Jacobi on the rank columns of F (only pairs touching the t dominant)
-  int sw1 = jacobi_os<EPL>(F, N, N, N, rank, J.tol, J.maxsweep, t, keys, scratch, &sh.piv_d);
+  double* Lg = J.work;                            // N x t column-major
+  double* Hg = Lg + (int64_t)N * t;               // t x t
+  double* F = Hg + (int64_t)t * t;                // N x N Jacobi factor
+  // ---- 1. eigen-decomposition of M
+  int rank = pivoted_cholesky(J.M, J.ldm, N, F, sh.diag, sh.act, sh.frow, &sh.piv_j, &sh.piv_d, 0.0);
+  const int tt = t < rank ? t : rank;
+  int sw1 = jacobi_any(F, N, N, rank, J.tol, J.maxsweep, tt, sh, lds, cap);
   for (int c = tid; c < N; c += 1024) {
     double s = 0.0;
     if (c < rank)
@@ -347,56 +475,83 @@ __device__ void small_pair(const SmallJob& J, double* lds, size_t lds_doubles, S
   __syncthreads();
   for (int c = tid; c < N; c += 1024) perm[rank_desc(keys, N, c)] = c;
   __syncthreads();
-  for (int i = tid; i < N; i += 1024) J.sigma[i] = keys[perm[i]];   // singular values of B
-  // L (N x t, column-major) = normalised dominant columns, stored where it fits
-  const bool ll = (size_t)N * t <= lds_doubles;
-  double* L = ll ? (fl ? J.work : lds) : J.work + (int64_t)N * N;
-  // (when F lives in LDS, L goes to global work first, then moved below)
-  for (int e = tid; e < N * t; e += 1024) {
-    int c = e / N, r = e - c * N;
-    int src = perm[c];
-    double nv = keys[src];
-    L[e] = (c < rank && nv > 0.0) ? F[(int64_t)src * N + r] / nv : 0.0;
+  // sigma_B: t dominant singular values of B, then the tail's Frobenius norm
+  if (tid == 0) {
+    double tr = 0.0, top = 0.0;
+    for (int i = 0; i < N; ++i) tr += J.M[(int64_t)i * J.ldm + i];
+    for (int i = 0; i < t; ++i) { double v = keys[perm[i]]; top += v * v; }
+    sh.kth = sqrt(fmax(0.0, tr - top));
   }
   __syncthreads();
-  if (ll && fl) {   // move L into LDS (F no longer needed)
-    for (int e = tid; e < N * t; e += 1024) lds[e] = L[e];
-    __syncthreads();
-    L = lds;
+  for (int i = tid; i < N; i += 1024)
+    J.sigma[i] = (i < t) ? keys[perm[i]] : (i == t ? sh.kth : 0.0);
+  // ---- 2. L = normalised dominant columns of F (N x t)
+  for (int e = tid; e < N * t; e += 1024) {
+    const int c = e / N, r = e - c * N;
+    const int src = perm[c];
+    const double nv = keys[src];
+    Lg[e] = (c < tt && nv > 0.0) ? F[(int64_t)src * N + r] / nv : 0.0;
   }
-  // ---- 3. SVD of L1 driven rotations on whole columns of L
-  int sw2 = jacobi_os<EPL>(L, N, N, l1, t, J.tol, J.maxsweep, 0, keys, scratch, &sh.piv_d);
+  __syncthreads();
+  // ---- 3. H = L1^T L1 + eps I, its eigenvectors Y (F is free again)
+  for (int e = tid; e < t * t; e += 1024) {
+    const int c = e / t, c2 = e - c * t;
+    double v = 0.0;
+    for (int r = 0; r < l1; ++r) v += Lg[(int64_t)c * N + r] * Lg[(int64_t)c2 * N + r];
+    Hg[e] = v;
+  }
+  __syncthreads();
+  double* FH = F;
+  int rh = pivoted_cholesky(Hg, t, t, FH, sh.diag, sh.act, sh.frow, &sh.piv_j, &sh.piv_d, 1e-12);
+  int sw2 = jacobi_any(FH, t, t, rh, J.tol, J.maxsweep, 0, sh, lds, cap);
   for (int c = tid; c < t; c += 1024) {
     double s = 0.0;
-    for (int r = 0; r < l1; ++r) { double v = L[(int64_t)c * N + r]; s += v * v; }
+    if (c < rh)
+      for (int r = 0; r < t; ++r) { double v = FH[(int64_t)c * t + r]; s += v * v; }
     keys[c] = sqrt(s);
+  }
+  __syncthreads();
+  // ---- 4. L Y (rows of Rcoef), alpha, beta (sorted by alpha)
+  for (int e = tid; e < t * N; e += 1024) {
+    const int c = e / N, r = e - c * N;      // column c of Y, row r
+    const double nv = keys[c];
+    double v = 0.0;
+    if (c < rh && nv > 0.0) {
+      for (int k = 0; k < t; ++k) v += Lg[(int64_t)k * N + r] * FH[(int64_t)c * t + k];
+      v /= nv;
+    }
+    J.Rcoef[(int64_t)c * J.ldr + r] = v;    // unsorted for now
+  }
+  __syncthreads();
+  for (int c = tid; c < t; c += 1024) {
+    double a = 0.0, b = 0.0;
+    for (int r = 0; r < l1; ++r) { double v = J.Rcoef[(int64_t)c * J.ldr + r]; a += v * v; }
+    for (int r = l1; r < N; ++r) { double v = J.Rcoef[(int64_t)c * J.ldr + r]; b += v * v; }
+    keys[c] = sqrt(a);
+    sh.frow[c] = sqrt(b);
   }
   __syncthreads();
   for (int c = tid; c < t; c += 1024) perm[rank_desc(keys, t, c)] = c;
   __syncthreads();
-  for (int i = tid; i < t; i += 1024) J.alpha[i] = keys[perm[i]];
-  for (int i = tid; i < t; i += 1024) {
-    int src = perm[i];
-    double s = 0.0;
-    for (int r = l1; r < N; ++r) { double v = L[(int64_t)src * N + r]; s += v * v; }
-    J.beta[i] = sqrt(s);
-  }
+  for (int i = tid; i < t; i += 1024) { J.alpha[i] = keys[perm[i]]; J.beta[i] = sh.frow[perm[i]]; }
+  // reorder Rcoef rows in place through Lg (no longer needed) and build X1t, X2t
+  for (int e = tid; e < t * N; e += 1024) Lg[e] = J.Rcoef[(int64_t)(e / N) * J.ldr + (e % N)];
   __syncthreads();
   for (int e = tid; e < t * N; e += 1024) {
-    int i = e / N, r = e - i * N;
-    int src = perm[i];
-    double v = L[(int64_t)src * N + r];
+    const int i = e / N, r = e - i * N;
+    const int src = perm[i];
+    const double v = Lg[(int64_t)src * N + r];
     J.Rcoef[(int64_t)i * J.ldr + r] = v;
     if (r < l1) {
-      double a = keys[src];
+      const double a = keys[src];
       J.X1t[(int64_t)i * J.ldx1 + r] = a > 0.0 ? v / a : 0.0;
     } else {
-      double b = J.beta[i];
+      const double b = sh.frow[src];
       J.X2t[(int64_t)i * J.ldx2 + (r - l1)] = b > BETA_ZERO ? v / b : 0.0;
     }
   }
   __syncthreads();
-  // ---- 4. comparative quantities over the t pairs
+  // ---- 5. comparative quantities over the t pairs
   if (tid < 64) {
     double sa = 0.0, sb = 0.0;
     for (int i = tid; i < t; i += 64) {
@@ -432,14 +587,10 @@ __device__ void small_pair(const SmallJob& J, double* lds, size_t lds_doubles, S
   }
 }
 
-__global__ __launch_bounds__(1024) void k_small(const SmallJob* __restrict__ jobs, int nj,
-                                                size_t lds_doubles) {
+__global__ __launch_bounds__(1024) void k_small(const SmallJob* __restrict__ jobs, int nj, int cap) {
   extern __shared__ double lds[];
   __shared__ SmallShared sh;
-  const SmallJob J = jobs[blockIdx.x];
-  const int N = J.l1 + J.l2;
-  if (N <= 256) small_pair<4>(J, lds, lds_doubles, sh);
-  else small_pair<8>(J, lds, lds_doubles, sh);
+  small_pair(jobs[blockIdx.x], lds, cap, sh);
 }
 
 // ------------------------------------------------------------- k_rowsign --
@@ -484,15 +635,8 @@ __global__ __launch_bounds__(256) void k_scale_rows(const SignJob* __restrict__ 
 
 // ---------------------------------------------------------------- launch --
 void launch_chol(const CholJob* j, int nj, int npad_max, double* gscratch, hipStream_t st) {
-  static bool attr_set = false;
-  if (!attr_set) {
-    size_t maxlds = (size_t)(CHOL_LDS_MAX * CHOL_LDS_MAX + 2 * CHOL_LDS_MAX) * sizeof(double);
-    hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)maxlds);
-    attr_set = true;
-  }
-  size_t lds = 0;
-  if (npad_max <= CHOL_LDS_MAX) lds = (size_t)(npad_max * npad_max + 2 * npad_max) * sizeof(double);
-  hipLaunchKernelGGL(k_chol, dim3(nj), dim3(1024), lds, st, j, nj, gscratch);
+  (void)npad_max;
+  hipLaunchKernelGGL(k_chol, dim3(nj), dim3(1024), 0, st, j, nj, gscratch);
 }
 
 void launch_small(const SmallJob* j, int nj, hipStream_t st) {
@@ -502,7 +646,7 @@ void launch_small(const SmallJob* j, int nj, hipStream_t st) {
     hipFuncSetAttribute((const void*)k_small, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_small, dim3(nj), dim3(1024), bytes, st, j, nj, bytes / sizeof(double));
+  hipLaunchKernelGGL(k_small, dim3(nj), dim3(1024), bytes, st, j, nj, (int)(bytes / sizeof(double)));
 }
 
 void launch_sign(const SignJob* j, const int* pre, int nj, int tiles, hipStream_t st) {

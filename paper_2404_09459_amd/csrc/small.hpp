@@ -8,7 +8,7 @@ constexpr int CHOL_LDS_MAX = 128;   // Gram orders kept in LDS by k_chol
 constexpr int CHOL_MAX = 256;       // largest padded Gram order
 constexpr int SMALL_MAXN = 512;     // largest l1 + l2 of the compressed pair
 constexpr double BETA_ZERO = 1e-14;
-constexpr size_t SMALL_LDS_BYTES = 128 * 1024;   // dynamic LDS of k_small (columns that fit)
+constexpr size_t SMALL_LDS_BYTES = 80000;   // dynamic LDS of k_small: Jacobi factors up to 10000 entries
 
 // flag bits of info[4] (same values as the public header)
 constexpr int FLAG_CHOL_FAIL = 0x4;
@@ -18,12 +18,13 @@ constexpr int FLAG_BETA_ZERO = 0x20;
 constexpr int FLAG_ALPHA_ZERO = 0x40;
 constexpr int FLAG_NONFINITE = 0x80;
 
-// One compressed pair: M = B B^T (N x N, N = l1 + l2) -> alpha, beta, ...
+// One compressed pair: M = B B^T (N x N, ldm), the Gram of the stacked
+// compressed pair B = [Q1^T G1; Q2^T G2], N = l1 + l2.
 struct SmallJob {
   const double* M; int64_t ldm;
   int32_t l1, l2, t, maxsweep;
   double tol;
-  double* work;                     // 2*N*N + N*t doubles
+  double* work;                     // N*t (L) + t*t (H) + N*N (Jacobi factor) doubles
   double* sigma;                    // N
   double *alpha, *beta, *theta, *P1, *P2, *D;
   double* X1t; int64_t ldx1;        // t x l1
