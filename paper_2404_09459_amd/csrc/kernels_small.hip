@@ -235,8 +235,8 @@ __global__ __launch_bounds__(1024) void k_chol(const CholJob* __restrict__ jobs,
 // applied to rows [0, nr) (nr >= nd).  Parallel round-robin ordering: each
 // round pairs every column once.
 //
-// G lanes hold one column pair, E = ceil(nr / G) <= 16 entries of each
-// column per lane, so a pair's three inner products reduce in log2(G)
+// G lanes hold one column pair, EM >= nr / G entries of each column per
+// lane, so a pair's three inner products reduce in log2(G)
 // shuffle steps and 1024 / G pairs rotate at once.  When A fits in the
 // LDS buffer it is copied there for all sweeps; otherwise the rounds work
 // on A in global memory.
@@ -246,32 +246,36 @@ __global__ __launch_bounds__(1024) void k_chol(const CholJob* __restrict__ jobs,
 // convergence the topk dominant columns are orthogonal to every other
 // column, so they span the dominant invariant subspace.  Returns the number
 // of sweeps used (maxsweep + 1 when not converged).
-template <int G>
+template <int G, int EM>
 __device__ __attribute__((always_inline)) inline void
 jacobi_round(double* L, int ldl, int nr, int nd, int nc, int round, double thr, const double* nrm2,
              double tol, int* rotated) {
   constexpr int SLOTS = 1024 / G;
   const int tid = threadIdx.x, grp = tid / G, j = tid % G;
-  const int E = (nr + G - 1) / G;
-  const int nc2 = nc + (nc & 1), npairs = nc2 / 2;
+  const int nc2 = nc + (nc & 1), npairs = nc2 / 2, m1 = nc2 - 1;
   bool any = false;
   for (int p0 = 0; p0 < npairs; p0 += SLOTS) {
     const int pi = p0 + grp;
     int p = -1, q = -1;
     if (pi < npairs) {
-      const int x0 = pi, x1 = nc2 - 1 - pi;
-      const int u = (x0 == 0) ? 0 : 1 + (x0 - 1 + round) % (nc2 - 1);
-      const int v = (x1 == 0) ? 0 : 1 + (x1 - 1 + round) % (nc2 - 1);
+      // round-robin positions: slot 0 fixed, the others rotate by `round`
+      int u = 0;
+      if (pi > 0) { u = pi - 1 + round; if (u >= m1) u -= m1; u += 1; }
+      int v = m1 - pi - 1 + round;        // m1 - pi >= 1
+      if (v >= m1) v -= m1;
+      v += 1;
       if (u < nc && v < nc && !(thr >= 0.0 && nrm2[u] < thr && nrm2[v] < thr)) { p = u; q = v; }
     }
-    double x[16], y[16];
+    double x[EM], y[EM];
     double al = 0.0, be = 0.0, ga = 0.0;
+    const double* Lp = L + (p >= 0 ? p : 0) * ldl;
+    const double* Lq = L + (q >= 0 ? q : 0) * ldl;
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
+    for (int e = 0; e < EM; ++e) {
       const int r = j + G * e;
-      const bool ok = p >= 0 && e < E && r < nr;
-      x[e] = ok ? L[(int64_t)p * ldl + r] : 0.0;
-      y[e] = ok ? L[(int64_t)q * ldl + r] : 0.0;
+      const bool ok = p >= 0 && r < nr;
+      x[e] = ok ? Lp[r] : 0.0;
+      y[e] = ok ? Lq[r] : 0.0;
       if (r < nd) { al += x[e] * x[e]; be += y[e] * y[e]; ga += x[e] * y[e]; }
     }
 #pragma unroll
@@ -284,12 +288,14 @@ jacobi_round(double* L, int ldl, int nr, int nd, int nc, int round, double thr, 
       const double zeta = (be - al) / (2.0 * ga);
       const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
       const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+      double* Wp = L + p * ldl;
+      double* Wq = L + q * ldl;
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
+      for (int e = 0; e < EM; ++e) {
         const int r = j + G * e;
-        if (e < E && r < nr) {
-          L[(int64_t)p * ldl + r] = c * x[e] - s * y[e];
-          L[(int64_t)q * ldl + r] = s * x[e] + c * y[e];
+        if (r < nr) {
+          Wp[r] = c * x[e] - s * y[e];
+          Wq[r] = s * x[e] + c * y[e];
         }
       }
       any = true;
@@ -299,7 +305,7 @@ jacobi_round(double* L, int ldl, int nr, int nd, int nc, int round, double thr, 
 }
 
 // All sweeps on W (ld ldw): LDS copy or A itself.
-template <int G>
+template <int G, int EM>
 __device__ __attribute__((always_inline)) inline int
 jacobi_sweeps(double* W, int ldw, int nr, int nd, int nc, double tol, int maxsweep, int topk, double* nrm2,
               int* scratch, double* kth_slot) {
@@ -326,7 +332,7 @@ jacobi_sweeps(double* W, int ldw, int nr, int nd, int nc, double tol, int maxswe
       thr = 0.25 * *kth_slot;
     }
     for (int round = 0; round < nc2 - 1; ++round) {
-      jacobi_round<G>(W, ldw, nr, nd, nc, round, thr, nrm2, tol, scratch);
+      jacobi_round<G, EM>(W, ldw, nr, nd, nc, round, thr, nrm2, tol, scratch);
       __syncthreads();
     }
     const int any = scratch[0];
@@ -336,20 +342,20 @@ jacobi_sweeps(double* W, int ldw, int nr, int nd, int nc, double tol, int maxswe
   return maxsweep + 1;
 }
 
-template <int G>
+template <int G, int EM>
 __device__ __attribute__((always_inline)) inline int
 jacobi_os(double* A, int lda, int nr, int nd, int nc, double tol, int maxsweep, int topk, double* nrm2,
           int* scratch, double* kth_slot, double* lds, int cap) {
   const int tid = threadIdx.x;
   if (nc < 2) return 0;
   if ((int64_t)nc * nr > cap)
-    return jacobi_sweeps<G>(A, lda, nr, nd, nc, tol, maxsweep, topk, nrm2, scratch, kth_slot);
+    return jacobi_sweeps<G, EM>(A, lda, nr, nd, nc, tol, maxsweep, topk, nrm2, scratch, kth_slot);
   for (int e = tid; e < nc * nr; e += 1024) {
     const int c = e / nr, r = e - c * nr;
     lds[e] = A[(int64_t)c * lda + r];
   }
   __syncthreads();
-  const int sw = jacobi_sweeps<G>(lds, nr, nr, nd, nc, tol, maxsweep, topk, nrm2, scratch, kth_slot);
+  const int sw = jacobi_sweeps<G, EM>(lds, nr, nr, nd, nc, tol, maxsweep, topk, nrm2, scratch, kth_slot);
   for (int e = tid; e < nc * nr; e += 1024) {
     const int c = e / nr, r = e - c * nr;
     A[(int64_t)c * lda + r] = lds[e];
@@ -447,14 +453,21 @@ struct SmallShared {
 //     unchanged), again by pivoted Cholesky + Jacobi;
 //  4. L Y: alpha_i = ||L1 y_i||, beta_i = ||L2 y_i|| (beta from L2 as the
 //     column norms, never sqrt(1 - alpha^2)), X1, X2, (L Y)^T, quantities.
+// G lanes per column pair and EM entries per lane: G * EM >= nr
 __device__ __attribute__((always_inline)) inline int
 jacobi_any(double* A, int lda, int nr, int nc, double tol, int maxsweep, int topk, SmallShared& sh,
            double* lds, int cap) {
-  return nr <= 256 ? jacobi_os<16>(A, lda, nr, nr, nc, tol, maxsweep, topk, sh.keys, sh.scratch, &sh.kth, lds, cap)
-                   : jacobi_os<32>(A, lda, nr, nr, nc, tol, maxsweep, topk, sh.keys, sh.scratch, &sh.kth, lds, cap);
+  double* k = sh.keys;
+  int* sc = sh.scratch;
+  double* kt = &sh.kth;
+  if (nr <= 64) return jacobi_os<16, 4>(A, lda, nr, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
+  if (nr <= 128) return jacobi_os<16, 8>(A, lda, nr, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
+  if (nr <= 256) return jacobi_os<16, 16>(A, lda, nr, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
+  return jacobi_os<32, 16>(A, lda, nr, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
 }
 
-__device__ void small_pair(const SmallJob& J, double* lds, int cap, SmallShared& sh) {
+__device__ __attribute__((always_inline)) inline void small_pair(const SmallJob& J, double* lds, int cap,
+                                                             SmallShared& sh) {
   const int l1 = J.l1, N = J.l1 + J.l2, t = J.t;
   const int tid = threadIdx.x;
   double* keys = sh.keys;
