@@ -249,3 +249,56 @@ def profile_read(plan, maxn=512):
 
 def decode_flags(word):
     return [name for bit, name in FLAGS.items() if word & bit]
+
+
+class BatchPlan:
+    """One plan for a list of uneven pairs (one Desc each), run as a captured
+    graph: bind once per set of device pointers, then replay."""
+
+    def __init__(self, descs, device):
+        torch = _torch()
+        self.descs = list(descs)
+        arr = (Desc * len(self.descs))(*self.descs)
+        h = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        check(lib().rgsvd_batch_plan(arr, len(self.descs), ctypes.byref(h), ctypes.byref(ws)),
+              "rgsvd_batch_plan")
+        self.h = h
+        self.ws = torch.empty(ws.value + 256, dtype=torch.uint8, device=device)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_ptr = ctypes.c_void_p(self.ws.data_ptr() + off)
+        self.device = device
+        self.outs = None
+
+    def bind(self, pairs, uvr=True):
+        """pairs: list of (G1, G2) device tensors; allocates and returns the
+        per-pair output dicts (filled by every run)."""
+        io = (PairIO * len(pairs))()
+        self.outs = []
+        self.keep = []
+        for i, ((G1, G2), d) in enumerate(zip(pairs, self.descs)):
+            m, n = G1.shape
+            p = G2.shape[0]
+            assert (m, p, n) == (d.m, d.p, d.n)
+            t = d.n if d.mode == MODE["full"] else d.k
+            N = 2 * (d.k + d.oversample)
+            o = alloc_outputs(t, m, p, n, N, self.device, uvr)
+            self.outs.append(o)
+            self.keep.append((G1, G2))
+            io[i].G1 = _ptr(G1); io[i].G2 = _ptr(G2)
+            io[i].ld1 = G1.stride(0); io[i].ld2 = G2.stride(0)
+            io[i].out = out_struct(o, m, p, n)
+        check(lib().rgsvd_batch_bind(self.h, io, self.ws_ptr, _stream(self.device)), "rgsvd_batch_bind")
+        return self.outs
+
+    def run(self):
+        check(lib().rgsvd_batch_run(self.h, _stream(self.device)), "rgsvd_batch_run")
+        return self.outs
+
+    def __del__(self):
+        try:
+            if self.h:
+                lib().rgsvd_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass

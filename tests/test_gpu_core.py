@@ -225,3 +225,31 @@ def test_determinism_bitwise(dev):
     b = _run(dev, w["G1"], w["G2"], 20, 10, 1, 1)
     for key in ("alpha", "beta", "theta", "U", "V", "R", "sigma_B"):
         assert np.array_equal(a[key], b[key]), key
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp32"])
+def test_reduced_precision_gate(dev, precision):
+    """BF16/FP32 sketch paths against the FP64 oracle: 1e-4 on the angular
+    distances of the pairs whose weaker component min(alpha_i, beta_i) ||R_i||
+    is above the noise floor (the k-subspace being gap-separated), 1e-5 on the
+    entropies."""
+    from oracle import rgsvd as O
+    from paper_2404_09459_amd import inputs as I
+    m, p, n, k, o, q = 3000, 2500, 800, 100, 10, 2
+    _say(f"{precision} gate m={m} p={p} n={n} k={k} q={q}")
+    j = np.arange(k)
+    G1, G2 = I.lowrank_pair(m, p, n, k, 0.97 ** j, 0.96 ** j, 5 + n, noise_spectral=1e-4,
+                            dtype=np.float32)
+    got = _run(dev, G1, G2, k, o, q, 21, precision=precision)
+    ref = O.rgsvd(G1.astype(np.float64), G2.astype(np.float64), k, o, q, 21)
+    s = ref["sigma_B"]
+    assert s[k - 1] >= 2 * s[k]
+    weak = np.minimum(ref["alpha"], ref["beta"]) * np.linalg.norm(ref["R"], axis=1)
+    idx = np.where(weak >= 10 * 1e-4)[0]
+    dth = np.max(np.abs(got["theta"][idx] - ref["theta"][idx]))
+    dd = np.max(np.abs(got["D"] - [ref["D1"], ref["D2"]]))
+    _say(f"   pinned {len(idx)}/{k} |dtheta|={dth:.2e} (all {np.max(np.abs(got['theta'] - ref['theta'])):.2e})"
+         f" |dD|={dd:.2e} info={got['info'].tolist()}")
+    assert len(idx) >= k // 2
+    assert dth <= 1e-4 and dd <= 1e-5
+    assert np.max(np.abs(got["alpha"] ** 2 + got["beta"] ** 2 - 1)) <= 1e-12
