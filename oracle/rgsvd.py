@@ -73,11 +73,37 @@ def basis_fixed(G, l, q, seed, stream):
     return Q
 
 
+BLOCK_DROP = 1e-5
+
+
+def _orth_block(Y, Q):
+    """Orthonormal columns for the block Y against the basis Q so far: the
+    reduced QR of (I - QQ^T) Y with a positive diagonal, taken column by column
+    (Gram-Schmidt against Q and the block's earlier columns, applied twice).
+    A column whose projected norm is below BLOCK_DROP times its own norm lies
+    numerically in the span already formed; it is returned as a zero column so
+    that the nonzero columns of [Q, P] stay orthonormal (normalising the
+    rounding residue instead would give a direction that is not orthogonal to
+    Q and count energy twice in the residual)."""
+    P = np.zeros_like(Y)
+    for j in range(Y.shape[1]):
+        y = Y[:, j]
+        v = y.copy()
+        for _ in range(2):
+            v = v - Q @ (Q.T @ v)
+            v = v - P[:, :j] @ (P[:, :j].T @ v)
+        nv = np.linalg.norm(v)
+        if nv > BLOCK_DROP * np.linalg.norm(y) and nv > 0:
+            P[:, j] = v / nv
+    return P
+
+
 def basis_adaptive(G, eps, b, seed, stream, lmax=None, rel=False):
     """Algorithm 1: blocks of b Gaussian columns until ||(I - QQ^T)G||_F < eps.
 
     Each block: Y_i = (I - QQ^T) G Omega_i (the projection applied twice),
-    reduced QR Y_i = P_i T_i, Q = [Q, P_i].  The residual is kept in the
+    reduced QR Y_i = P_i T_i, Q = [Q, P_i]; columns of a block that are
+    numerically inside span(Q) become zero columns (see _orth_block).  The residual is kept in the
     cumulative form of Sec. 2: ||G||_F^2 - sum_i ||P_i^T G||_F^2, floored at
     zero.  Blocks use consecutive global columns of one Omega stream.
     The loop runs over ceil(min(m, n)/b) blocks with a short last block.
@@ -95,9 +121,7 @@ def basis_adaptive(G, eps, b, seed, stream, lmax=None, rel=False):
     while col < lcap:
         bb = min(b, lcap - col)
         Y = G @ gaussian_matrix(seed, stream, n, col, bb)
-        for _ in range(2):
-            Y = Y - Q @ (Q.T @ Y)
-        P, _ = qr_pos(Y)
+        P = _orth_block(Y, Q)
         Q = np.hstack([Q, P])
         Bt = P.T @ G
         energy += float(np.sum(Bt * Bt))

@@ -51,10 +51,20 @@ def test_adaptive_first_block_is_fixed_sketch_prefix():
 
 
 def test_adaptive_stops_on_exact_low_rank():
+    """Rank 6, blocks of 4: the second block crosses the rank.  Its two
+    columns inside span(Q) come back as zero columns, the six others are
+    orthonormal, the range is captured exactly (Lemma c2), and the cumulative
+    residual falls below a tolerance above its cancellation floor
+    (about sqrt(eps) ||G||_F)."""
     j = np.arange(6)
     G1, _ = I.lowrank_pair(80, 80, 60, 6, 0.5 ** j, 0.5 ** j, 3, noise_entry=0.0)
-    Q, hist = O.basis_adaptive(G1, 1e-10, 4, 2, STREAM_G1)
-    assert Q.shape[1] == 8 and hist[-1] < 1e-10
+    Q, hist = O.basis_adaptive(G1, 1e-6, 4, 2, STREAM_G1)
+    assert Q.shape[1] == 8 and hist[-1] < 1e-6
+    live = np.linalg.norm(Q, axis=0) > 0
+    assert live.sum() == 6
+    Ql = Q[:, live]
+    assert np.max(np.abs(Ql.T @ Ql - np.eye(6))) <= 1e-14
+    assert np.linalg.norm(G1 - Q @ (Q.T @ G1)) <= 1e-13 * np.linalg.norm(G1)
 
 
 def test_theorem_projector_expected_residual_bound():
