@@ -30,6 +30,12 @@ sys.path.insert(0, ROOT)
 METRIC = "rGSVD pairs/s + sketch TFLOP/s, mixed vs FP64, at angular-dist err<=1e-4"
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TF = {"fp64": 78.6, "fp32": 157.3, "mixed": 2516.6}
+# 256 CUs x 4 SIMDs x 16 FP64 FMA lanes x 2 flops x 2.4 GHz
+FP64_VEC_PEAK_TF = 78.6
+# HBM bytes per launch on the 20000/15000 x 5000 workload, from FETCH_SIZE and
+# WRITE_SIZE scaled by a copy kernel of known size (profiles/hbm_counters_*.md)
+TRAFFIC_SMALL = 2.14e6
+TRAFFIC_SKETCH = 756.06e6
 
 
 def log(*a):
@@ -79,6 +85,9 @@ def main():
     ap.add_argument("--precisions", default="mixed,fp32,fp64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain elementwise copy of MIB MiB (read + write) for "
+                         "calibrating hardware byte counters")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this build measures one MI355X "
@@ -142,6 +151,16 @@ def main():
                                             sorted(agg.items(), key=lambda x: -x[1][0])))
         del plan
 
+    if args.calib_copy > 0:
+        nel = args.calib_copy * (1 << 20) // 4
+        a = torch.ones(nel, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.neg(a, out=b)
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: 3 x {args.calib_copy} MiB read + {args.calib_copy} MiB written")
+        del a, b
+
     # ---------------------------------------------------------- CPU oracle --
     cpu = None
     ref = None
@@ -179,29 +198,37 @@ def main():
                        "sketch_tflops": sk_flops / (r["sketch_ms"] * 1e-3) / 1e12,
                        "errors_vs_oracle": e, "info": r["info"],
                        "stage_ms": {kk: round(v[0], 4) for kk, v in r["stages"].items()}}
-    # dominant kernel of the headline path
+    # dominant kernel of the headline path, priced against its own roofline
     agg = res[flag]["stages"]
     dom = max(agg.items(), key=lambda x: x[1][0])
     dom_tag, (dom_ms, dom_cnt) = dom[0], dom[1]
     avg_ms = dom_ms / dom_cnt
     gbytes = (m + p) * n * esz
-    if dom_tag in ("nn", "tn"):
-        if flag == "mixed":
-            roof = {"bound": "hbm", "achieved": gbytes / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s"}
-        else:
-            roof = {"bound": "mfma", "achieved": 2.0 * (m + p) * n * l / (avg_ms * 1e-3) / 1e12,
-                    "peak": MFMA_PEAK_TF[flag], "unit": "TFLOP/s"}
+    N = 2 * l
+    if dom_tag == "small":
+        # one workgroup per pair: two dense symmetric eigendecompositions with
+        # vectors (M: N x N, H: k x k) at 9 n^3 flops each, FP64 vector ALU
+        flops = 9.0 * N ** 3 + 9.0 * k ** 3
+        roof = {"bound": "alu", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": FP64_VEC_PEAK_TF,
+                "unit": "TFLOP/s", "traffic": TRAFFIC_SMALL if args.workload == "medium" else None}
+    elif dom_tag in ("nn", "tn") and flag == "mixed":
+        roof = {"bound": "hbm", "achieved": gbytes / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "traffic": None}
+    elif dom_tag in ("nn", "tn"):
+        roof = {"bound": "mfma", "achieved": 2.0 * (m + p) * n * l / (avg_ms * 1e-3) / 1e12,
+                "peak": MFMA_PEAK_TF[flag], "unit": "TFLOP/s", "traffic": None}
     else:
-        roof = {"bound": "alu", "achieved": None, "peak": None, "unit": None}
-    if roof.get("achieved") is not None:
-        roof["frac"] = roof["achieved"] / roof["peak"]
-    else:
-        roof["frac"] = None
-    roof["traffic"] = None
-    roof["kernel"] = dom_tag
+        roof = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "traffic": None}
+    roof["frac"] = roof["achieved"] / roof["peak"] if roof.get("achieved") is not None else None
+    roof["kernel"] = {"small": "k_small", "nn": "k_gw", "tn": "k_gtq"}.get(dom_tag, dom_tag)
     roof["avg_launch_ms"] = avg_ms
     roof["launches_per_step"] = dom_cnt
+    # the streaming sketch kernel beside it: one read of G1 and G2 per launch
+    sk_ms = res[flag]["sketch_ms"]
+    roof_sketch = {"bound": "hbm", "kernel": "k_gw", "achieved": gbytes / (sk_ms * 1e-3) / 1e9,
+                   "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbytes / (sk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                   "traffic": TRAFFIC_SKETCH if args.workload == "medium" else None,
+                   "tflops": sk_flops / (sk_ms * 1e-3) / 1e12}
     gate = None
     if paths[flag]["errors_vs_oracle"]:
         e = paths[flag]["errors_vs_oracle"]
@@ -218,6 +245,7 @@ def main():
         "accuracy_gate_passed": gate,
         "sketch_tflops": paths[flag]["sketch_tflops"],
         "roofline": roof,
+        "roofline_sketch": roof_sketch,
         "cpu_baseline": cpu,
         "paths": paths,
     }

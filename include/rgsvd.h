@@ -116,7 +116,7 @@ typedef struct {
   uint64_t seed;            /* Omega seed                                              */
   double tol;               /* adaptive: eps of Algorithm 1 (absolute Frobenius)       */
   int64_t block;            /* adaptive: b of Algorithm 1 (0 -> 100)                   */
-  int64_t lmax;             /* adaptive/learned: cap on l_i (0 -> min(m_i, n))         */
+  int64_t lmax;             /* adaptive/learned: cap on l_i (0 -> min(m_i, n, 224))    */
 } rgsvd_desc;
 
 /* Caller-owned device outputs.  alpha, beta, theta, P1, P2 have t entries,
@@ -144,11 +144,25 @@ int rgsvd_plan(const rgsvd_desc* desc, rgsvd_plan_t* plan, size_t* workspace_byt
  * dimensions ld1, ld2 >= n (elements).  workspace: device buffer of the
  * size rgsvd_plan reported, owned by the caller, not used concurrently by
  * another run.  The plan must not be used by two streams at once.
+ *
+ * Fixed sizing only enqueues.  Adaptive sizing (Sec. 2, Algorithm 1) runs
+ * block by block: Omega columns [l, l + block) of each matrix's stream, the
+ * block projected against the basis so far and orthonormalised, the new rows
+ * of B = Q^T G and their energy; the residual ||G||_F^2 - sum ||B_j||_F^2
+ * is compared with tol^2 on the host, so the call synchronises `stream`
+ * once after the norms of G and once per block (FP64 precision, truncated
+ * mode; blocks rows numerically inside the span of the basis become zero
+ * basis vectors).  Learned sizing synchronises once: it evaluates the
+ * attached network on the probe features and runs the fixed path at the
+ * chosen l (one of k+4, k+8, k+16, k+32, 2k, capped) and q (0..3).  For
+ * both, info[1], info[2], info[3] report the l1, l2, q used and sigma_B
+ * needs room for the capacities l1 + l2 of rgsvd_plan_sizes.
  * Errors: RGSVD_EINVAL, RGSVD_EWORKSPACE, RGSVD_ENOMODEL, RGSVD_EHIP. */
 int rgsvd_run(rgsvd_plan_t plan, const void* G1, int64_t ld1, const void* G2, int64_t ld2,
               void* workspace, void* stream, const rgsvd_out* out);
 
-/* t (number of returned pairs) and l1, l2 the plan uses for fixed sizing. */
+/* t (number of returned pairs) and l1, l2: the sketch widths of fixed
+ * sizing, the largest widths (capacities) of adaptive and learned sizing. */
 int rgsvd_plan_sizes(rgsvd_plan_t plan, int64_t* t, int64_t* l1, int64_t* l2);
 
 void rgsvd_destroy(rgsvd_plan_t plan);
@@ -190,8 +204,8 @@ int rgsvd_batch_run(rgsvd_plan_t plan, void* stream);
  * W2 (64x64), b2 (64), W3 (2x64), b3 (2), row-major W[out][in],
  * concatenated (RGSVD_MLP_PARAMS floats).  Features (32): log10(s_i/s_1)
  * of the 16 singular values of the probe sketches G1 Omega[:, :16] and
- * G2 Omega[:, :16].  Outputs: (log2 of the sketch width l, power count q)
- * regression targets. */
+ * G2 Omega[:, :16].  Outputs: regression targets (log2(l / k), q) of the
+ * sketch width l and the power count q. */
 #define RGSVD_MLP_PARAMS 6402
 #define RGSVD_MLP_IN 32
 #define RGSVD_MLP_OUT 2
@@ -212,11 +226,13 @@ int rgsvd_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t
 /* Attach a trained sizing network (device params, copied into the plan's
  * own device buffer on `stream`). */
 int rgsvd_set_sizing_model(rgsvd_plan_t plan, const float* params, void* stream);
-/* Probe features of a pair for the sizing network: the 32 features above
- * into feat (device, 32 floats). */
-int rgsvd_probe_features(const rgsvd_desc* desc, const void* G1, int64_t ld1, const void* G2,
-                         int64_t ld2, float* feat, void* workspace, size_t workspace_bytes,
-                         void* stream);
+/* Probe features of a pair for the sizing network (enqueued on `stream`):
+ * the 32 features above, each log10(s_i / s_1) floored at -8 (the FP64 Gram
+ * of the probe resolves s_i / s_1 down to about 1e-8), into feat (device,
+ * 32 floats).  Uses the plan's shapes, storage type and seed and its
+ * workspace (any sizing mode; single-pair plans). */
+int rgsvd_probe_features(rgsvd_plan_t plan, const void* G1, int64_t ld1, const void* G2, int64_t ld2,
+                         void* workspace, float* feat, void* stream);
 
 /* ----------------------------------------------------------- checks ---- */
 /* Omega[r][col0 + c] (r < rows, c < ncols) into out (row-major, ld >= ncols),

@@ -44,7 +44,7 @@ inline int ct_of(int L) {
 }
 
 enum Kind { K_ZERO, K_COPY, K_GEN, K_NN, K_AB, K_GRAM, K_RED, K_CHOL, K_SMALL, K_SIGN, K_SCALE, K_GW, K_GTQ,
-            K_CVT };
+            K_CVT, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP };
 
 enum Tag { T_ZERO, T_COPY, T_GEN, T_NN, T_TN, T_RED, T_GRAM, T_CHOL, T_SX, T_SMALL, T_RECOVER, T_SIGN,
            T_MGRAM, T_NTAGS };
@@ -72,6 +72,12 @@ struct SideLay {
   size_t Yt = 0, Wt = 0, part = 0, gpart = 0, gram = 0, sinv = 0, Yt16 = 0, Wt16 = 0;
   const void* G = nullptr; int64_t ldg = 0;
   uint64_t seed = 0; int stream = 1;
+  // adaptive basis (Algorithm 1): Omega block buffer, rows formed so far,
+  // current block width, per-side scalars (||G||_F^2, block energy) and the
+  // partial sums behind them
+  size_t Ot = 0, scal = 0, spart = 0;
+  int cap = 0, lcur = 0, bcur = 0, gtiles = 0;
+  bool active = false;
 };
 
 struct PairLay {
@@ -81,6 +87,7 @@ struct PairLay {
   int gch = 1, gcl = 0;
   size_t mpart = 0, M = 0, work = 0, sigma = 0, X1t = 0, X2t = 0, Rcoef = 0, sgn = 0, info = 0;
   size_t alpha = 0;  // internal outputs when the caller passes null
+  int l1cap = 0, l2cap = 0;
   rgsvd_out out{};
 };
 
@@ -95,6 +102,12 @@ struct rgsvd_plan_s {
   std::vector<SideLay> sides;
   size_t off_chol = 0, off_jobs = 0, jobs_cap = 0, ws = 0;
   int nchol_slots = 0;
+  // adaptive sizing: which part build() emits, and the block size
+  enum Part { FIXED, A_INIT, A_BLOCK, TAIL, PROBE } part = FIXED;
+  bool adaptive = false, learned = false;
+  size_t off_feat = 0;      // probe features (32 floats), network output (2), activations (128)
+  int block = 100;
+  double* hscal = nullptr;   // pinned host copy of the per-side scalars
   int wave_slots = 2048;   // concurrently resident single-wave workgroups
   // job tables
   std::vector<unsigned char> host;   // serialized job tables
@@ -129,8 +142,11 @@ int layout(rgsvd_plan_s* P) {
   const size_t psz = wsz;                      // partial element size
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = up(off + bytes, ALIGN); return o; };
+  // adaptive runs grow Q by blocks written 16-row aligned at offset l: one
+  // spare 16-row group past the capacity
+  const int spare = P->adaptive ? 16 : 0;
   P->Lmax = 16;
-  for (auto& pr : P->pairs) P->Lmax = std::max(P->Lmax, (int)upi(std::max(pr.l1, pr.l2), 16));
+  for (auto& pr : P->pairs) P->Lmax = std::max(P->Lmax, (int)upi(std::max(pr.l1, pr.l2), 16) + spare);
   P->npadG = (int)upi(P->Lmax, 64);
   const int nsides = 2 * (int)P->pairs.size();
   P->sides.clear();
@@ -141,7 +157,8 @@ int layout(rgsvd_plan_s* P) {
       s.pair = (int)pi; s.which = w;
       s.m = (int)(w ? pr.p : pr.m); s.n = (int)pr.n;
       s.l = w ? pr.l2 : pr.l1;
-      s.L = (int)upi(s.l, 16);
+      s.cap = s.l;
+      s.L = (int)upi(s.l, 16) + spare;
       s.ldy = (int)upi(s.m, 64); s.ldw = (int)upi(s.n, 64);
       s.seed = pr.seed; s.stream = w ? 2 : 1;
       // G^T Q row chunks: enough single-wave tiles to fill the wave slots once
@@ -174,6 +191,13 @@ int layout(rgsvd_plan_s* P) {
       s.gpart = take((size_t)gch * P->npadG * P->npadG * 8);
       s.gram = take((size_t)P->npadG * P->npadG * 8);
       s.sinv = take((size_t)P->npadG * P->npadG * 8);
+      if (P->adaptive) {
+        const int lb = (int)upi(std::min(P->block, s.cap), 16);
+        s.Ot = take((size_t)lb * s.ldw * wsz);
+        s.scal = take(8 * 8);
+        s.gtiles = (s.m + 63) / 64;
+        s.spart = take((size_t)std::max(s.gtiles, 64) * 8);
+      }
       P->sides.push_back(s);
     }
   }
@@ -197,6 +221,7 @@ int layout(rgsvd_plan_s* P) {
     pr.info = take(RGSVD_INFO_WORDS * 4);
     pr.alpha = take(t * 8 * 5 + 16);   // alpha, beta, theta, P1, P2, D when not given
   }
+  P->off_feat = take((RGSVD_MLP_IN + RGSVD_MLP_OUT + 2 * 64 + 2) * sizeof(float));
   P->nchol_slots = 0;
   if (P->npadG > 128) P->nchol_slots = nsides;
   P->off_chol = take((size_t)std::max(1, P->nchol_slots) * (CHOL_MAX * CHOL_MAX + 2 * CHOL_MAX) * 8);
@@ -246,13 +271,16 @@ int build(rgsvd_plan_s* P, void* ws) {
   const int wt = (prec == P64) ? 0 : 1;            // working type code
   const int gt = (P->gdt == RGSVD_F64) ? 0 : 1;
   const bool mixed = (prec == PBF);
-  const int ctL = ct_of(P->Lmax);
+  const int ctL = ct_of([&] { int L = 16; for (auto& s : P->sides) L = std::max(L, s.L); return L; }());
   std::vector<SideLay>& S = P->sides;
   const int ns = (int)S.size();
 
+  const auto part = P->part;
+  const bool head = (part == rgsvd_plan_s::FIXED || part == rgsvd_plan_s::A_INIT);
+  const bool tail = (part == rgsvd_plan_s::FIXED || part == rgsvd_plan_s::TAIL);
   // 0. zero the W buffers (their padding rows must read as zero) and copy
   //    the info templates
-  for (auto& s : S) {
+  if (head) for (auto& s : S) {
     Stage z; z.kind = K_ZERO; z.tag = T_ZERO; z.zoff = s.Wt;
     z.zbytes = (size_t)s.L * s.ldw * (prec == P64 ? 8 : 4);
     P->stages.push_back(z);
@@ -260,13 +288,16 @@ int build(rgsvd_plan_s* P, void* ws) {
     y.zbytes = (size_t)s.L * s.ldy * (prec == P64 ? 8 : 4);
     P->stages.push_back(y);
   }
-  {
+  if (head || part == rgsvd_plan_s::TAIL) {
+    // the tail of an adaptive run rewrites the words with the final sizes
+    // (flags raised by the block steps are kept)
+    const int nw = head ? RGSVD_INFO_WORDS : 4;
     std::vector<uint32_t> tmpl;
     std::vector<CopyJob> cj;
     std::vector<int> tl;
     for (auto& pr : P->pairs) {
       uint32_t w[RGSVD_INFO_WORDS] = {0};
-      w[1] = pr.l1; w[2] = pr.l2; w[3] = pr.q;
+      w[1] = pr.l1; w[2] = pr.l2; w[3] = P->adaptive ? 0 : pr.q;
       for (int i = 0; i < RGSVD_INFO_WORDS; ++i) tmpl.push_back(w[i]);
     }
     size_t toff = B.put(tmpl);
@@ -274,7 +305,7 @@ int build(rgsvd_plan_s* P, void* ws) {
       auto& pr = P->pairs[i];
       int32_t* info = pr.out.info ? pr.out.info : (int32_t*)WS(ws, pr.info);
       cj.push_back(CopyJob{(const uint32_t*)WS(ws, P->off_jobs + toff) + i * RGSVD_INFO_WORDS,
-                           (uint32_t*)info, RGSVD_INFO_WORDS});
+                           (uint32_t*)info, nw});
       tl.push_back(1);
     }
     B.add(K_COPY, cj, tl).tag = T_COPY;
@@ -284,8 +315,70 @@ int build(rgsvd_plan_s* P, void* ws) {
     return pr.out.info ? pr.out.info : (int32_t*)WS(ws, pr.info);
   };
 
+  // probe features of the pair and the sizing network's output (learned
+  // sizing): Omega[:, :16], Y = G Omega16, its 16 x 16 Gram in FP64, the
+  // features from the Gram's eigenvalues, and the network on them
+  if (part == rgsvd_plan_s::PROBE) {
+    const int pw = (prec == P64) ? P64 : P32;
+    const size_t wsz = (pw == P64) ? 8 : 4;
+    for (auto& s : S) {
+      Stage z; z.kind = K_ZERO; z.tag = T_ZERO; z.zoff = s.Yt; z.zbytes = (size_t)16 * s.ldy * wsz;
+      P->stages.push_back(z);
+    }
+    {
+      std::vector<GenJob> j; std::vector<int> tl;
+      for (auto& s : S) {
+        GenJob g{};
+        g.Wt = WS(ws, s.Wt); g.ldw = s.ldw; g.seed = s.seed; g.n = s.n; g.col0 = 0;
+        g.ncols = 16; g.L = 16; g.stream = s.stream;
+        j.push_back(g);
+        tl.push_back(((s.n + 255) / 256) * 4);
+      }
+      Stage& st = B.add(K_GEN, j, tl); st.f64 = (pw == P64); st.tag = T_GEN;
+    }
+    {
+      std::vector<NnJob> j; std::vector<int> tl;
+      for (auto& s : S) {
+        NnJob x{};
+        x.G = s.G; x.Wt = WS(ws, s.Wt); x.Yt = WS(ws, s.Yt);
+        x.ldg = s.ldg; x.ldw = s.ldw; x.ldy = s.ldy; x.m = s.m; x.n = s.n; x.L = 16;
+        j.push_back(x);
+        tl.push_back((s.m + 15) / 16);
+      }
+      Stage& st = B.add(K_GW, j, tl);
+      st.prec = pw; st.gdt = gt; st.rt = 1; st.ct = 1; st.tag = T_NN;
+    }
+    {
+      std::vector<GramJob> gj; std::vector<int> gtl;
+      std::vector<RedJob> rj; std::vector<int> rtl;
+      std::vector<FeatJob> fj; std::vector<int> ftl;
+      for (size_t i = 0; i < S.size(); ++i) {
+        auto& s = S[i];
+        GramJob g{};
+        g.X1 = WS(ws, s.Yt); g.X2 = nullptr; g.out = (double*)WS(ws, s.gpart);
+        g.ld1 = s.ldy; g.ld2 = 0; g.r1 = 16; g.r2 = 0; g.k0 = 0; g.k1 = s.m; g.npad = 64; g.clen = s.gcl_m;
+        gj.push_back(g); gtl.push_back(s.gch_m);
+        RedJob r{};
+        r.in = WS(ws, s.gpart); r.out = WS(ws, s.gram); r.sq = nullptr;
+        r.stride = 64 * 64; r.count = r.stride;
+        r.nparts = s.gch_m; r.rows = 64; r.cols = 64; r.ldo = 64; r.ldi = 64;
+        rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
+        fj.push_back(FeatJob{(const double*)WS(ws, s.gram), (float*)WS(ws, P->off_feat) + 16 * i, 64, 0});
+        ftl.push_back(1);
+      }
+      Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = (pw == P64) ? 0 : 1; gs.tag = T_GRAM;
+      Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.ta = 0; r.td = 0; r.tag = T_RED;
+      B.add(K_FEAT, fj, ftl).tag = T_SMALL;
+    }
+    if (P->mlp) {
+      Stage m; m.kind = K_MLP; m.tag = T_SMALL; P->stages.push_back(m);
+    }
+    if (P->host.size() > P->jobs_cap) return RGSVD_ENOMEM;
+    return RGSVD_OK;
+  }
+
   // 1. Omega
-  {
+  if (part == rgsvd_plan_s::FIXED) {
     std::vector<GenJob> j; std::vector<int> tl;
     for (auto& s : S) {
       GenJob g{};
@@ -404,19 +497,153 @@ int build(rgsvd_plan_s* P, void* ws) {
     r.sym = false; r.ta = wt; r.td = wt; r.tag = T_RED;
   };
 
-  const int qmax = [&] { int q = 0; for (auto& pr : P->pairs) q = std::max(q, pr.q); return q; }();
-  // sketch
-  add_nn(mixed ? PBF : prec);
-  add_orth(true, qmax == 0 ? 2 : 1);
-  for (int it = 1; it <= qmax; ++it) {
-    int p = mixed ? (it < qmax ? PBF : P32) : prec;
-    add_tn(p);
-    add_orth(false, 1);
-    add_nn(p);
-    add_orth(true, it == qmax ? 2 : 1);
+  if (part == rgsvd_plan_s::FIXED) {
+    const int qmax = [&] { int q = 0; for (auto& pr : P->pairs) q = std::max(q, pr.q); return q; }();
+    // sketch
+    add_nn(mixed ? PBF : prec);
+    add_orth(true, qmax == 0 ? 2 : 1);
+    for (int it = 1; it <= qmax; ++it) {
+      int p = mixed ? (it < qmax ? PBF : P32) : prec;
+      add_tn(p);
+      add_orth(false, 1);
+      add_nn(p);
+      add_orth(true, it == qmax ? 2 : 1);
+    }
+    // projection B_i = Q_i^T G_i
+    add_tn(mixed ? P32 : prec);
   }
-  // projection B_i = Q_i^T G_i
-  add_tn(mixed ? P32 : prec);
+
+  // sums of squares (adaptive): jobs and their finishing sums
+  auto add_sumsq = [&](std::vector<SumsqJob>& j, std::vector<int>& tl, std::vector<SumsqFin>& f) {
+    Stage& a = B.add(K_SUMSQ, j, tl); a.tag = T_RED;
+    std::vector<int> ftl(f.size(), 1);
+    B.add(K_SUMFIN, f, ftl).tag = T_RED;
+  };
+  if (part == rgsvd_plan_s::A_INIT) {
+    // ||G_i||_F^2 (FP64 partials over 64-row slabs, summed in order)
+    std::vector<SumsqJob> j; std::vector<int> tl; std::vector<SumsqFin> f;
+    for (auto& s : S) {
+      j.push_back(SumsqJob{s.G, s.ldg, s.m, s.n, gt == 0 ? 1 : 0, 64, (double*)WS(ws, s.spart)});
+      tl.push_back(s.gtiles);
+      f.push_back(SumsqFin{(const double*)WS(ws, s.spart), (double*)WS(ws, s.scal), s.gtiles, 0});
+    }
+    add_sumsq(j, tl, f);
+  }
+  if (part == rgsvd_plan_s::A_BLOCK) {
+    // one block of Algorithm 1 on every active side: Omega columns
+    // [l, l + b) of the side's stream, Y = G Omega into Q's rows [l, l + b),
+    // then Y projected against the earlier rows and orthonormalised by three
+    // truncated CholeskyQR passes over the stacked [Q; Y] (only Y's rows are
+    // rewritten), B rows [l, l + b) = Q_new^T G and the block's energy
+    // ||B_new||_F^2.
+    std::vector<SideLay*> A;
+    for (auto& s : S) if (s.active) A.push_back(&s);
+    const size_t wsz = 8;
+    {
+      std::vector<GenJob> j; std::vector<int> tl;
+      for (auto* s : A) {
+        GenJob g{};
+        g.Wt = WS(ws, s->Ot); g.ldw = s->ldw; g.seed = s->seed; g.n = s->n; g.col0 = s->lcur;
+        g.ncols = s->bcur; g.L = (int)upi(s->bcur, 16); g.stream = s->stream;
+        j.push_back(g);
+        tl.push_back(((s->n + 255) / 256) * (((s->bcur - 1) >> 2) + 1));
+      }
+      Stage& st = B.add(K_GEN, j, tl); st.f64 = true; st.tag = T_GEN;
+    }
+    {
+      std::vector<NnJob> j; std::vector<int> tl;
+      for (auto* s : A) {
+        NnJob x{};
+        x.G = s->G; x.Wt = WS(ws, s->Ot); x.Yt = WS(ws, s->Yt) + (size_t)s->lcur * s->ldy * wsz;
+        x.ldg = s->ldg; x.ldw = s->ldw; x.ldy = s->ldy; x.m = s->m; x.n = s->n; x.L = (int)upi(s->bcur, 16);
+        j.push_back(x);
+        tl.push_back((s->m + 15) / 16);
+      }
+      Stage& st = B.add(K_GW, j, tl);
+      st.prec = P64; st.gdt = gt; st.rt = 1; st.ct = ctL; st.tag = T_NN;
+    }
+    for (int ps = 0; ps < 3; ++ps) {
+      std::vector<GramJob> gj; std::vector<int> gtl;
+      std::vector<RedJob> rj; std::vector<int> rtl;
+      std::vector<CholJob> cj; std::vector<int> ctl;
+      std::vector<AbJob> aj; std::vector<int> atl;
+      const int nb = P->npadG / 64, nblk = nb * (nb + 1) / 2;
+      for (auto* s : A) {
+        const int N = s->lcur + s->bcur;
+        GramJob g{};
+        g.X1 = WS(ws, s->Yt); g.X2 = nullptr; g.out = (double*)WS(ws, s->gpart);
+        g.ld1 = s->ldy; g.ld2 = 0; g.r1 = N; g.r2 = 0; g.k0 = 0; g.k1 = s->m;
+        g.npad = P->npadG; g.clen = s->gcl_m;
+        gj.push_back(g); gtl.push_back(nblk * s->gch_m);
+        RedJob r{};
+        r.in = WS(ws, s->gpart); r.out = WS(ws, s->gram); r.sq = nullptr;
+        r.stride = (int64_t)P->npadG * P->npadG; r.count = r.stride;
+        r.nparts = s->gch_m; r.rows = P->npadG; r.cols = P->npadG; r.ldo = P->npadG; r.ldi = P->npadG;
+        rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
+        CholJob c{};
+        c.gram = (const double*)WS(ws, s->gram); c.sinv = (double*)WS(ws, s->sinv); c.r = nullptr;
+        c.info = info_of(s->pair); c.N = N; c.npad = P->npadG; c.flagbit = 0;
+        // rows of the block that lie (numerically) in the span of Q and of
+        // the block's earlier rows become zero rows of the basis
+        c.trunc = 1; c.shift0 = 0.0;
+        cj.push_back(c); ctl.push_back(1);
+        AbJob a{};
+        a.A = (const double*)WS(ws, s->sinv) + (size_t)s->lcur * P->npadG; a.lda = P->npadG;
+        a.B = WS(ws, s->Yt); a.ldb = s->ldy;
+        a.D = WS(ws, s->Yt) + (size_t)s->lcur * s->ldy * wsz; a.ldd = s->ldy;
+        a.rows = s->bcur; a.K = N; a.J = s->m; a.accumulate = 0; a.colscale = nullptr;
+        aj.push_back(a);
+        atl.push_back((s->m + 64 * 2 - 1) / (64 * 2));
+      }
+      Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = 0; gs.tag = T_GRAM;
+      Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.ta = 0; r.td = 0; r.tag = T_RED;
+      Stage& c = B.add(K_CHOL, cj, ctl); c.npad_max = P->npadG; c.tag = T_CHOL;
+      Stage& a = B.add(K_AB, aj, atl);
+      a.prec = P64; a.ta = 0; a.tb = 0; a.td = 0; a.ct = ctL; a.js = 2; a.tag = T_SX;
+    }
+    {
+      std::vector<AbJob> aj; std::vector<int> atl;
+      std::vector<RedJob> rj; std::vector<int> rtl;
+      for (auto* s : A) {
+        const int lb = (int)upi(s->bcur, 16);
+        for (int c = 0; c < s->nchunk; ++c) {
+          int r0 = c * s->mchunk;
+          int rows = std::min(s->mchunk, s->m - r0);
+          AbJob a{};
+          a.A = WS(ws, s->Yt) + ((size_t)s->lcur * s->ldy + r0) * wsz; a.lda = s->ldy;
+          a.B = (const char*)s->G + (size_t)r0 * s->ldg * (gt == 0 ? 8 : 4); a.ldb = s->ldg;
+          a.D = WS(ws, s->part) + (size_t)c * lb * s->ldw * wsz; a.ldd = s->ldw;
+          a.rows = lb; a.K = rows; a.J = s->n; a.accumulate = 0; a.colscale = nullptr;
+          aj.push_back(a);
+          atl.push_back((s->n + 31) / 32);
+        }
+        RedJob r{};
+        r.in = WS(ws, s->part); r.out = WS(ws, s->Wt) + (size_t)s->lcur * s->ldw * wsz; r.sq = nullptr;
+        r.stride = (int64_t)lb * s->ldw; r.count = (int64_t)lb * s->n;
+        r.nparts = s->nchunk; r.rows = lb; r.cols = s->n; r.ldo = s->ldw; r.ldi = s->ldw;
+        rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
+      }
+      Stage& a = B.add(K_GTQ, aj, atl);
+      a.prec = P64; a.gdt = gt; a.ct = ctL; a.js = 2; a.tag = T_TN;
+      Stage& r = B.add(K_RED, rj, rtl);
+      r.sym = false; r.ta = 0; r.td = 0; r.tag = T_RED;
+    }
+    {
+      std::vector<SumsqJob> j; std::vector<int> tl; std::vector<SumsqFin> f;
+      for (auto* s : A) {
+        const int nt = (s->bcur + 15) / 16;
+        j.push_back(SumsqJob{WS(ws, s->Wt) + (size_t)s->lcur * s->ldw * wsz, s->ldw, s->bcur, s->n, 1, 16,
+                             (double*)WS(ws, s->spart)});
+        tl.push_back(nt);
+        f.push_back(SumsqFin{(const double*)WS(ws, s->spart), (double*)WS(ws, s->scal) + 1, nt, 0});
+      }
+      add_sumsq(j, tl, f);
+    }
+  }
+  if (!tail) {
+    if (P->host.size() > P->jobs_cap) return RGSVD_ENOMEM;
+    return RGSVD_OK;
+  }
 
   // M = B B^T per pair
   {
@@ -539,6 +766,80 @@ __global__ void k_copy(const CopyJob* j, const int* pre, int nj) {
   for (int64_t i = threadIdx.x; i < J.nwords; i += blockDim.x) J.dst[i] = J.src[i];
 }
 
+// sum of squares of a row slab per tile (256 threads), in FP64
+__global__ __launch_bounds__(256) void k_sumsq(const SumsqJob* j, const int* pre, int nj) {
+  const int jb = find_side(pre, nj, blockIdx.x);
+  const SumsqJob J = j[jb];
+  const int t = blockIdx.x - pre[jb];
+  const int r0 = t * J.rpt, r1 = min(J.rows, r0 + J.rpt);
+  double acc = 0.0;
+  for (int r = r0; r < r1; ++r) {
+    if (J.f64) {
+      const double* x = (const double*)J.X + (int64_t)r * J.ld;
+      for (int c = threadIdx.x; c < J.cols; c += 256) acc += x[c] * x[c];
+    } else {
+      const float* x = (const float*)J.X + (int64_t)r * J.ld;
+      for (int c = threadIdx.x; c < J.cols; c += 256) { const double v = x[c]; acc += v * v; }
+    }
+  }
+  acc = wave_sum(acc);
+  __shared__ double ws4[4];
+  if ((threadIdx.x & 63) == 0) ws4[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) J.part[t] = ws4[0] + ws4[1] + ws4[2] + ws4[3];
+}
+
+__global__ void k_sumfin(const SumsqFin* j, int nj) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nj) return;
+  const SumsqFin J = j[i];
+  double s = 0.0;
+  for (int t = 0; t < J.ntiles; ++t) s += J.part[t];
+  J.out[0] = s;
+}
+
+// Probe features: eigenvalues of the 16 x 16 probe Gram by cyclic Jacobi
+// (one thread, FP64), sigma_j = sqrt(lambda_j) in descending order, then
+// log10(sigma_j / sigma_1) floored at -8 (the Gram resolves sigma_j / sigma_1
+// down to about sqrt(eps)).
+__global__ void k_feat(const FeatJob* j, int nj) {
+  const FeatJob J = j[blockIdx.x];
+  __shared__ double a[16][16];
+  for (int e = threadIdx.x; e < 256; e += blockDim.x) a[e >> 4][e & 15] = J.gram[(int64_t)(e >> 4) * J.ldg + (e & 15)];
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  for (int r = 0; r < 16; ++r)
+    for (int c = 0; c < r; ++c) a[r][c] = a[c][r];   // the reduction filled the upper triangle
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int r = 0; r < 16; ++r)
+      for (int c = 0; c < 16; ++c) { if (r != c) off += a[r][c] * a[r][c]; else dia += a[r][c] * a[r][c]; }
+    if (!(off > 1e-32 * dia)) break;
+    for (int p = 0; p < 15; ++p)
+      for (int q = p + 1; q < 16; ++q) {
+        const double apq = a[p][q];
+        if (apq == 0.0) continue;
+        const double th = (a[q][q] - a[p][p]) / (2.0 * apq);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+        for (int r = 0; r < 16; ++r) {
+          const double x = a[r][p], y = a[r][q];
+          a[r][p] = c * x - s * y; a[r][q] = s * x + c * y;
+        }
+        for (int r = 0; r < 16; ++r) {
+          const double x = a[p][r], y = a[q][r];
+          a[p][r] = c * x - s * y; a[q][r] = s * x + c * y;
+        }
+      }
+  }
+  double sv[16];
+  for (int i = 0; i < 16; ++i) sv[i] = sqrt(fmax(a[i][i], 0.0));
+  for (int i = 1; i < 16; ++i)
+    for (int k = i; k > 0 && sv[k] > sv[k - 1]; --k) { const double t = sv[k]; sv[k] = sv[k - 1]; sv[k - 1] = t; }
+  for (int i = 0; i < 16; ++i)
+    J.out[i] = (float)((sv[0] > 0.0 && sv[i] > 0.0) ? fmax(log10(sv[i] / sv[0]), -8.0) : -8.0);
+}
+
 int enqueue(rgsvd_plan_s* P, void* ws, hipStream_t st) {
   char* jb = (char*)ws + P->off_jobs;
   if (P->prof) {
@@ -569,6 +870,16 @@ int enqueue(rgsvd_plan_s* P, void* ws, hipStream_t st) {
       case K_GW: launch_gw(s.prec, s.gdt, s.rt, s.ct, (const NnJob*)j, pre, s.nj, s.tiles, st); break;
       case K_GTQ: launch_gtq(s.prec, s.gdt, s.ct, s.js, (const AbJob*)j, pre, s.nj, s.tiles, st); break;
       case K_CVT: launch_cvt(j, pre, s.nj, s.tiles, st); break;
+      case K_SUMSQ: hipLaunchKernelGGL(k_sumsq, dim3(s.tiles), dim3(256), 0, st, (const SumsqJob*)j, pre, s.nj); break;
+      case K_SUMFIN:
+        hipLaunchKernelGGL(k_sumfin, dim3((s.nj + 63) / 64), dim3(64), 0, st, (const SumsqFin*)j, s.nj);
+        break;
+      case K_FEAT: hipLaunchKernelGGL(k_feat, dim3(s.nj), dim3(64), 0, st, (const FeatJob*)j, s.nj); break;
+      case K_MLP: {
+        float* f = (float*)((char*)ws + P->off_feat);
+        rgsvd_mlp_forward(P->mlp, f, 1, f + RGSVD_MLP_IN, f + RGSVD_MLP_IN + RGSVD_MLP_OUT, st);
+        break;
+      }
     }
   }
   if (P->prof) hipEventRecord(P->pev[si], st);
@@ -589,6 +900,14 @@ int upload(rgsvd_plan_s* P, void* ws, hipStream_t st) {
   return RGSVD_OK;
 }
 
+// capacity of an adaptive basis: lmax (0: no cap) clamped to min(rows, n)
+// and to the largest supported width
+int64_t adaptive_cap(int64_t lmax, int64_t rows, int64_t n) {
+  int64_t c = std::min<int64_t>(rows, n);
+  if (lmax > 0) c = std::min(c, lmax);
+  return std::min<int64_t>(c, MAXL - 32);
+}
+
 int check_desc(const rgsvd_desc* d) {
   if (!d) return RGSVD_EINVAL;
   if (d->m < 1 || d->p < 1 || d->n < 1 || d->k < 1 || d->oversample < 0 || d->power_iters < 0)
@@ -605,6 +924,17 @@ int check_desc(const rgsvd_desc* d) {
     if (d->mode == RGSVD_FULL && 2 * l < d->n) return RGSVD_ENOTGMP;
     if (d->mode == RGSVD_TRUNCATED && d->k > l) return RGSVD_EINVAL;
     if (2 * l > SMALL_MAXN) return RGSVD_EUNSUPPORTED;
+  } else if (d->sizing == RGSVD_SIZE_ADAPTIVE) {
+    // Algorithm 1 with an absolute tolerance; FP64 arithmetic, truncated mode
+    if (!(d->tol > 0.0) || !std::isfinite(d->tol) || d->block < 0 || d->lmax < 0) return RGSVD_EINVAL;
+    if (d->precision != RGSVD_PREC_FP64 || d->mode != RGSVD_TRUNCATED) return RGSVD_EUNSUPPORTED;
+    if (d->k > adaptive_cap(d->lmax, d->m, d->n) || d->k > adaptive_cap(d->lmax, d->p, d->n))
+      return RGSVD_EINVAL;
+  } else if (d->sizing == RGSVD_SIZE_LEARNED) {
+    // the network picks l on a grid up to min(2k, capacity) and q <= 3
+    if (d->lmax < 0 || d->mode != RGSVD_TRUNCATED) return d->lmax < 0 ? RGSVD_EINVAL : RGSVD_EUNSUPPORTED;
+    if (d->k > adaptive_cap(d->lmax, d->m, d->n) || d->k > adaptive_cap(d->lmax, d->p, d->n))
+      return RGSVD_EINVAL;
   } else {
     return RGSVD_EUNSUPPORTED;
   }
@@ -625,11 +955,125 @@ PairLay pair_from(const rgsvd_desc* d) {
   pr.m = d->m; pr.p = d->p; pr.n = d->n; pr.k = d->k; pr.o = d->oversample; pr.q = d->power_iters;
   pr.seed = d->seed;
   pr.l1 = pr.l2 = (int)(d->k + d->oversample);
+  if (d->sizing == RGSVD_SIZE_ADAPTIVE || d->sizing == RGSVD_SIZE_LEARNED) {
+    pr.l1 = (int)adaptive_cap(d->lmax, d->m, d->n);
+    pr.l2 = (int)adaptive_cap(d->lmax, d->p, d->n);
+    pr.q = 0;
+  }
+  pr.l1cap = pr.l1; pr.l2cap = pr.l2;
   pr.t = (d->mode == RGSVD_FULL) ? (int)d->n : (int)d->k;
   return pr;
 }
 
 }  // namespace
+
+// Algorithm 1 on both matrices, block by block, then the shared tail.  The
+// stopping test needs the residual on the host, so the stream is
+// synchronised once after the norms and once per block.
+int run_adaptive(rgsvd_plan_s* P, void* ws, hipStream_t st) {
+  PairLay& pr = P->pairs[0];
+  std::vector<SideLay>& S = P->sides;
+  if (!P->hscal && hipHostMalloc((void**)&P->hscal, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return RGSVD_EHIP;
+  pr.l1 = pr.l1cap; pr.l2 = pr.l2cap;
+  for (auto& s : S) { s.lcur = 0; s.bcur = 0; s.active = true; }
+  auto stage_list = [&](rgsvd_plan_s::Part part) {
+    P->part = part;
+    int rc = build(P, ws);
+    P->part = rgsvd_plan_s::FIXED;
+    if (!rc) rc = upload(P, ws, st);
+    if (!rc) rc = enqueue(P, ws, st);
+    return rc;
+  };
+  auto fetch = [&](int word) {   // scal[word] of every side into hscal[side]
+    for (size_t i = 0; i < S.size(); ++i)
+      if (hipMemcpyAsync(P->hscal + i, (char*)ws + S[i].scal + 8 * word, 8, hipMemcpyDeviceToHost, st) != hipSuccess)
+        return RGSVD_EHIP;
+    return hipStreamSynchronize(st) == hipSuccess ? RGSVD_OK : RGSVD_EHIP;
+  };
+  int rc = stage_list(rgsvd_plan_s::A_INIT);
+  if (!rc) rc = fetch(0);
+  if (rc) return rc;
+  std::vector<double> g2(S.size()), esum(S.size(), 0.0);
+  for (size_t i = 0; i < S.size(); ++i) g2[i] = P->hscal[i];
+  const double eps = P->d.tol;
+  for (;;) {
+    bool any = false;
+    for (auto& s : S) {
+      if (!s.active) continue;
+      s.bcur = std::min(P->block, s.cap - s.lcur);
+      if (s.bcur <= 0) s.active = false; else any = true;
+    }
+    if (!any) break;
+    rc = stage_list(rgsvd_plan_s::A_BLOCK);
+    if (!rc) rc = fetch(1);
+    if (rc) return rc;
+    for (size_t i = 0; i < S.size(); ++i) {
+      auto& s = S[i];
+      if (!s.active) continue;
+      esum[i] += P->hscal[i];
+      s.lcur += s.bcur;
+      const double res = std::sqrt(std::max(0.0, g2[i] - esum[i]));
+      if (!(res >= eps) || s.lcur >= s.cap) s.active = false;
+    }
+  }
+  pr.l1 = S[0].lcur;
+  pr.l2 = S[1].lcur;
+  return stage_list(rgsvd_plan_s::TAIL);
+}
+
+// Probe stage list with every side at width 16 (their buffers hold more).
+int run_probe(rgsvd_plan_s* P, void* ws, hipStream_t st) {
+  for (auto& s : P->sides) { s.l = 16; s.L = 16; }
+  P->part = rgsvd_plan_s::PROBE;
+  int rc = build(P, ws);
+  P->part = rgsvd_plan_s::FIXED;
+  if (!rc) rc = upload(P, ws, st);
+  if (!rc) rc = enqueue(P, ws, st);
+  return rc;
+}
+
+// Sketch sizes from the network output (log2(l / k), q): the smallest l of
+// the grid {k+4, k+8, k+16, k+32, 2k} (capped) at or above k 2^y0, and q
+// rounded with a bias of 0.3 towards more passes, clamped to [0, 3].
+void decide_sizes(double y0, double y1, int k, int cap, int* l, int* q) {
+  int g[5] = {k + 4, k + 8, k + 16, k + 32, 2 * k};
+  std::vector<int> grid;
+  for (int v : g) { v = std::min(v, cap); if (v >= k) grid.push_back(v); }
+  std::sort(grid.begin(), grid.end());
+  grid.erase(std::unique(grid.begin(), grid.end()), grid.end());
+  const double want = k * std::exp2(std::isfinite(y0) ? std::min(y0, 8.0) : 8.0);
+  *l = grid.back();
+  for (int v : grid) if (v >= want) { *l = v; break; }
+  const double qq = std::floor((std::isfinite(y1) ? y1 : 3.0) + 0.8);
+  *q = (int)std::min(3.0, std::max(0.0, qq));
+}
+
+// Learned sizing: probe features and the network on the device, one read of
+// its two outputs, then the fixed-size run at the chosen (l, q).
+int run_learned(rgsvd_plan_s* P, void* ws, hipStream_t st) {
+  PairLay& pr = P->pairs[0];
+  if (!P->mlp) return RGSVD_ENOMODEL;
+  if (!P->hscal && hipHostMalloc((void**)&P->hscal, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
+    return RGSVD_EHIP;
+  int rc = run_probe(P, ws, st);
+  if (rc) return rc;
+  const float* yd = (const float*)((char*)ws + P->off_feat) + RGSVD_MLP_IN;
+  if (hipMemcpyAsync(P->hscal, yd, 2 * sizeof(float), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return RGSVD_EHIP;
+  const float* y = (const float*)P->hscal;
+  int l = 0, q = 0;
+  decide_sizes(y[0], y[1], (int)pr.k, std::min(pr.l1cap, pr.l2cap), &l, &q);
+  pr.l1 = pr.l2 = l;
+  pr.q = q;
+  for (auto& s : P->sides) { s.l = l; s.L = (int)upi(l, 16); }
+  P->part = rgsvd_plan_s::FIXED;
+  rc = build(P, ws);
+  if (!rc) rc = upload(P, ws, st);
+  if (!rc) rc = enqueue(P, ws, st);
+  return rc;
+}
 
 // ===================================================================== ABI ==
 extern "C" {
@@ -659,6 +1103,9 @@ int rgsvd_plan(const rgsvd_desc* desc, rgsvd_plan_t* plan, size_t* workspace_byt
   P->prec = desc->precision == RGSVD_PREC_FP64 ? P64 : (desc->precision == RGSVD_PREC_FP32 ? P32 : PBF);
   P->gdt = desc->in_dtype;
   P->mode = desc->mode;
+  P->adaptive = desc->sizing == RGSVD_SIZE_ADAPTIVE;
+  P->learned = desc->sizing == RGSVD_SIZE_LEARNED;
+  P->block = desc->block > 0 ? (int)desc->block : 100;
   P->pairs.push_back(pair_from(desc));
   P->wave_slots = device_wave_slots();
   rc = layout(P);
@@ -671,8 +1118,8 @@ int rgsvd_plan(const rgsvd_desc* desc, rgsvd_plan_t* plan, size_t* workspace_byt
 int rgsvd_plan_sizes(rgsvd_plan_t P, int64_t* t, int64_t* l1, int64_t* l2) {
   if (!P || P->pairs.empty()) return RGSVD_EINVAL;
   if (t) *t = P->pairs[0].t;
-  if (l1) *l1 = P->pairs[0].l1;
-  if (l2) *l2 = P->pairs[0].l2;
+  if (l1) *l1 = P->pairs[0].l1cap;
+  if (l2) *l2 = P->pairs[0].l2cap;
   return RGSVD_OK;
 }
 
@@ -686,6 +1133,20 @@ int rgsvd_run(rgsvd_plan_t P, const void* G1, int64_t ld1, const void* G2, int64
     return RGSVD_EINVAL;
   if (P->d.sizing == RGSVD_SIZE_LEARNED && !P->mlp) return RGSVD_ENOMODEL;
   hipStream_t st = (hipStream_t)stream;
+  if (P->adaptive) {
+    pr.out = *out;
+    P->sides[0].G = G1; P->sides[0].ldg = ld1;
+    P->sides[1].G = G2; P->sides[1].ldg = ld2;
+    P->bound = false;
+    return run_adaptive(P, workspace, st);
+  }
+  if (P->learned) {
+    pr.out = *out;
+    P->sides[0].G = G1; P->sides[0].ldg = ld1;
+    P->sides[1].G = G2; P->sides[1].ldg = ld2;
+    P->bound = false;
+    return run_learned(P, workspace, st);
+  }
   bool same = P->bound && P->lastG1 == G1 && P->lastG2 == G2 && P->lastws == workspace &&
               P->lastld1 == ld1 && P->lastld2 == ld2 && out_eq(P->lastout, *out);
   if (!same) {
@@ -710,6 +1171,7 @@ void rgsvd_destroy(rgsvd_plan_t P) {
   if (P->pinned) hipHostFree(P->pinned);
   if (P->gexec) hipGraphExecDestroy(P->gexec);
   if (P->mlp) hipFree(P->mlp);
+  if (P->hscal) hipHostFree(P->hscal);
   for (auto e : P->pev) hipEventDestroy(e);
   delete P;
 }
@@ -813,10 +1275,22 @@ extern "C" int rgsvd_set_sizing_model(rgsvd_plan_t P, const float* params, void*
                         (hipStream_t)stream) == hipSuccess ? RGSVD_OK : RGSVD_EHIP;
 }
 
-extern "C" int rgsvd_probe_features(const rgsvd_desc* desc, const void* G1, int64_t ld1, const void* G2,
-                                    int64_t ld2, float* feat, void* workspace, size_t workspace_bytes,
-                                    void* stream) {
-  (void)desc; (void)G1; (void)ld1; (void)G2; (void)ld2; (void)feat; (void)workspace;
-  (void)workspace_bytes; (void)stream;
-  return RGSVD_EUNSUPPORTED;
+extern "C" int rgsvd_probe_features(rgsvd_plan_t P, const void* G1, int64_t ld1, const void* G2, int64_t ld2,
+                                    void* workspace, float* feat, void* stream) {
+  if (!P || P->batched || !G1 || !G2 || !feat) return RGSVD_EINVAL;
+  if (!workspace || ((uintptr_t)workspace & (ALIGN - 1))) return RGSVD_EWORKSPACE;
+  PairLay& pr = P->pairs[0];
+  if (ld1 < pr.n || ld2 < pr.n) return RGSVD_EINVAL;
+  hipStream_t st = (hipStream_t)stream;
+  P->sides[0].G = G1; P->sides[0].ldg = ld1;
+  P->sides[1].G = G2; P->sides[1].ldg = ld2;
+  P->bound = false;
+  // restore the plan's own widths afterwards (the probe runs at width 16)
+  std::vector<std::pair<int, int>> keep;
+  for (auto& s : P->sides) keep.push_back({s.l, s.L});
+  int rc = run_probe(P, workspace, st);
+  for (size_t i = 0; i < P->sides.size(); ++i) { P->sides[i].l = keep[i].first; P->sides[i].L = keep[i].second; }
+  if (rc) return rc;
+  return hipMemcpyAsync(feat, (char*)workspace + P->off_feat, RGSVD_MLP_IN * sizeof(float),
+                        hipMemcpyDeviceToDevice, st) == hipSuccess ? RGSVD_OK : RGSVD_EHIP;
 }

@@ -52,9 +52,35 @@ struct GenJob {
 
 // Cholesky of an N x N SPD Gram (sum of partials already formed) and the
 // inverse of its lower factor: sinv = L^{-1} (lower, N_pad x N_pad).
+// shift0 > 0 adds shift0 * trace(Gram) to the diagonal from the start
+// (the first pass of shifted CholeskyQR).  trunc != 0: a row whose pivot is
+// below CHOL_TRUNC_REL times its original diagonal (numerically inside the
+// span of the rows before it) gets a zero row in L^{-1} instead of a restart.
 struct CholJob {
   const double* gram; double* sinv; double* r; int32_t* info;
-  int32_t N, npad, flagbit, pad;
+  int32_t N, npad, flagbit, trunc;
+  double shift0;
+};
+
+// Sum of squares of a rows x cols block (row stride ld, FP64 or FP32
+// elements): tile t of the job writes the partial of rows
+// [t*rpt, (t+1)*rpt) to part[t]; the finishing job adds the ntiles partials
+// in order into out[0].
+struct SumsqJob {
+  const void* X; int64_t ld;
+  int32_t rows, cols, f64, rpt;
+  double* part;
+};
+struct SumsqFin {
+  const double* part; double* out;
+  int32_t ntiles, pad;
+};
+
+// Probe features of one matrix: eigenvalues of its 16 x 16 probe Gram
+// (ld ldg) -> log10(sigma_j / sigma_1), floored, into out[0..15].
+struct FeatJob {
+  const double* gram; float* out;
+  int32_t ldg, pad;
 };
 
 }  // namespace rg

@@ -34,14 +34,16 @@ __device__ void chol_regs(const CholJob& J, double* lds) {
   __shared__ double piv_s, maxd_s;
   __shared__ int bad_s;
   double w[4][4];
+  __shared__ double trace_s;
   if (tid == 0) {
-    double md = 0.0;
-    for (int i = 0; i < N; ++i) md = fmax(md, J.gram[(int64_t)i * np + i]);
+    double md = 0.0, tr = 0.0;
+    for (int i = 0; i < N; ++i) { const double d = J.gram[(int64_t)i * np + i]; md = fmax(md, d); tr += d; }
     maxd_s = md;
+    trace_s = tr;
   }
   __syncthreads();
   const double maxdiag = maxd_s;
-  double shift = 0.0;
+  double shift = J.shift0 > 0.0 ? J.shift0 * trace_s : 0.0;
   bool shifted = false;
   for (int attempt = 0;; ++attempt) {
 #pragma unroll
@@ -70,6 +72,20 @@ __device__ void chol_regs(const CholJob& J, double* lds) {
       __syncthreads();
       const double piv = piv_s;
       const double d0k = J.gram[(int64_t)k * np + k];
+      if (J.trunc && isfinite(piv) && !(piv > CHOL_TRUNC_REL * d0k && piv > 0.0)) {
+        // row k is numerically dependent on the rows before it: zero row of
+        // L^{-1}, no elimination step
+        if (ty == ok_) {
+#pragma unroll
+          for (int a = 0; a < 4; ++a)
+            if (a == ak)
+#pragma unroll
+              for (int b = 0; b < 4; ++b) w[a][b] = 0.0;
+        }
+        if (tid == 0) xd[k] = 0.0;
+        __syncthreads();
+        continue;
+      }
       if (!(piv > 1e-15 * d0k) || !(piv > 0.0) || !isfinite(piv)) { if (tid == 0) bad_s = 1; break; }
       const double d = sqrt(piv), rd = 1.0 / d;
       // owners of row k scale it and publish it
@@ -145,10 +161,14 @@ __device__ void chol_global(const CholJob& J, double* W, double* xd, double* d0)
   __shared__ double shift;
   __shared__ int shifted;
   const int tid = threadIdx.x;
-  if (tid == 0) { shift = 0.0; shifted = 0; }
+  double maxdiag = 0.0, trace = 0.0;
+  for (int i = 0; i < N; ++i) {
+    const double d = J.gram[(int64_t)i * np + i];
+    maxdiag = fmax(maxdiag, d);
+    trace += d;
+  }
+  if (tid == 0) { shift = J.shift0 > 0.0 ? J.shift0 * trace : 0.0; shifted = 0; }
   __syncthreads();
-  double maxdiag = 0.0;
-  for (int i = 0; i < N; ++i) maxdiag = fmax(maxdiag, J.gram[(int64_t)i * np + i]);
   int attempt = 0;
   for (;;) {
     for (int e = tid; e < np * np; e += 1024) {
@@ -167,7 +187,14 @@ __device__ void chol_global(const CholJob& J, double* W, double* xd, double* d0)
     __syncthreads();
     const int tx = tid & 31, ty = tid >> 5;
     for (int k = 0; k < N; ++k) {
-      double piv = W[k * np + k];
+      const double piv = W[k * np + k];
+      __syncthreads();   // every thread holds the pivot before row k is rescaled
+      if (J.trunc && isfinite(piv) && !(piv > CHOL_TRUNC_REL * d0[k] && piv > 0.0)) {
+        for (int j = tid; j < np; j += 1024) W[k * np + j] = 0.0;
+        if (tid == 0) xd[k] = 0.0;
+        __syncthreads();
+        continue;
+      }
       bool brk = !(piv > 1e-15 * d0[k]) || !(piv > 0.0) || !isfinite(piv);
       if (brk) { if (tid == 0) bad = 1; break; }
       double d = sqrt(piv), rd = 1.0 / d;

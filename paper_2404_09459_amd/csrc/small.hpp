@@ -8,6 +8,7 @@ constexpr int CHOL_LDS_MAX = 128;   // Gram orders kept in LDS by k_chol
 constexpr int CHOL_MAX = 256;       // largest padded Gram order
 constexpr int SMALL_MAXN = 512;     // largest l1 + l2 of the compressed pair
 constexpr double BETA_ZERO = 1e-14;
+constexpr double CHOL_TRUNC_REL = 1e-10;   // truncated Cholesky: pivot / original diagonal
 constexpr size_t SMALL_LDS_BYTES = 80000;   // dynamic LDS of k_small: Jacobi factors up to 10000 entries
 
 // flag bits of info[4] (same values as the public header)

@@ -83,9 +83,8 @@ EXPORTS = {
                                       ctypes.c_void_p, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
                                       ctypes.c_float, ctypes.c_float, ctypes.c_void_p]),
     "rgsvd_set_sizing_model": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
-    "rgsvd_probe_features": (ctypes.c_int, [ctypes.POINTER(Desc), ctypes.c_void_p, ctypes.c_int64,
-                                            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
-                                            ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "rgsvd_probe_features": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                            ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rgsvd_gaussian": (ctypes.c_int, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int64, ctypes.c_int64,
                                       ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                       ctypes.c_void_p]),
@@ -210,9 +209,15 @@ def run(plan, G1, G2, o):
 _PLANS = {}
 
 
-def rgsvd(G1, G2, k, oversample, q, seed, precision="fp64", mode="truncated", uvr=True):
+def rgsvd(G1, G2, k, oversample, q, seed, precision="fp64", mode="truncated", uvr=True,
+          sizing="fixed", tol=0.0, block=0, lmax=0):
     """Randomized GSVD of the device pair (G1, G2); returns a dict of device
-    tensors: alpha, beta, theta, P1, P2, D, sigma_B, info and (uvr) U, V, R."""
+    tensors: alpha, beta, theta, P1, P2, D, sigma_B, info and (uvr) U, V, R.
+
+    sizing="adaptive" builds each basis by Algorithm 1 (blocks of `block`
+    columns, default 100, until the residual ||(I - QQ^T) G||_F < tol, at
+    most `lmax` columns); `oversample` and `q` are then unused, the widths
+    reached are info[1], info[2] and sigma_B holds info[1] + info[2] values."""
     torch = _torch()
     if G1.dtype != G2.dtype or G1.dtype not in (torch.float64, torch.float32):
         raise ValueError("G1, G2 must both be float64 or float32")
@@ -221,10 +226,11 @@ def rgsvd(G1, G2, k, oversample, q, seed, precision="fp64", mode="truncated", uv
     m, n = G1.shape
     p = G2.shape[0]
     dt = F64 if G1.dtype == torch.float64 else F32
-    key = (m, p, n, k, oversample, q, seed, dt, precision, mode, G1.device.index)
+    key = (m, p, n, k, oversample, q, seed, dt, precision, mode, sizing, tol, block, lmax, G1.device.index)
     plan = _PLANS.get(key)
     if plan is None:
-        plan = Plan(make_desc(m, p, n, k, oversample, q, seed, dt, precision, "fixed", mode), G1.device)
+        plan = Plan(make_desc(m, p, n, k, oversample, q, seed, dt, precision, sizing, mode, tol, block, lmax),
+                    G1.device)
         _PLANS[key] = plan
     o = alloc_outputs(plan.t, m, p, n, plan.l1 + plan.l2, G1.device, uvr)
     run(plan, G1, G2, o)

@@ -1,0 +1,198 @@
+"""Learned sketch sizing: probe features, labels from the method itself, and
+training of the 32-64-64-2 network with the library's own HIP kernels.
+
+The network reads the 32 probe features of a pair (log10 of the normalised
+singular values of G_i Omega[:, :16], i = 1, 2) and regresses
+(log2(l / k), q): the sketch width relative to the target rank and the power
+count.  A pair's label is the cheapest point of the grid
+l in {k+4, k+8, k+16, k+32, 2k} x q in {0..3} (fewest passes over G, then the
+smallest l) at which the production (mixed-precision) run meets the angular
+tolerance against a converged FP64 run of the same method
+(l_ref = min(2k + 50, cap), q_ref = 4) on the pairs whose weaker component
+is above the noise floor.  The network is not in the paper.
+"""
+import ctypes
+import math
+
+import numpy as np
+
+from . import inputs as I
+from . import rgsvd as R
+
+GRID_Q = (0, 1, 2, 3)
+TOL_THETA = 1e-4
+
+
+def _torch():
+    import torch
+    return torch
+
+
+# ------------------------------------------------------------ features ---
+def probe_features(G1, G2, seed, precision="fp64"):
+    """32 probe features of a device pair (float32 device tensor)."""
+    torch = _torch()
+    m, n = G1.shape
+    p = G2.shape[0]
+    dt = R.F64 if G1.dtype == torch.float64 else R.F32
+    plan = R.Plan(R.make_desc(m, p, n, 1, 0, 0, seed, dt, precision), G1.device)
+    feat = torch.empty(32, dtype=torch.float32, device=G1.device)
+    R.check(R.lib().rgsvd_probe_features(plan.h, R._ptr(G1), G1.stride(0), R._ptr(G2), G2.stride(0),
+                                         plan.ws_ptr, R._ptr(feat), R._stream(G1.device)), "probe_features")
+    torch.cuda.current_stream(G1.device).synchronize()
+    del plan
+    return feat
+
+
+# ----------------------------------------------------------------- MLP ---
+def init_params(seed, device):
+    """He-initialised packed parameters (W[out][in] row-major per layer)."""
+    torch = _torch()
+    rng = np.random.default_rng(seed)
+    dims = (32, 64, 64, 2)
+    parts = []
+    for i in range(3):
+        fi, fo = dims[i], dims[i + 1]
+        parts.append(rng.standard_normal(fo * fi) * math.sqrt(2.0 / fi) * (0.5 if i == 2 else 1.0))
+        parts.append(np.zeros(fo))
+    return torch.tensor(np.concatenate(parts), dtype=torch.float32, device=device)
+
+
+def mlp_forward(params, X):
+    torch = _torch()
+    X = X.contiguous()
+    B = X.shape[0]
+    Y = torch.empty((B, 2), dtype=torch.float32, device=X.device)
+    act = torch.empty((B, 128), dtype=torch.float32, device=X.device)
+    R.check(R.lib().rgsvd_mlp_forward(R._ptr(params), R._ptr(X), B, R._ptr(Y), R._ptr(act),
+                                      R._stream(X.device)), "mlp_forward")
+    return Y, act
+
+
+def mlp_backward(params, X, T, act):
+    torch = _torch()
+    B = X.shape[0]
+    g = torch.empty_like(params)
+    loss = torch.empty(1, dtype=torch.float32, device=X.device)
+    R.check(R.lib().rgsvd_mlp_backward(R._ptr(params), R._ptr(X.contiguous()), R._ptr(T.contiguous()), B,
+                                       R._ptr(act), R._ptr(g), R._ptr(loss), R._stream(X.device)),
+            "mlp_backward")
+    return g, loss
+
+
+def adam(params, g, mom, vel, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    R.check(R.lib().rgsvd_mlp_adam(R._ptr(params), R._ptr(g), R._ptr(mom), R._ptr(vel), step,
+                                   ctypes.c_float(lr), ctypes.c_float(b1), ctypes.c_float(b2),
+                                   ctypes.c_float(eps), R._stream(params.device)), "mlp_adam")
+
+
+def train(X, T, device, epochs=400, lr=3e-3, seed=0):
+    """Full-batch Adam on (X, T) (device float32); returns params, losses."""
+    torch = _torch()
+    params = init_params(seed, device)
+    mom = torch.zeros_like(params)
+    vel = torch.zeros_like(params)
+    losses = []
+    for step in range(1, epochs + 1):
+        _, act = mlp_forward(params, X)
+        g, loss = mlp_backward(params, X, T, act)
+        adam(params, g, mom, vel, step, lr=lr)
+        if step % 50 == 0 or step == 1:
+            losses.append(float(loss.item()))
+    return params, losses
+
+
+# --------------------------------------------------------------- pairs ---
+def pair_specs(npairs, seed, m_range=(500, 3000), n_range=(100, 400), r_range=(5, 40),
+               d_range=(0.5, 0.99), nu_range=(1e-6, 1e-2)):
+    """Training / held-out pairs shaped like the learned-sizing workload
+    (scaled down): shared rank r, decays d1, d2, spectral noise floor nu
+    (log-uniform); k = the number of shared components above 10 nu (>= 2)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(npairs):
+        m = int(rng.integers(m_range[0], m_range[1] + 1))
+        p = int(rng.integers(m_range[0], m_range[1] + 1))
+        n = int(rng.integers(n_range[0], n_range[1] + 1))
+        r = int(rng.integers(r_range[0], min(r_range[1], n // 4) + 1))
+        d1 = float(rng.uniform(*d_range))
+        d2 = float(rng.uniform(*d_range))
+        nu = float(np.exp(rng.uniform(np.log(nu_range[0]), np.log(nu_range[1]))))
+        j = np.arange(r)
+        mag = np.minimum(d1 ** j, d2 ** j)
+        k = int(max(2, min(r, np.sum(mag >= 10 * nu))))
+        out.append(dict(m=m, p=p, n=n, r=r, d1=d1, d2=d2, nu=nu, k=k, seed=seed * 7919 + i))
+    return out
+
+
+def make_pair(spec):
+    j = np.arange(spec["r"])
+    return I.lowrank_pair(spec["m"], spec["p"], spec["n"], spec["r"], spec["d1"] ** j, spec["d2"] ** j,
+                          spec["seed"], noise_spectral=spec["nu"], dtype=np.float32)
+
+
+def _pinned(ref, k, nu):
+    s = ref["sigma_B"]
+    weak = np.minimum(ref["alpha"], ref["beta"]) * np.linalg.norm(ref["R"], axis=1)
+    if len(s) > k and s[k - 1] < 2 * s[k]:
+        return np.arange(0)
+    return np.where(weak >= 10 * nu)[0]
+
+
+def _run(g1, g2, k, l, q, seed, precision):
+    """One fixed-size run with a plan of its own (freed afterwards)."""
+    torch = _torch()
+    m, n = g1.shape
+    p = g2.shape[0]
+    dt = R.F64 if g1.dtype == torch.float64 else R.F32
+    plan = R.Plan(R.make_desc(m, p, n, k, l - k, q, seed, dt, precision), g1.device)
+    o = R.alloc_outputs(plan.t, m, p, n, plan.l1 + plan.l2, g1.device, uvr=(precision == "fp64"))
+    R.run(plan, g1, g2, o)
+    torch.cuda.synchronize()
+    out = {kk: v.cpu().numpy() for kk, v in o.items() if kk not in ("Ut", "Vt")}
+    del plan
+    return out
+
+
+def l_grid(k, cap):
+    return sorted({v for v in (min(cap, x) for x in (k + 4, k + 8, k + 16, k + 32, 2 * k)) if v >= k})
+
+
+def passes(got, ref, idx):
+    if len(idx) == 0:
+        return True
+    return float(np.max(np.abs(got["theta"][idx] - ref["theta"][idx]))) <= TOL_THETA
+
+
+def label(g1, g2, spec, seed=1, precision="mixed"):
+    """(l, q, reference) of a device pair: the cheapest passing grid point."""
+    k, nu = spec["k"], spec["nu"]
+    cap = min(spec["m"], spec["p"], spec["n"], 224)
+    lref = min(2 * k + 50, cap)
+    ref = _run(g1, g2, k, lref, 4, seed, "fp64")
+    idx = _pinned(ref, k, nu)
+    grid = l_grid(k, cap)
+    for q in GRID_Q:
+        for l in grid:
+            if passes(_run(g1, g2, k, l, q, seed, precision), ref, idx):
+                return l, q, ref, idx
+    return grid[-1], GRID_Q[-1], ref, idx
+
+
+def cost(spec, l, q):
+    """Passes over G (2q + 2), the HBM-bound cost of a run."""
+    return 2 * q + 2
+
+
+def targets(k, l, q):
+    return (math.log2(l / k), float(q))
+
+
+def decide(y, k, cap):
+    """Same rounding as the library: the smallest grid l at or above
+    k 2^y0; q = floor(y1 + 0.8) clamped to [0, 3]."""
+    grid = l_grid(k, cap)
+    want = k * 2.0 ** min(float(y[0]), 8.0)
+    l = next((v for v in grid if v >= want), grid[-1])
+    q = int(min(3, max(0, math.floor(float(y[1]) + 0.8))))
+    return l, q

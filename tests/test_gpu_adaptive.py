@@ -1,0 +1,73 @@
+"""Adaptive sizing (Algorithm 1 with the residual test) on the GPU against the
+oracle's Algorithm 1: the same widths l1, l2 (the residual decisions sit far
+from the tolerance) and, on the resulting bases, the compressed GSVD to 1e-10
+(FP64 arithmetic).  The exactly low-rank pair crosses its rank inside a block,
+where the projected block is rank deficient."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_09459_amd import rgsvd as R
+    R.lib()
+    return torch.device("cuda:0")
+
+
+def _noisy(dtype):
+    from paper_2404_09459_amd import inputs as I
+    j = np.arange(80)
+    return I.lowrank_pair(1500, 1200, 400, 80, 0.93 ** j, 0.9 ** j, 42, noise_entry=1e-9, dtype=dtype)
+
+
+def _exact():
+    from paper_2404_09459_amd import inputs as I
+    j = np.arange(20)
+    return I.lowrank_pair(700, 600, 200, 20, 0.8 ** j, 0.7 ** j, 43)
+
+
+@pytest.mark.parametrize("case,k,eps,b,lmax,dt,l_expect", [
+    ("noisy", 40, 1e-4, 16, 0, np.float64, (80, 80)),
+    ("noisy", 40, 3e-2, 16, 0, np.float32, (80, 64)),
+    ("exact", 20, 1e-6, 16, 64, np.float64, (32, 32)),
+])
+def test_adaptive_matches_algorithm1(dev, case, k, eps, b, lmax, dt, l_expect):
+    from oracle import rgsvd as O
+    from paper_2404_09459_amd import rgsvd as R
+    G1, G2 = _noisy(dt) if case == "noisy" else _exact()
+    _say(f"adaptive {case} {G1.shape}/{G2.shape[0]} k={k} eps={eps} b={b} lmax={lmax} dtype={G1.dtype}")
+    seed = 5
+    g1 = torch.from_numpy(G1).to(dev)
+    g2 = torch.from_numpy(G2).to(dev)
+    got = R.rgsvd(g1, g2, k, 0, 0, seed, sizing="adaptive", tol=eps, block=b, lmax=lmax)
+    torch.cuda.synchronize()
+    got = {kk: v.cpu().numpy() for kk, v in got.items()}
+    G1d, G2d = G1.astype(np.float64), G2.astype(np.float64)
+    Q1, h1 = O.basis_adaptive(G1d, eps, b, seed, 1, lmax=lmax or None)
+    Q2, h2 = O.basis_adaptive(G2d, eps, b, seed, 2, lmax=lmax or None)
+    ref = O.finish(G1d, G2d, Q1, Q2, k)
+    l1, l2 = int(got["info"][1]), int(got["info"][2])
+    da = np.max(np.abs(got["alpha"] - ref["alpha"]))
+    db = np.max(np.abs(got["beta"] - ref["beta"]))
+    dth = np.max(np.abs(got["theta"] - ref["theta"]))
+    dd = np.max(np.abs(got["D"] - [ref["D1"], ref["D2"]]))
+    ds = np.max(np.abs(got["sigma_B"][:k] - ref["sigma_B"][:k]))
+    _say(f"   widths gpu ({l1}, {l2}) oracle ({Q1.shape[1]}, {Q2.shape[1]}); residuals {h1[-1]:.2e} {h2[-1]:.2e};"
+         f" |da|={da:.1e} |db|={db:.1e} |dtheta|={dth:.1e} |dD|={dd:.1e} |dsigma|={ds:.1e}"
+         f" info={got['info'].tolist()}")
+    assert (l1, l2) == (Q1.shape[1], Q2.shape[1]) == l_expect
+    assert max(da, db, dth, dd) <= 1e-10
+    assert ds <= 1e-10 * ref["sigma_B"][0]

@@ -54,3 +54,45 @@ def test_training_reduces_loss():
     for s in range(1, 201):
         th, m, v = mlp.adam_step(th, mlp.grad(th, X, T), m, v, s, 3e-3)
     assert mlp.loss(th, X, T) < 0.2 * l0
+
+
+# ------------------------------------------------------- sizing features ---
+def test_probe_features_scale_invariant_and_rank_revealing():
+    """log10(sigma_j / sigma_1) of the probe sketch: unchanged by scaling G,
+    first entry 0, non-increasing, and a rank-r matrix (r < 16) shows a drop
+    to the floor region after r values (the probe sketch has rank r)."""
+    from oracle.sizing import features
+    rng = np.random.default_rng(3)
+    m, n, r = 300, 120, 6
+    G1 = rng.standard_normal((m, r)) @ rng.standard_normal((r, n))
+    G2 = rng.standard_normal((250, n))
+    f = features(G1, G2, 9)
+    f2 = features(7.5 * G1, 0.01 * G2, 9)
+    assert f.shape == (32,)
+    live = f > -8                        # entries above the floor
+    assert np.array_equal(live, f2 > -8)
+    assert np.allclose(f[live], f2[live], atol=1e-12)
+    assert f[0] == 0.0 and f[16] == 0.0
+    assert np.all(np.diff(f[:16]) <= 1e-12) and np.all(np.diff(f[16:]) <= 1e-12)
+    assert f[r - 1] > -3 and np.all(f[r:16] == -8.0)    # rank 6: the rest is at the floor
+    assert np.all(f[16:] > -3)                           # full-rank Gaussian G2
+
+
+def test_probe_spectrum_of_orthonormal_rows_is_gaussian_block():
+    """For G with orthonormal rows spanning R^n (G = I_n), G Omega16 is the
+    Gaussian block itself, so the probe spectrum equals its singular values."""
+    from oracle.philox import gaussian_matrix
+    from oracle.sizing import probe_spectrum
+    n = 64
+    s = probe_spectrum(np.eye(n), 4, 1)
+    ref = np.linalg.svd(gaussian_matrix(4, 1, n, 0, 16), compute_uv=False)
+    assert np.allclose(s, ref, rtol=1e-13)
+
+
+def test_decide_rounds_up_to_grid():
+    from oracle.sizing import decide, l_grid
+    assert l_grid(20, 1000) == [24, 28, 36, 40, 52]
+    assert decide([0.0, 0.0], 20, 1000) == (24, 0)
+    assert decide([np.log2(30 / 20), 1.3], 20, 1000) == (36, 2)
+    assert decide([5.0, 9.0], 20, 1000) == (52, 3)
+    assert decide([0.5, -2.0], 20, 30) == (30, 0)
