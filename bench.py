@@ -85,6 +85,7 @@ def main():
     ap.add_argument("--precisions", default="mixed,fp32,fp64")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--cpu-reps", type=int, default=3)
+    ap.add_argument("--no-tune", action="store_true", help="skip the tile-shape autotuner")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain elementwise copy of MIB MiB (read + write) for "
                          "calibrating hardware byte counters")
@@ -117,6 +118,12 @@ def main():
     for prec in precs:
         plan = R.Plan(R.make_desc(m, p, n, k, o, q, seed, R.F64 if esz == 8 else R.F32, prec), dev)
         outs = R.alloc_outputs(plan.t, m, p, n, plan.l1 + plan.l2, dev, uvr=True)
+        tune = None
+        if not args.no_tune:
+            choice, tms = R.autotune(plan, G1, G2, outs, reps=2)
+            tune = {"rows_per_tile": choice[0], "cols_per_lane": choice[1],
+                    "chunks": ["heuristic", "half", "twice"][choice[2]], "ms": tms}
+            log(f"[bench] {prec}: autotuned tile shapes {tune}")
         for _ in range(args.warmup):
             R.run(plan, G1, G2, outs)
         torch.cuda.synchronize()
@@ -144,7 +151,7 @@ def main():
             a[1] += 1
         sketch_ms = next(t for tag, t in stages if tag == "nn")
         res[prec] = dict(ms=ms, stages=agg, sketch_ms=sketch_ms, got=got,
-                         info=got["info"].tolist())
+                         info=got["info"].tolist(), tune=tune)
         log(f"[bench] {prec}: {ms:.3f} ms/pair ({1000 / ms:.1f} pairs/s); sketch {sketch_ms:.3f} ms;"
             f" info {got['info'].tolist()}")
         log("[bench]   stages: " + ", ".join(f"{kk}={v[0]:.3f}ms/{v[1]}" for kk, v in
@@ -196,7 +203,7 @@ def main():
             e = errors(r["got"], ref, idx)
         paths[prec] = {"pairs_per_s": 1000.0 / r["ms"], "ms_per_pair": r["ms"],
                        "sketch_tflops": sk_flops / (r["sketch_ms"] * 1e-3) / 1e12,
-                       "errors_vs_oracle": e, "info": r["info"],
+                       "errors_vs_oracle": e, "info": r["info"], "autotune": r["tune"],
                        "stage_ms": {kk: round(v[0], 4) for kk, v in r["stages"].items()}}
     # dominant kernel of the headline path, priced against its own roofline
     agg = res[flag]["stages"]

@@ -199,6 +199,26 @@ int rgsvd_batch_bind(rgsvd_plan_t plan, const rgsvd_pair_io* io, void* workspace
 /* Replay the bound batch on `stream` (graph launch). */
 int rgsvd_batch_run(rgsvd_plan_t plan, void* stream);
 
+/* ---------------------------------------------------------- autotuner --- */
+/* Tile shapes of the streaming kernels chosen by measurement on the caller's
+ * data:
+ * rows per tile of the G W kernel (1 or 4), columns per lane of the G^T Q
+ * kernel (2 or 4) and the number of row chunks of its split reduction (the
+ * heuristic count, half, twice).  Each valid combination is enqueued
+ * reps + 1 times on `stream` (outputs are written, one warm-up) and timed
+ * with HIP events; the fastest is kept in the plan and in a per-process cache
+ * keyed by the plan's shapes, storage type and precision, which later plans
+ * of the same key start from.  choice (3 int32, may be NULL): rt, js, chunk
+ * index (0 heuristic, 1 half, 2 twice); best_ms (may be NULL): mean run time
+ * of the choice.  Synchronises `stream`.  Fixed-size plans only.
+ * rgsvd_batch_autotune takes the batch's pointers like rgsvd_batch_bind and
+ * must be followed by rgsvd_batch_bind (which captures with the choice). */
+int rgsvd_autotune(rgsvd_plan_t plan, const void* G1, int64_t ld1, const void* G2, int64_t ld2,
+                   void* workspace, void* stream, const rgsvd_out* out, int32_t reps, int32_t* choice,
+                   float* best_ms);
+int rgsvd_batch_autotune(rgsvd_plan_t plan, const rgsvd_pair_io* io, void* workspace, void* stream,
+                         int32_t reps, int32_t* choice, float* best_ms);
+
 /* ---------------------------------------------------- sizing network ---- */
 /* 32-64-64-2 ReLU MLP in FP32.  Parameter layout: W1 (64x32), b1 (64),
  * W2 (64x64), b2 (64), W3 (2x64), b3 (2), row-major W[out][in],

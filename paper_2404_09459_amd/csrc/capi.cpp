@@ -18,7 +18,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "../../include/rgsvd.h"
@@ -78,6 +80,7 @@ struct SideLay {
   size_t Ot = 0, scal = 0, spart = 0;
   int cap = 0, lcur = 0, bcur = 0, gtiles = 0;
   bool active = false;
+  int nchunk0 = 1, nchunk_max = 1;   // heuristic and largest row-chunk counts of G^T Q
 };
 
 struct PairLay {
@@ -108,6 +111,9 @@ struct rgsvd_plan_s {
   size_t off_feat = 0;      // probe features (32 floats), network output (2), activations (128)
   int block = 100;
   double* hscal = nullptr;   // pinned host copy of the per-side scalars
+  // tile-shape knobs of the streaming kernels (0: heuristic); set by the
+  // autotuner or taken from its per-shape cache
+  int tune_rt = 0, tune_js = 0, tune_chunk = 0;
   int wave_slots = 2048;   // concurrently resident single-wave workgroups
   // job tables
   std::vector<unsigned char> host;   // serialized job tables
@@ -171,6 +177,8 @@ int layout(rgsvd_plan_s* P) {
       int mch = (int)upi((s.m + nch - 1) / nch, 32);
       nch = (s.m + mch - 1) / mch;
       s.nchunk = nch; s.mchunk = mch;
+      s.nchunk0 = nch;
+      s.nchunk_max = std::max(1, std::min(2 * nch, (s.m + 31) / 32));
       // Gram chunks over m and over n
       int nb = P->npadG / 64, nblk = nb * (nb + 1) / 2;
       int gt = std::max(1, 512 / std::max(1, nblk * nsides));
@@ -186,7 +194,7 @@ int layout(rgsvd_plan_s* P) {
         s.Yt16 = take((size_t)s.L * s.ldy * 2);
         s.Wt16 = take((size_t)s.L * s.ldw * 2);
       }
-      s.part = take((size_t)s.nchunk * s.L * s.ldw * psz);
+      s.part = take((size_t)s.nchunk_max * s.L * s.ldw * psz);
       int gch = std::max(s.gch_m, s.gch_n);
       s.gpart = take((size_t)gch * P->npadG * P->npadG * 8);
       s.gram = take((size_t)P->npadG * P->npadG * 8);
@@ -226,7 +234,7 @@ int layout(rgsvd_plan_s* P) {
   if (P->npadG > 128) P->nchol_slots = nsides;
   P->off_chol = take((size_t)std::max(1, P->nchol_slots) * (CHOL_MAX * CHOL_MAX + 2 * CHOL_MAX) * 8);
   // job area: generous bound
-  size_t per_side = 64 * 1024 + (size_t)(P->sides.empty() ? 0 : P->sides[0].nchunk) * 256;
+  size_t per_side = 64 * 1024 + (size_t)(P->sides.empty() ? 0 : P->sides[0].nchunk_max) * 256;
   P->jobs_cap = up(per_side * nsides + 256 * 1024, ALIGN);
   P->off_jobs = take(P->jobs_cap);
   P->ws = off;
@@ -274,6 +282,14 @@ int build(rgsvd_plan_s* P, void* ws) {
   const int ctL = ct_of([&] { int L = 16; for (auto& s : P->sides) L = std::max(L, s.L); return L; }());
   std::vector<SideLay>& S = P->sides;
   const int ns = (int)S.size();
+  // row chunks of the G^T Q reductions: heuristic, half or twice as many
+  for (auto& s : S) {
+    int nch = s.nchunk0;
+    if (P->tune_chunk == 1) nch = std::max(1, nch / 2);
+    if (P->tune_chunk == 2) nch = std::min(s.nchunk_max, 2 * nch);
+    s.mchunk = (int)upi((s.m + nch - 1) / nch, 32);
+    s.nchunk = (s.m + s.mchunk - 1) / s.mchunk;
+  }
 
   const auto part = P->part;
   const bool head = (part == rgsvd_plan_s::FIXED || part == rgsvd_plan_s::A_INIT);
@@ -409,7 +425,8 @@ int build(rgsvd_plan_s* P, void* ws) {
   auto add_nn = [&](int p) {
     if (p == PBF) add_cvt(false);
     std::vector<NnJob> j; std::vector<int> tl;
-    int rt = (p == P64 || gt == 0 || ctL > 8) ? 1 : 4;
+    const bool rt4_ok = !(p == P64 || gt == 0 || ctL > 8);
+    int rt = P->tune_rt ? (P->tune_rt == 4 && rt4_ok ? 4 : 1) : (rt4_ok ? 4 : 1);
     for (auto& s : S) {
       NnJob x{};
       x.G = s.G; x.Wt = WS(ws, p == PBF ? s.Wt16 : s.Wt); x.Yt = WS(ws, s.Yt);
@@ -470,7 +487,8 @@ int build(rgsvd_plan_s* P, void* ws) {
     if (p == PBF) add_cvt(true);
     std::vector<AbJob> aj; std::vector<int> atl;
     std::vector<RedJob> rj; std::vector<int> rtl;
-    const int js = (p == P64 || gt == 0 || ctL > 8) ? 2 : 4;
+    const bool js4_ok = !(p == P64 || gt == 0 || ctL > 8);
+    const int js = P->tune_js ? (P->tune_js == 4 && js4_ok ? 4 : 2) : (js4_ok ? 4 : 2);
     const size_t psz = (prec == P64) ? 8 : 4;
     const size_t asz = (p == P64) ? 8 : (p == P32 ? 4 : 2);
     for (auto& s : S) {
@@ -1075,6 +1093,70 @@ int run_learned(rgsvd_plan_s* P, void* ws, hipStream_t st) {
   return rc;
 }
 
+// --------------------------------------------------------------- autotune --
+// Tile shapes of the streaming kernels, chosen by timing: rows per tile of
+// the G W kernel (1 or 4), columns per lane of the G^T Q kernel (2 or 4) and
+// the number of row chunks its reduction is split over (the heuristic count,
+// half of it or twice it).  Every valid combination runs `reps` times after
+// one warm-up with HIP events around the enqueued stages; the fastest total
+// wins and is remembered for the plan's shape key.
+struct TuneChoice { int rt, js, chunk; float ms; };
+std::map<std::string, TuneChoice>& tune_cache() {
+  static std::map<std::string, TuneChoice> c;
+  return c;
+}
+
+std::string shape_key(const rgsvd_plan_s* P) {
+  std::string k = std::to_string(P->prec) + "/" + std::to_string(P->gdt) + "/" + std::to_string(P->batched);
+  for (auto& pr : P->pairs)
+    k += ":" + std::to_string(pr.m) + "," + std::to_string(pr.p) + "," + std::to_string(pr.n) + "," +
+         std::to_string(pr.l1) + "," + std::to_string(pr.l2) + "," + std::to_string(pr.q);
+  return k;
+}
+
+void apply_cached_tune(rgsvd_plan_s* P) {
+  auto it = tune_cache().find(shape_key(P));
+  if (it == tune_cache().end()) return;
+  P->tune_rt = it->second.rt; P->tune_js = it->second.js; P->tune_chunk = it->second.chunk;
+}
+
+int autotune_plan(rgsvd_plan_s* P, void* ws, hipStream_t st, int reps, int32_t* choice, float* best_ms) {
+  const bool streamy = P->prec != P64 && P->gdt == RGSVD_F32;
+  std::vector<int> rts = streamy ? std::vector<int>{1, 4} : std::vector<int>{1};
+  std::vector<int> jss = streamy ? std::vector<int>{2, 4} : std::vector<int>{2};
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RGSVD_EHIP;
+  TuneChoice best{0, 0, 0, 1e30f};
+  int rc = RGSVD_OK;
+  for (int rt : rts)
+    for (int js : jss)
+      for (int ch = 0; ch < 3 && !rc; ++ch) {
+        P->tune_rt = rt; P->tune_js = js; P->tune_chunk = ch;
+        P->part = rgsvd_plan_s::FIXED;
+        rc = build(P, ws);
+        if (!rc) rc = upload(P, ws, st);
+        if (!rc) rc = enqueue(P, ws, st);   // warm-up
+        if (rc) break;
+        hipEventRecord(e0, st);
+        for (int r = 0; r < reps && !rc; ++r) rc = enqueue(P, ws, st);
+        hipEventRecord(e1, st);
+        if (rc || hipEventSynchronize(e1) != hipSuccess) { rc = rc ? rc : RGSVD_EHIP; break; }
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= (float)std::max(1, reps);
+        if (ms < best.ms) best = TuneChoice{rt, js, ch, ms};
+      }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  P->tune_rt = best.rt; P->tune_js = best.js; P->tune_chunk = best.chunk;
+  tune_cache()[shape_key(P)] = best;
+  P->bound = false;
+  if (choice) { choice[0] = best.rt; choice[1] = best.js; choice[2] = best.chunk; }
+  if (best_ms) *best_ms = best.ms;
+  return RGSVD_OK;
+}
+
 // ===================================================================== ABI ==
 extern "C" {
 
@@ -1110,6 +1192,7 @@ int rgsvd_plan(const rgsvd_desc* desc, rgsvd_plan_t* plan, size_t* workspace_byt
   P->wave_slots = device_wave_slots();
   rc = layout(P);
   if (rc) { delete P; return rc; }
+  apply_cached_tune(P);
   *plan = P;
   *workspace_bytes = P->ws;
   return RGSVD_OK;
@@ -1219,6 +1302,7 @@ int rgsvd_batch_plan(const rgsvd_desc* shapes, int32_t npairs, rgsvd_plan_t* pla
   P->wave_slots = device_wave_slots();
   int rc = layout(P);
   if (rc) { delete P; return rc; }
+  apply_cached_tune(P);
   *plan = P;
   *workspace_bytes = P->ws;
   return RGSVD_OK;
@@ -1262,6 +1346,38 @@ int rgsvd_batch_bind(rgsvd_plan_t P, const rgsvd_pair_io* io, void* workspace, v
 int rgsvd_batch_run(rgsvd_plan_t P, void* stream) {
   if (!P || !P->batched || !P->bound || !P->gexec) return RGSVD_EINVAL;
   return hipGraphLaunch(P->gexec, (hipStream_t)stream) == hipSuccess ? RGSVD_OK : RGSVD_EHIP;
+}
+
+int rgsvd_autotune(rgsvd_plan_t P, const void* G1, int64_t ld1, const void* G2, int64_t ld2, void* workspace,
+                   void* stream, const rgsvd_out* out, int32_t reps, int32_t* choice, float* best_ms) {
+  if (!P || P->batched || P->adaptive || P->learned || !G1 || !G2 || !out || reps < 1) return RGSVD_EINVAL;
+  if (!workspace || ((uintptr_t)workspace & (ALIGN - 1))) return RGSVD_EWORKSPACE;
+  PairLay& pr = P->pairs[0];
+  if (ld1 < pr.n || ld2 < pr.n) return RGSVD_EINVAL;
+  pr.out = *out;
+  P->sides[0].G = G1; P->sides[0].ldg = ld1;
+  P->sides[1].G = G2; P->sides[1].ldg = ld2;
+  const bool prof = P->prof;
+  P->prof = false;
+  int rc = autotune_plan(P, workspace, (hipStream_t)stream, reps, choice, best_ms);
+  P->prof = prof;
+  return rc;
+}
+
+int rgsvd_batch_autotune(rgsvd_plan_t P, const rgsvd_pair_io* io, void* workspace, void* stream, int32_t reps,
+                         int32_t* choice, float* best_ms) {
+  if (!P || !P->batched || !io || reps < 1) return RGSVD_EINVAL;
+  if (!workspace || ((uintptr_t)workspace & (ALIGN - 1))) return RGSVD_EWORKSPACE;
+  for (size_t i = 0; i < P->pairs.size(); ++i) {
+    auto& pr = P->pairs[i];
+    if (!io[i].G1 || !io[i].G2 || io[i].ld1 < pr.n || io[i].ld2 < pr.n) return RGSVD_EINVAL;
+    pr.out = io[i].out;
+    P->sides[2 * i].G = io[i].G1; P->sides[2 * i].ldg = io[i].ld1;
+    P->sides[2 * i + 1].G = io[i].G2; P->sides[2 * i + 1].ldg = io[i].ld2;
+  }
+  if (P->gexec) { hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+  P->bound = false;
+  return autotune_plan(P, workspace, (hipStream_t)stream, reps, choice, best_ms);
 }
 
 }  // extern "C"

@@ -311,7 +311,8 @@ jacobi_round(double* L, int ldl, int nr, int nd, int nc, int round, double thr, 
       be += __shfl_xor(be, o, 64);
       ga += __shfl_xor(ga, o, 64);
     }
-    if (p >= 0 && al > 0.0 && be > 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be)) {
+    // rotate unless |gamma| <= tol sqrt(alpha beta), tested on squares
+    if (p >= 0 && al > 0.0 && be > 0.0 && ga * ga > (tol * tol) * (al * be)) {
       const double zeta = (be - al) / (2.0 * ga);
       const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
       const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;

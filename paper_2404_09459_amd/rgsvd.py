@@ -74,6 +74,11 @@ EXPORTS = {
     "rgsvd_batch_bind": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(PairIO), ctypes.c_void_p,
                                         ctypes.c_void_p]),
     "rgsvd_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "rgsvd_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                      ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Out),
+                                      ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "rgsvd_batch_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "rgsvd_mlp_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32,
                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "rgsvd_mlp_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -206,6 +211,19 @@ def run(plan, G1, G2, o):
     return o
 
 
+def autotune(plan, G1, G2, o, reps=2):
+    """Pick the streaming kernels' tile shapes for `plan` by timing on these
+    inputs (outputs are written); returns ((rt, js, chunk), ms per run)."""
+    m, n = G1.shape
+    p = G2.shape[0]
+    out = out_struct(o, m, p, n)
+    ch = (ctypes.c_int32 * 3)()
+    ms = ctypes.c_float()
+    check(lib().rgsvd_autotune(plan.h, _ptr(G1), G1.stride(0), _ptr(G2), G2.stride(0), plan.ws_ptr,
+                               _stream(G1.device), ctypes.byref(out), reps, ch, ctypes.byref(ms)), "rgsvd_autotune")
+    return (ch[0], ch[1], ch[2]), ms.value
+
+
 _PLANS = {}
 
 
@@ -300,6 +318,21 @@ class BatchPlan:
     def run(self):
         check(lib().rgsvd_batch_run(self.h, _stream(self.device)), "rgsvd_batch_run")
         return self.outs
+
+    def autotune(self, pairs, reps=2):
+        """Time the tile-shape choices on this batch, then bind (capture)."""
+        io = (PairIO * len(pairs))()
+        outs = self.bind(pairs)   # allocate outputs and build io once
+        for i, ((G1, G2), o) in enumerate(zip(pairs, outs)):
+            io[i].G1 = _ptr(G1); io[i].G2 = _ptr(G2)
+            io[i].ld1 = G1.stride(0); io[i].ld2 = G2.stride(0)
+            io[i].out = out_struct(o, G1.shape[0], G2.shape[0], G1.shape[1])
+        ch = (ctypes.c_int32 * 3)()
+        ms = ctypes.c_float()
+        check(lib().rgsvd_batch_autotune(self.h, io, self.ws_ptr, _stream(self.device), reps, ch,
+                                         ctypes.byref(ms)), "rgsvd_batch_autotune")
+        check(lib().rgsvd_batch_bind(self.h, io, self.ws_ptr, _stream(self.device)), "rgsvd_batch_bind")
+        return (ch[0], ch[1], ch[2]), ms.value
 
     def __del__(self):
         try:
