@@ -266,3 +266,23 @@ def test_quantities_edge_cases():
     assert q["D1"] == 0.0 and q["D2"] == 0.0            # one genelet carries all
     q1 = O.quantities(np.array([0.6]), np.array([0.8]))
     assert q1["D1"] == 0.0                               # t = 1
+
+
+def test_power_iterations_reach_the_optimal_subspace():
+    """Subspace iteration (HMT): with a gap after l, q = 3 drives the residual
+    ||(I - QQ^T) G||_F to the optimal rank-l tail sqrt(sum_{j>l} s_j^2) of the
+    SVD, and never does worse than q = 0 on this seed."""
+    rng = np.random.default_rng(8)
+    m, n, l = 120, 90, 12
+    U = np.linalg.qr(rng.standard_normal((m, n)))[0]
+    V = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    s = np.concatenate([0.9 ** np.arange(l), 1e-3 * 0.9 ** np.arange(n - l)])
+    G = (U * s) @ V.T
+    tail = np.sqrt(np.sum(s[l:] ** 2))
+    res = {}
+    for q in (0, 3):
+        Q = O.basis_fixed(G, l, q, 6, STREAM_G1)
+        assert np.max(np.abs(Q.T @ Q - np.eye(l))) <= 1e-13
+        res[q] = np.linalg.norm(G - Q @ (Q.T @ G))
+    assert res[3] <= res[0] + 1e-15
+    assert abs(res[3] - tail) <= 1e-6 * tail
