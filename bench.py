@@ -32,9 +32,9 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TF = {"fp64": 78.6, "fp32": 157.3, "mixed": 2516.6}
 # 256 CUs x 4 SIMDs x 16 FP64 FMA lanes x 2 flops x 2.4 GHz
 FP64_VEC_PEAK_TF = 78.6
-# HBM bytes per launch on the 20000/15000 x 5000 workload, from FETCH_SIZE and
-# WRITE_SIZE scaled by a copy kernel of known size (profiles/hbm_counters_*.md)
-TRAFFIC_SMALL = 2.14e6
+# HBM bytes per launch of the sketch kernel on the 20000/15000 x 5000 workload,
+# from FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known size
+# (profiles/hbm_counters_*.md)
 TRAFFIC_SKETCH = 756.06e6
 
 
@@ -212,12 +212,21 @@ def main():
     avg_ms = dom_ms / dom_cnt
     gbytes = (m + p) * n * esz
     N = 2 * l
-    if dom_tag == "small":
+    if dom_tag == "bjacobi":
+        # block one-sided Jacobi on the factor of M (order N; H runs inside
+        # k_small at this size): a sweep visits the N (N - 1) / 2 column pairs,
+        # each with three length-N inner products and a rotation of two
+        # length-N columns, 12 N flops; sweeps as reported in info[5]
+        sw1 = int(res[flag]["info"][5])
+        flops = sw1 * 6.0 * N * N * (N - 1)
+        roof = {"bound": "alu", "achieved": flops / (dom_ms * 1e-3) / 1e12, "peak": FP64_VEC_PEAK_TF,
+                "unit": "TFLOP/s", "traffic": None}
+    elif dom_tag == "small":
         # one workgroup per pair: two dense symmetric eigendecompositions with
         # vectors (M: N x N, H: k x k) at 9 n^3 flops each, FP64 vector ALU
         flops = 9.0 * N ** 3 + 9.0 * k ** 3
         roof = {"bound": "alu", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": FP64_VEC_PEAK_TF,
-                "unit": "TFLOP/s", "traffic": TRAFFIC_SMALL if args.workload == "medium" else None}
+                "unit": "TFLOP/s", "traffic": None}
     elif dom_tag in ("nn", "tn") and flag == "mixed":
         roof = {"bound": "hbm", "achieved": gbytes / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "traffic": None}
@@ -227,7 +236,8 @@ def main():
     else:
         roof = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "traffic": None}
     roof["frac"] = roof["achieved"] / roof["peak"] if roof.get("achieved") is not None else None
-    roof["kernel"] = {"small": "k_small", "nn": "k_gw", "tn": "k_gtq"}.get(dom_tag, dom_tag)
+    roof["kernel"] = {"small": "k_small", "nn": "k_gw", "tn": "k_gtq",
+                      "bjacobi": "k_bjinit + k_bjround"}.get(dom_tag, dom_tag)
     roof["avg_launch_ms"] = avg_ms
     roof["launches_per_step"] = dom_cnt
     # the streaming sketch kernel beside it: one read of G1 and G2 per launch

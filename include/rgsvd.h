@@ -175,7 +175,8 @@ const char* rgsvd_strerror(int code);
  *   0 zero fill, 1 info init, 2 Omega generation, 3 G W product,
  *   4 split G^T Q / Q^T G product, 5 partial-sum reduction, 6 Gram (CholeskyQR),
  *   7 Cholesky + inverse, 8 triangular update Q = Y R^{-1}, 9 small FP64 step,
- *   10 recovery products, 11 sign convention, 12 Gram of the compressed pair. */
+ *   10 recovery products, 11 sign convention, 12 Gram of the compressed pair,
+ *   13 block Jacobi sweep (start or round) on a factor of the small step. */
 int rgsvd_profile(rgsvd_plan_t plan, int32_t enable);
 int rgsvd_profile_read(rgsvd_plan_t plan, int32_t max, float* ms, int32_t* tag, int32_t* count);
 

@@ -46,10 +46,10 @@ inline int ct_of(int L) {
 }
 
 enum Kind { K_ZERO, K_COPY, K_GEN, K_NN, K_AB, K_GRAM, K_RED, K_CHOL, K_SMALL, K_SIGN, K_SCALE, K_GW, K_GTQ,
-            K_CVT, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP };
+            K_CVT, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP, K_BJINIT, K_BJROUND };
 
 enum Tag { T_ZERO, T_COPY, T_GEN, T_NN, T_TN, T_RED, T_GRAM, T_CHOL, T_SX, T_SMALL, T_RECOVER, T_SIGN,
-           T_MGRAM, T_NTAGS };
+           T_MGRAM, T_BJAC, T_NTAGS };
 
 struct Stage {
   Kind kind;
@@ -61,6 +61,7 @@ struct Stage {
   bool sym = false, f64 = false;
   int npad_max = 0;
   size_t zoff = 0, zbytes = 0;  // K_ZERO: workspace range
+  int sweep = 0, round = 0;     // K_BJINIT, K_BJROUND
 };
 
 struct CopyJob { const uint32_t* src; uint32_t* dst; int64_t nwords; };
@@ -89,6 +90,7 @@ struct PairLay {
   uint64_t seed = 0;
   int gch = 1, gcl = 0;
   size_t mpart = 0, M = 0, work = 0, sigma = 0, X1t = 0, X2t = 0, Rcoef = 0, sgn = 0, info = 0;
+  size_t bjn = 0, bjs = 0;   // block Jacobi: column norms, state
   size_t alpha = 0;  // internal outputs when the caller passes null
   int l1cap = 0, l2cap = 0;
   rgsvd_out out{};
@@ -221,6 +223,8 @@ int layout(rgsvd_plan_s* P) {
     pr.M = take((size_t)pr.Npad * pr.Npad * 8);
     size_t N = pr.N, t = pr.t;
     pr.work = take((N * t + t * t + N * N) * 8);
+    pr.bjn = take(N * 8);
+    pr.bjs = take(sizeof(BJState));
     pr.sigma = take(N * 8);
     pr.X1t = take(t * pr.l1 * 8);
     pr.X2t = take(t * pr.l2 * 8);
@@ -687,12 +691,19 @@ int build(rgsvd_plan_s* P, void* ws) {
     Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = wt; gs.tag = T_MGRAM;
     Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.tag = T_RED;
   }
-  // small step
+  // small step: one launch, or stages around the block Jacobi sweeps on the
+  // factors of M (order N) and H (order t) that do not fit k_small's LDS
   {
-    std::vector<SmallJob> sj; std::vector<int> tl;
-    for (size_t pi = 0; pi < P->pairs.size(); ++pi) {
+    // (l1 + l2 is the order the run uses: below the laid-out capacity N
+    // after adaptive or learned sizing; t <= l1 + l2)
+    auto big = [](int64_t order) { return order * order * 8 > (int64_t)SMALL_LDS_BYTES; };
+    auto bjm = [&](const PairLay& pr) { return big(pr.l1 + pr.l2); };
+    auto bjh = [&](const PairLay& pr) { return big(pr.t); };
+    auto small_job = [&](size_t pi, int stage) {
       auto& pr = P->pairs[pi];
       SmallJob x{};
+      x.stage = stage; x.bjh = bjh(pr) ? 1 : 0;
+      x.st = (BJState*)WS(ws, pr.bjs);
       x.M = (const double*)WS(ws, pr.M); x.ldm = pr.Npad;
       x.l1 = pr.l1; x.l2 = pr.l2; x.t = pr.t; x.maxsweep = 40; x.tol = 1e-15;
       x.work = (double*)WS(ws, pr.work);
@@ -708,9 +719,55 @@ int build(rgsvd_plan_s* P, void* ws) {
       x.X2t = (double*)WS(ws, pr.X2t); x.ldx2 = pr.l2;
       x.Rcoef = (double*)WS(ws, pr.Rcoef); x.ldr = pr.N;
       x.info = info_of((int)pi);
-      sj.push_back(x); tl.push_back(1);
-    }
-    B.add(K_SMALL, sj, tl).tag = T_SMALL;
+      return x;
+    };
+    auto add_small = [&](int stage) {
+      std::vector<SmallJob> sj; std::vector<int> tl;
+      for (size_t pi = 0; pi < P->pairs.size(); ++pi) {
+        const auto& pr = P->pairs[pi];
+        const int st = stage == 1 ? (bjm(pr) ? 1 : 0) : stage;
+        if ((stage == 2 && !bjm(pr)) || (stage == 3 && !bjh(pr))) continue;
+        sj.push_back(small_job(pi, st)); tl.push_back(1);
+      }
+      if (!sj.empty()) B.add(K_SMALL, sj, tl).tag = T_SMALL;
+      return !sj.empty();
+    };
+    // sweeps of the block Jacobi: a sweep-start launch, then one launch per
+    // round (jobs with fewer rounds skip the extra ones)
+    auto add_bj = [&](bool onH) {
+      std::vector<BJJob> bj; std::vector<int> tl, one;
+      int rmax = 0;
+      for (auto& pr : P->pairs) {
+        if (!(onH ? bjh(pr) : bjm(pr))) continue;
+        const int N = pr.l1 + pr.l2, t = pr.t;
+        const int nr = onH ? t : N;
+        const int b = nr <= 256 ? BJ_B : BJ_B / 2;
+        const int nblk = 2 * ((nr + 2 * b - 1) / (2 * b));
+        double* F = (double*)WS(ws, pr.work) + (size_t)N * t + (size_t)t * t;
+        bj.push_back(BJJob{F, (BJState*)WS(ws, pr.bjs), (double*)WS(ws, pr.bjn), 1e-15, nr, nblk});
+        tl.push_back(nblk / 2); one.push_back(1);
+        rmax = std::max(rmax, nblk - 1);
+      }
+      Stage si = B.add(K_BJINIT, bj, one);
+      si.tag = T_BJAC;
+      P->stages.pop_back();
+      Stage sr = B.add(K_BJROUND, bj, tl);
+      sr.tag = T_BJAC;
+      P->stages.pop_back();
+      for (int sw = 0; sw < BJ_SWEEPS; ++sw) {
+        si.sweep = sw;
+        P->stages.push_back(si);
+        for (int r = 0; r < rmax; ++r) {
+          sr.sweep = sw; sr.round = r;
+          P->stages.push_back(sr);
+        }
+      }
+    };
+    bool any_m = false, any_h = false;
+    for (auto& pr : P->pairs) { any_m |= bjm(pr); any_h |= bjh(pr); }
+    add_small(1);
+    if (any_m) { add_bj(false); add_small(2); }
+    if (any_h) { add_bj(true); add_small(3); }
   }
   // recovery: R (needed for the sign convention), then U, V
   const int ctT = ct_of([&] { int t = 1; for (auto& pr : P->pairs) t = std::max(t, pr.t); return t; }());
@@ -883,6 +940,8 @@ int enqueue(rgsvd_plan_s* P, void* ws, hipStream_t st) {
       case K_RED: launch_reduce(s.ta, s.td, s.sym, (const RedJob*)j, pre, s.nj, s.tiles, st); break;
       case K_CHOL: launch_chol((const CholJob*)j, s.nj, s.npad_max, (double*)((char*)ws + P->off_chol), st); break;
       case K_SMALL: launch_small((const SmallJob*)j, s.nj, st); break;
+      case K_BJINIT: launch_bjinit((const BJJob*)j, s.nj, s.sweep, st); break;
+      case K_BJROUND: launch_bjround((const BJJob*)j, pre, s.nj, s.tiles, s.sweep, s.round, st); break;
       case K_SIGN: launch_sign((const SignJob*)j, pre, s.nj, s.tiles, st); break;
       case K_SCALE: launch_scale((const SignJob*)j, pre, s.nj, s.tiles, st); break;
       case K_GW: launch_gw(s.prec, s.gdt, s.rt, s.ct, (const NnJob*)j, pre, s.nj, s.tiles, st); break;

@@ -273,6 +273,66 @@ __global__ __launch_bounds__(1024) void k_chol(const CholJob* __restrict__ jobs,
 // convergence the topk dominant columns are orthogonal to every other
 // column, so they span the dominant invariant subspace.  Returns the number
 // of sweeps used (maxsweep + 1 when not converged).
+// One column pair (p, q) held by G consecutive lanes: lane j owns rows
+// j + G e (e < EM) of both columns.  Inner products over rows [0, nd), the
+// rotation over rows [0, nr).  The pair turns unless
+// |gamma| <= tol sqrt(alpha beta) (tested on squares); when thr >= 0 and
+// one column is below thr (a dominant column against a sub-threshold one)
+// it also needs |gamma| > tol max(alpha, beta): such a rotation turns the
+// dominant column by about gamma / max(alpha, beta), and the dominant
+// subspace is settled below that.  Returns whether the pair turned.
+template <int G, int EM>
+__device__ __attribute__((always_inline)) inline bool
+pair_step(double* Lp, double* Lq, int j, int nr, int nd, bool live, double tol, double thr) {
+  double x[EM], y[EM];
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int e = 0; e < EM; ++e) {
+    const int r = j + G * e;
+    const bool ok = live && r < nr;
+    x[e] = ok ? Lp[r] : 0.0;
+    y[e] = ok ? Lq[r] : 0.0;
+    if (r < nd) { al += x[e] * x[e]; be += y[e] * y[e]; ga += x[e] * y[e]; }
+  }
+#pragma unroll
+  for (int o = G / 2; o > 0; o >>= 1) {
+    al += __shfl_xor(al, o, 64);
+    be += __shfl_xor(be, o, 64);
+    ga += __shfl_xor(ga, o, 64);
+  }
+  const double g2 = ga * ga, tol2 = tol * tol;
+  bool turn = live && al > 0.0 && be > 0.0 && g2 > tol2 * (al * be);
+  if (turn && thr >= 0.0 && fmin(al, be) < thr) {
+    const double mx = fmax(al, be);
+    turn = g2 > tol2 * (mx * mx);
+  }
+  if (turn) {
+    const double zeta = (be - al) / (2.0 * ga);
+    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+#pragma unroll
+    for (int e = 0; e < EM; ++e) {
+      const int r = j + G * e;
+      if (r < nr) {
+        Lp[r] = c * x[e] - s * y[e];
+        Lq[r] = s * x[e] + c * y[e];
+      }
+    }
+  }
+  return turn;
+}
+
+// Round-robin tournament on m1 + 1 players (m1 odd): in round `round`,
+// slot pi (0 <= pi <= m1 / 2) pairs players u and v; slot 0 keeps player 0
+// and the others rotate, so every pair meets once in m1 rounds.
+__device__ inline void tournament(int pi, int round, int m1, int& u, int& v) {
+  u = 0;
+  if (pi > 0) { u = pi - 1 + round; if (u >= m1) u -= m1; u += 1; }
+  v = m1 - pi - 1 + round;          // m1 - pi >= 1
+  if (v >= m1) v -= m1;
+  v += 1;
+}
+
 template <int G, int EM>
 __device__ __attribute__((always_inline)) inline void
 jacobi_round(double* L, int ldl, int nr, int nd, int nc, int round, double thr, const double* nrm2,
@@ -285,49 +345,12 @@ jacobi_round(double* L, int ldl, int nr, int nd, int nc, int round, double thr, 
     const int pi = p0 + grp;
     int p = -1, q = -1;
     if (pi < npairs) {
-      // round-robin positions: slot 0 fixed, the others rotate by `round`
-      int u = 0;
-      if (pi > 0) { u = pi - 1 + round; if (u >= m1) u -= m1; u += 1; }
-      int v = m1 - pi - 1 + round;        // m1 - pi >= 1
-      if (v >= m1) v -= m1;
-      v += 1;
+      int u, v;
+      tournament(pi, round, m1, u, v);
       if (u < nc && v < nc && !(thr >= 0.0 && nrm2[u] < thr && nrm2[v] < thr)) { p = u; q = v; }
     }
-    double x[EM], y[EM];
-    double al = 0.0, be = 0.0, ga = 0.0;
-    const double* Lp = L + (p >= 0 ? p : 0) * ldl;
-    const double* Lq = L + (q >= 0 ? q : 0) * ldl;
-#pragma unroll
-    for (int e = 0; e < EM; ++e) {
-      const int r = j + G * e;
-      const bool ok = p >= 0 && r < nr;
-      x[e] = ok ? Lp[r] : 0.0;
-      y[e] = ok ? Lq[r] : 0.0;
-      if (r < nd) { al += x[e] * x[e]; be += y[e] * y[e]; ga += x[e] * y[e]; }
-    }
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-      al += __shfl_xor(al, o, 64);
-      be += __shfl_xor(be, o, 64);
-      ga += __shfl_xor(ga, o, 64);
-    }
-    // rotate unless |gamma| <= tol sqrt(alpha beta), tested on squares
-    if (p >= 0 && al > 0.0 && be > 0.0 && ga * ga > (tol * tol) * (al * be)) {
-      const double zeta = (be - al) / (2.0 * ga);
-      const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-      const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
-      double* Wp = L + p * ldl;
-      double* Wq = L + q * ldl;
-#pragma unroll
-      for (int e = 0; e < EM; ++e) {
-        const int r = j + G * e;
-        if (r < nr) {
-          Wp[r] = c * x[e] - s * y[e];
-          Wq[r] = s * x[e] + c * y[e];
-        }
-      }
-      any = true;
-    }
+    const bool live = p >= 0;
+    any |= pair_step<G, EM>(L + (live ? p : 0) * ldl, L + (live ? q : 0) * ldl, j, nr, nd, live, tol, thr);
   }
   if (any) *rotated = 1;
 }
@@ -472,15 +495,6 @@ struct SmallShared {
   double kth;
 };
 
-// Per pair (one workgroup):
-//  1. diagonally pivoted Cholesky of M and one-sided Jacobi on its graded
-//     factor F (pairs with a dominant column only): the t dominant
-//     eigenvectors Z of M, i.e. left singular vectors of B, and sigma_B;
-//  2. L = Z (N x t), the joint basis [L1; L2] of Algorithm 2's CS step;
-//  3. Y = eigenvectors of H = L1^T L1 (+ a tiny shift, which leaves them
-//     unchanged), again by pivoted Cholesky + Jacobi;
-//  4. L Y: alpha_i = ||L1 y_i||, beta_i = ||L2 y_i|| (beta from L2 as the
-//     column norms, never sqrt(1 - alpha^2)), X1, X2, (L Y)^T, quantities.
 // G lanes per column pair and EM entries per lane: G * EM >= nr
 __device__ __attribute__((always_inline)) inline int
 jacobi_any(double* A, int lda, int nr, int nc, double tol, int maxsweep, int topk, SmallShared& sh,
@@ -494,6 +508,34 @@ jacobi_any(double* A, int lda, int nr, int nc, double tol, int maxsweep, int top
   return jacobi_os<32, 16>(A, lda, nr, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
 }
 
+// Block Jacobi hand-over: the state for a factor of nc columns and nr rows
+// (thread 0).
+__device__ inline void bj_start(BJState* S, int nc, int nr, int topk) {
+  S->nc = nc; S->nr = nr; S->topk = topk; S->done = 0;
+  S->sweeps = 0; S->rot[0] = 1; S->rot[1] = 1; S->thr = -1.0;
+}
+
+// After the launched block sweeps: their count when converged (a sweep
+// without rotations), else the single-workgroup sweeps continue on A.
+__device__ __attribute__((always_inline)) inline int
+bj_finish(const BJState* S, double* A, int nr, int nc, int topk, double tol, int maxsweep, SmallShared& sh,
+          double* lds, int cap) {
+  const int nsw = S->sweeps;
+  if (S->done || nsw < 1 || S->rot[(nsw - 1) & 1] == 0) return nsw;
+  return nsw + jacobi_any(A, nr, nr, nc, tol, maxsweep - nsw, topk, sh, lds, cap);
+}
+
+// Per pair (one workgroup):
+//  1. diagonally pivoted Cholesky of M and one-sided Jacobi on its graded
+//     factor F (pairs with a dominant column only): the t dominant
+//     eigenvectors Z of M, i.e. left singular vectors of B, and sigma_B;
+//  2. L = Z (N x t), the joint basis [L1; L2] of Algorithm 2's CS step;
+//  3. Y = eigenvectors of H = L1^T L1 (+ a tiny shift, which leaves them
+//     unchanged), again by pivoted Cholesky + Jacobi;
+//  4. L Y: alpha_i = ||L1 y_i||, beta_i = ||L2 y_i|| (beta from L2 as the
+//     column norms, never sqrt(1 - alpha^2)), X1, X2, (L Y)^T, quantities.
+// Stages (SmallJob::stage) split the step around the block Jacobi launches
+// on the factors of M and H.
 __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob& J, double* lds, int cap,
                                                              SmallShared& sh) {
   const int l1 = J.l1, N = J.l1 + J.l2, t = J.t;
@@ -503,48 +545,73 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
   double* Lg = J.work;                            // N x t column-major
   double* Hg = Lg + (int64_t)N * t;               // t x t
   double* F = Hg + (int64_t)t * t;                // N x N Jacobi factor
-  // ---- 1. eigen-decomposition of M
-  int rank = pivoted_cholesky(J.M, J.ldm, N, F, sh.diag, sh.act, sh.frow, &sh.piv_j, &sh.piv_d, 0.0);
-  const int tt = t < rank ? t : rank;
-  int sw1 = jacobi_any(F, N, N, rank, J.tol, J.maxsweep, tt, sh, lds, cap);
-  for (int c = tid; c < N; c += 1024) {
-    double s = 0.0;
-    if (c < rank)
-      for (int r = 0; r < N; ++r) { double v = F[(int64_t)c * N + r]; s += v * v; }
-    keys[c] = sqrt(s);
-  }
-  __syncthreads();
-  for (int c = tid; c < N; c += 1024) perm[rank_desc(keys, N, c)] = c;
-  __syncthreads();
-  // sigma_B: t dominant singular values of B, then the tail's Frobenius norm
-  if (tid == 0) {
-    double tr = 0.0, top = 0.0;
-    for (int i = 0; i < N; ++i) tr += J.M[(int64_t)i * J.ldm + i];
-    for (int i = 0; i < t; ++i) { double v = keys[perm[i]]; top += v * v; }
-    sh.kth = sqrt(fmax(0.0, tr - top));
-  }
-  __syncthreads();
-  for (int i = tid; i < N; i += 1024)
-    J.sigma[i] = (i < t) ? keys[perm[i]] : (i == t ? sh.kth : 0.0);
-  // ---- 2. L = normalised dominant columns of F (N x t)
-  for (int e = tid; e < N * t; e += 1024) {
-    const int c = e / N, r = e - c * N;
-    const int src = perm[c];
-    const double nv = keys[src];
-    Lg[e] = (c < tt && nv > 0.0) ? F[(int64_t)src * N + r] / nv : 0.0;
-  }
-  __syncthreads();
-  // ---- 3. H = L1^T L1 + eps I, its eigenvectors Y (F is free again)
-  for (int e = tid; e < t * t; e += 1024) {
-    const int c = e / t, c2 = e - c * t;
-    double v = 0.0;
-    for (int r = 0; r < l1; ++r) v += Lg[(int64_t)c * N + r] * Lg[(int64_t)c2 * N + r];
-    Hg[e] = v;
-  }
-  __syncthreads();
+  BJState* S = J.st;
+  const int stage = J.stage;
+  int rh, sw1, sw2;
   double* FH = F;
-  int rh = pivoted_cholesky(Hg, t, t, FH, sh.diag, sh.act, sh.frow, &sh.piv_j, &sh.piv_d, 1e-12);
-  int sw2 = jacobi_any(FH, t, t, rh, J.tol, J.maxsweep, 0, sh, lds, cap);
+  if (stage <= 2) {
+    // ---- 1. eigen-decomposition of M
+    int rank, tt;
+    if (stage <= 1) {
+      rank = pivoted_cholesky(J.M, J.ldm, N, F, sh.diag, sh.act, sh.frow, &sh.piv_j, &sh.piv_d, 0.0);
+      tt = t < rank ? t : rank;
+      if (stage == 1) {
+        if (tid == 0) { S->rank = rank; bj_start(S, rank, N, tt); }
+        return;
+      }
+      sw1 = jacobi_any(F, N, N, rank, J.tol, J.maxsweep, tt, sh, lds, cap);
+    } else {
+      rank = S->rank;
+      tt = t < rank ? t : rank;
+      sw1 = bj_finish(S, F, N, rank, tt, J.tol, J.maxsweep, sh, lds, cap);
+    }
+    for (int c = tid; c < N; c += 1024) {
+      double s = 0.0;
+      if (c < rank)
+        for (int r = 0; r < N; ++r) { double v = F[(int64_t)c * N + r]; s += v * v; }
+      keys[c] = sqrt(s);
+    }
+    __syncthreads();
+    for (int c = tid; c < N; c += 1024) perm[rank_desc(keys, N, c)] = c;
+    __syncthreads();
+    // sigma_B: t dominant singular values of B, then the tail's Frobenius norm
+    if (tid == 0) {
+      double tr = 0.0, top = 0.0;
+      for (int i = 0; i < N; ++i) tr += J.M[(int64_t)i * J.ldm + i];
+      for (int i = 0; i < t; ++i) { double v = keys[perm[i]]; top += v * v; }
+      sh.kth = sqrt(fmax(0.0, tr - top));
+    }
+    __syncthreads();
+    for (int i = tid; i < N; i += 1024)
+      J.sigma[i] = (i < t) ? keys[perm[i]] : (i == t ? sh.kth : 0.0);
+    // ---- 2. L = normalised dominant columns of F (N x t)
+    for (int e = tid; e < N * t; e += 1024) {
+      const int c = e / N, r = e - c * N;
+      const int src = perm[c];
+      const double nv = keys[src];
+      Lg[e] = (c < tt && nv > 0.0) ? F[(int64_t)src * N + r] / nv : 0.0;
+    }
+    __syncthreads();
+    // ---- 3. H = L1^T L1 + eps I, its eigenvectors Y (F is free again)
+    for (int e = tid; e < t * t; e += 1024) {
+      const int c = e / t, c2 = e - c * t;
+      double v = 0.0;
+      for (int r = 0; r < l1; ++r) v += Lg[(int64_t)c * N + r] * Lg[(int64_t)c2 * N + r];
+      Hg[e] = v;
+    }
+    __syncthreads();
+    rh = pivoted_cholesky(Hg, t, t, FH, sh.diag, sh.act, sh.frow, &sh.piv_j, &sh.piv_d, 1e-12);
+    if (J.bjh) {
+      if (tid == 0) { S->sw1 = sw1; bj_start(S, rh, t, 0); }
+      return;
+    }
+    sw2 = jacobi_any(FH, t, t, rh, J.tol, J.maxsweep, 0, sh, lds, cap);
+  } else {
+    // ---- 3 (continued): the block Jacobi on H has run
+    sw1 = S->sw1;
+    rh = S->nc;
+    sw2 = bj_finish(S, FH, t, rh, 0, J.tol, J.maxsweep, sh, lds, cap);
+  }
   for (int c = tid; c < t; c += 1024) {
     double s = 0.0;
     if (c < rh)
@@ -634,6 +701,115 @@ __global__ __launch_bounds__(1024) void k_small(const SmallJob* __restrict__ job
   small_pair(jobs[blockIdx.x], lds, cap, sh);
 }
 
+// ------------------------------------------------------------ block Jacobi --
+// One-sided Jacobi on a factor too large for one workgroup's LDS: the
+// columns are split into nblk blocks of B; a round-robin tournament over the
+// blocks gives each of nblk / 2 workgroups a block pair per round (one
+// launch per round, so the launch boundary orders the rounds).  The
+// workgroup stages its 2 B columns in LDS and turns the B^2 cross pairs (B
+// inner rounds of B disjoint pairs); in the first round of a sweep, where
+// every block meets exactly one other, it also turns the pairs inside both
+// blocks.  Each pair of columns is therefore visited once per sweep, as in
+// the single-workgroup sweeps, with the same rotation and skip rules.
+
+// Sweep start: a sweep without rotations ends the run; otherwise squared
+// column norms and the skip threshold (a quarter of the topk-th largest).
+__global__ __launch_bounds__(1024) void k_bjinit(const BJJob* __restrict__ jobs, int nj, int sweep) {
+  __shared__ double n2[SMALL_MAXN];
+  __shared__ double kth;
+  const BJJob J = jobs[blockIdx.x];
+  BJState* S = J.st;
+  const int tid = threadIdx.x, wave = tid >> 6, ln = tid & 63;
+  if (S->done) return;
+  if (sweep > 0 && S->rot[(sweep - 1) & 1] == 0) {
+    if (tid == 0) { S->done = 1; S->sweeps = sweep; }
+    return;
+  }
+  const int nc = S->nc, nr = J.nr, topk = S->topk;
+  for (int c = wave; c < nc; c += 16) {
+    double v2 = 0.0;
+    for (int i = ln; i < nr; i += 64) { const double v = J.A[(int64_t)c * nr + i]; v2 += v * v; }
+    v2 = wave_sum(v2);
+    if (ln == 0) n2[c] = v2;
+  }
+  __syncthreads();
+  for (int c = tid; c < nc; c += 1024) J.nrm2[c] = n2[c];
+  double thr = -1.0;
+  if (topk > 0 && topk < nc) {
+    if (tid < nc) {
+      const double v = n2[tid];
+      int r = 0;
+      for (int j2 = 0; j2 < nc; ++j2) { const double w = n2[j2]; r += (w > v) || (w == v && j2 < tid); }
+      if (r == topk - 1) kth = v;
+    }
+    __syncthreads();
+    thr = 0.25 * kth;
+  }
+  if (tid == 0) { S->rot[sweep & 1] = 0; S->sweeps = sweep + 1; S->thr = thr; }
+}
+
+template <int B, int G, int EM>
+__device__ __attribute__((always_inline)) inline void
+bj_visit(const BJJob& J, BJState* S, int w, int sweep, int round, double* lds, double* n0) {
+  const int nr = J.nr, nc = S->nc, tid = threadIdx.x;
+  const double thr = S->thr;
+  int bu, bv;
+  tournament(w, round, J.nblk - 1, bu, bv);
+  const int c0u = bu * B, c0v = bv * B;
+  const int cu = min(max(nc - c0u, 0), B), cv = min(max(nc - c0v, 0), B);
+  if (cu + cv < 2) return;
+  // local column c < B is column c0u + c, c >= B is column c0v + c - B
+  auto gcol = [&](int c) { return c < B ? c0u + c : c0v + c - B; };
+  auto valid = [&](int c) { return c < B ? c < cu : c - B < cv; };
+  for (int e = tid; e < 2 * B * nr; e += BJ_THREADS) {
+    const int c = e / nr, r = e - c * nr;
+    lds[e] = valid(c) ? J.A[(int64_t)gcol(c) * nr + r] : 0.0;
+  }
+  if (tid < 2 * B) n0[tid] = valid(tid) ? J.nrm2[gcol(tid)] : 0.0;
+  __syncthreads();
+  const int g = tid / G, j = tid % G;
+  auto live = [&](int a, int b) {
+    return valid(a) && valid(b) && !(thr >= 0.0 && n0[a] < thr && n0[b] < thr);
+  };
+  bool any = false;
+  if (round == 0) {
+    // pairs inside each block: slots [0, B/2) in block u, [B/2, B) in block v
+    const int side = g / (B / 2), pi = g % (B / 2);
+    for (int s2 = 0; s2 < B - 1; ++s2) {
+      int u, v;
+      tournament(pi, s2, B - 1, u, v);
+      const int a = side * B + u, b = side * B + v;
+      any |= pair_step<G, EM>(lds + a * nr, lds + b * nr, j, nr, nr, live(a, b), J.tol, thr);
+      __syncthreads();
+    }
+  }
+  for (int s2 = 0; s2 < B; ++s2) {
+    const int a = g, b = B + ((g + s2) & (B - 1));
+    any |= pair_step<G, EM>(lds + a * nr, lds + b * nr, j, nr, nr, live(a, b), J.tol, thr);
+    __syncthreads();
+  }
+  for (int e = tid; e < 2 * B * nr; e += BJ_THREADS) {
+    const int c = e / nr, r = e - c * nr;
+    if (valid(c)) J.A[(int64_t)gcol(c) * nr + r] = lds[e];
+  }
+  if (__syncthreads_or(any) && tid == 0) atomicOr(&S->rot[sweep & 1], 1);
+}
+
+// One round of one sweep for every job (nblk / 2 workgroups each).
+__global__ __launch_bounds__(BJ_THREADS) void k_bjround(const BJJob* __restrict__ jobs,
+                                                        const int* __restrict__ pre, int nj, int sweep,
+                                                        int round) {
+  extern __shared__ double lds[];
+  __shared__ double n0[2 * BJ_B];
+  const int jb = find_side(pre, nj, blockIdx.x);
+  const BJJob J = jobs[jb];
+  BJState* S = J.st;
+  if (S->done || round >= J.nblk - 1) return;
+  const int w = blockIdx.x - pre[jb];
+  if (J.nr <= 256) bj_visit<BJ_B, BJ_THREADS / BJ_B, 8>(J, S, w, sweep, round, lds, n0);
+  else bj_visit<BJ_B / 2, 2 * BJ_THREADS / BJ_B, 8>(J, S, w, sweep, round, lds, n0);
+}
+
 // ------------------------------------------------------------- k_rowsign --
 // s_i = sign of the largest-magnitude entry of row i of R (first on ties)
 __global__ __launch_bounds__(256) void k_rowsign(const SignJob* __restrict__ jobs,
@@ -688,6 +864,20 @@ void launch_small(const SmallJob* j, int nj, hipStream_t st) {
     attr_set = true;
   }
   hipLaunchKernelGGL(k_small, dim3(nj), dim3(1024), bytes, st, j, nj, (int)(bytes / sizeof(double)));
+}
+
+void launch_bjinit(const BJJob* j, int nj, int sweep, hipStream_t st) {
+  hipLaunchKernelGGL(k_bjinit, dim3(nj), dim3(1024), 0, st, j, nj, sweep);
+}
+
+void launch_bjround(const BJJob* j, const int* pre, int nj, int tiles, int sweep, int round, hipStream_t st) {
+  static bool attr_set = false;
+  const size_t bytes = (size_t)2 * BJ_B * 256 * sizeof(double);   // 2 B columns of <= 256 rows
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)k_bjround, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_bjround, dim3(tiles), dim3(BJ_THREADS), bytes, st, j, pre, nj, sweep, round);
 }
 
 void launch_sign(const SignJob* j, const int* pre, int nj, int tiles, hipStream_t st) {

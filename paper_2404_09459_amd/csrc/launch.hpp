@@ -15,6 +15,8 @@ void launch_reduce(int ti, int to, bool sym, const RedJob* j, const int* pre, in
                    hipStream_t st);
 void launch_chol(const CholJob* j, int nj, int npad_max, double* gscratch, hipStream_t st);
 void launch_small(const SmallJob* j, int nj, hipStream_t st);
+void launch_bjinit(const BJJob* j, int nj, int sweep, hipStream_t st);
+void launch_bjround(const BJJob* j, const int* pre, int nj, int tiles, int sweep, int round, hipStream_t st);
 void launch_sign(const SignJob* j, const int* pre, int nj, int tiles, hipStream_t st);
 void launch_scale(const SignJob* j, const int* pre, int nj, int tiles, hipStream_t st);
 

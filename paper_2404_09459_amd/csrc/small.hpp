@@ -19,12 +19,38 @@ constexpr int FLAG_BETA_ZERO = 0x20;
 constexpr int FLAG_ALPHA_ZERO = 0x40;
 constexpr int FLAG_NONFINITE = 0x80;
 
+// Block one-sided Jacobi for factors too large for k_small's LDS (order^2 >
+// SMALL_LDS_BYTES / 8): columns in blocks of BJ_B (order <= 256) or BJ_B / 2
+// (order <= 512); one workgroup per block pair and one launch per round; at
+// most BJ_SWEEPS sweeps are launched, the single-workgroup sweeps finish a
+// factor that has not converged by then.
+constexpr int BJ_B = 16;
+constexpr int BJ_SWEEPS = 12;
+constexpr int BJ_THREADS = 512;
+
+// State of a block Jacobi run, shared by the staged small kernel and the
+// sweep and round kernels (device memory, one per pair).
+struct BJState {
+  int32_t nc, nr, topk, done;       // columns, rows, dominant count, converged flag
+  int32_t sweeps, rank, sw1, pad;   // sweeps started; rank of M; sweeps on M
+  int32_t rot[2];                   // rotations seen in the sweep of that parity
+  double thr;                       // skip threshold of the sweep (-1: none)
+  double pad2[3];
+};
+
 // One compressed pair: M = B B^T (N x N, ldm), the Gram of the stacked
 // compressed pair B = [Q1^T G1; Q2^T G2], N = l1 + l2.
+//
+// stage 0 runs the whole step.  With the block Jacobi the step runs in
+// stages: 1 factors M and stops before its Jacobi; 2 finishes that Jacobi,
+// forms H, factors it and stops before its Jacobi when bjh is set (else
+// runs to the end); 3 finishes the Jacobi on H and runs to the end.
 struct SmallJob {
   const double* M; int64_t ldm;
   int32_t l1, l2, t, maxsweep;
   double tol;
+  int32_t stage, bjh;
+  BJState* st;
   double* work;                     // N*t (L) + t*t (H) + N*N (Jacobi factor) doubles
   double* sigma;                    // N
   double *alpha, *beta, *theta, *P1, *P2, *D;
@@ -35,6 +61,15 @@ struct SmallJob {
 };
 
 // sign convention of one pair: sgn[i] from row i of R (t x n)
+// One block Jacobi factor: A (nr x nc, column-major, ld nr), nc read from
+// the state; nblk = 2 P blocks, P workgroups per round; nrm2: squared column
+// norms at the start of the sweep (nr entries).
+struct BJJob {
+  double* A; BJState* st; double* nrm2;
+  double tol;
+  int32_t nr, nblk;
+};
+
 struct SignJob {
   double* R; int64_t ldr; double* sgn; int32_t t, n;
 };

@@ -259,10 +259,10 @@ def rgsvd(G1, G2, k, oversample, q, seed, precision="fp64", mode="truncated", uv
 
 
 STAGE_TAGS = ["zero", "info", "gen", "nn", "tn", "reduce", "gram", "chol", "sx", "small",
-              "recover", "sign", "mgram"]
+              "recover", "sign", "mgram", "bjacobi"]
 
 
-def profile_read(plan, maxn=512):
+def profile_read(plan, maxn=1024):
     """Per-stage (tag, ms) of the last profiled run (call after a sync)."""
     ms = (ctypes.c_float * maxn)()
     tg = (ctypes.c_int32 * maxn)()
