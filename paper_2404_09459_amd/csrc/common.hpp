@@ -102,4 +102,38 @@ __device__ inline float wave_sum(float v) {
   return v;
 }
 
+// A double moved across lanes by a DPP control (both 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// A double from lane ^ 16 (ds_swizzle bit-mask mode, within 32 lanes).
+__device__ __forceinline__ double swz16_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)b, 0x401F);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), 0x401F);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over each aligned group of G lanes (G a power of two <= 64), left in
+// every lane of the group.  Each step adds a partner holding the same
+// partial (quad xor 1, xor 2; 8-lane mirror; 16-lane mirror; lane ^ 16;
+// lane ^ 32), so both sides of every step form the same two-term sum and
+// all G lanes end with bit-identical results.  The whole wave must be
+// active.
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+  if (G > 1) v += dpp_f64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  if (G > 2) v += dpp_f64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  if (G > 4) v += dpp_f64<0x141>(v);   // row_half_mirror
+  if (G > 8) v += dpp_f64<0x140>(v);   // row_mirror
+  if (G > 16) v += swz16_f64(v);
+  if (G > 32) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
 }  // namespace rg

@@ -258,9 +258,8 @@ __global__ __launch_bounds__(1024) void k_chol(const CholJob* __restrict__ jobs,
 
 // ------------------------------------------------------ one-sided Jacobi --
 // Orthogonalises the nc columns of A (column-major, ld lda) by plane
-// rotations (Hestenes).  Inner products use rows [0, nd); the rotations are
-// applied to rows [0, nr) (nr >= nd).  Parallel round-robin ordering: each
-// round pairs every column once.
+// rotations (Hestenes) over rows [0, nr).  Parallel round-robin ordering:
+// each round pairs every column once.
 //
 // G lanes hold one column pair, EM >= nr / G entries of each column per
 // lane, so a pair's three inner products reduce in log2(G)
@@ -281,25 +280,16 @@ __global__ __launch_bounds__(1024) void k_chol(const CholJob* __restrict__ jobs,
 // it also needs |gamma| > tol max(alpha, beta): such a rotation turns the
 // dominant column by about gamma / max(alpha, beta), and the dominant
 // subspace is settled below that.  Returns whether the pair turned.
-template <int G, int EM>
-__device__ __attribute__((always_inline)) inline bool
-pair_step(double* Lp, double* Lq, int j, int nr, int nd, bool live, double tol, double thr) {
-  double x[EM], y[EM];
-  double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-  for (int e = 0; e < EM; ++e) {
-    const int r = j + G * e;
-    const bool ok = live && r < nr;
-    x[e] = ok ? Lp[r] : 0.0;
-    y[e] = ok ? Lq[r] : 0.0;
-    if (r < nd) { al += x[e] * x[e]; be += y[e] * y[e]; ga += x[e] * y[e]; }
-  }
-#pragma unroll
-  for (int o = G / 2; o > 0; o >>= 1) {
-    al += __shfl_xor(al, o, 64);
-    be += __shfl_xor(be, o, 64);
-    ga += __shfl_xor(ga, o, 64);
-  }
+// Rotation of a column pair from its inner products alpha = ||x||^2,
+// beta = ||y||^2, gamma = x^T y.  The pair turns unless
+// |gamma| <= tol sqrt(alpha beta) (tested on squares); when thr >= 0 and
+// one column is below thr (a dominant column against a sub-threshold one)
+// it also needs |gamma| > tol max(alpha, beta): such a rotation turns the
+// dominant column by about gamma / max(alpha, beta), and the dominant
+// subspace is settled below that.  On a turn, (c, s) with
+// x' = c x - s y, y' = s x + c y orthogonal.
+__device__ __forceinline__ bool jacobi_turn(double al, double be, double ga, bool live, double tol, double thr,
+                                            double& c, double& s) {
   const double g2 = ga * ga, tol2 = tol * tol;
   bool turn = live && al > 0.0 && be > 0.0 && g2 > tol2 * (al * be);
   if (turn && thr >= 0.0 && fmin(al, be) < thr) {
@@ -307,9 +297,43 @@ pair_step(double* Lp, double* Lq, int j, int nr, int nd, bool live, double tol, 
     turn = g2 > tol2 * (mx * mx);
   }
   if (turn) {
-    const double zeta = (be - al) / (2.0 * ga);
-    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-    const double c = 1.0 / sqrt(1.0 + t * t), s = c * t;
+    // t = tan of the angle that zeroes gamma, the root of
+    // t^2 + 2 zeta t - 1 = 0 (zeta = (beta - alpha) / (2 gamma)) of smaller
+    // magnitude, written without zeta: 2 gamma sign(d) / (|d| + sqrt(d^2 + 4 gamma^2))
+    const double d = be - al;
+    const double t = (d >= 0.0 ? 2.0 * ga : -2.0 * ga) / (fabs(d) + sqrt(fma(d, d, 4.0 * g2)));
+    c = rsqrt(fma(t, t, 1.0));
+    s = c * t;
+  }
+  return turn;
+}
+
+// One column pair (p, q) of nr rows held by G consecutive lanes: lane j
+// owns rows j + G e (e < EM) of both columns.  Rows past nr read the last
+// row (in bounds) scaled by zero, so every load is unconditional.  Returns
+// whether the pair turned.
+template <int G, int EM>
+__device__ __attribute__((always_inline)) inline bool
+pair_step(double* Lp, double* Lq, int j, int nr, bool live, double tol, double thr) {
+  double x[EM], y[EM];
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int e = 0; e < EM; ++e) {
+    const int r = j + G * e;
+    const int rr = r < nr ? r : nr - 1;
+    const double w = (live && r < nr) ? 1.0 : 0.0;
+    x[e] = Lp[rr] * w;
+    y[e] = Lq[rr] * w;
+    al = fma(x[e], x[e], al);
+    be = fma(y[e], y[e], be);
+    ga = fma(x[e], y[e], ga);
+  }
+  al = group_sum<G>(al);
+  be = group_sum<G>(be);
+  ga = group_sum<G>(ga);
+  double c, s;
+  const bool turn = jacobi_turn(al, be, ga, live, tol, thr, c, s);
+  if (turn) {
 #pragma unroll
     for (int e = 0; e < EM; ++e) {
       const int r = j + G * e;
@@ -317,6 +341,36 @@ pair_step(double* Lp, double* Lq, int j, int nr, int nd, bool live, double tol, 
         Lp[r] = c * x[e] - s * y[e];
         Lq[r] = s * x[e] + c * y[e];
       }
+    }
+  }
+  return turn;
+}
+
+// The same on LDS columns padded to G * EM rows whose rows past the order
+// hold zeros (they stay zero under rotations): no bounds tests.
+template <int G, int EM>
+__device__ __attribute__((always_inline)) inline bool
+pair_step_padded(double* Lp, double* Lq, int j, bool live, double tol, double thr) {
+  double x[EM], y[EM];
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int e = 0; e < EM; ++e) {
+    x[e] = Lp[j + G * e];
+    y[e] = Lq[j + G * e];
+    al = fma(x[e], x[e], al);
+    be = fma(y[e], y[e], be);
+    ga = fma(x[e], y[e], ga);
+  }
+  al = group_sum<G>(al);
+  be = group_sum<G>(be);
+  ga = group_sum<G>(ga);
+  double c, s;
+  const bool turn = jacobi_turn(al, be, ga, live, tol, thr, c, s);
+  if (turn) {
+#pragma unroll
+    for (int e = 0; e < EM; ++e) {
+      Lp[j + G * e] = c * x[e] - s * y[e];
+      Lq[j + G * e] = s * x[e] + c * y[e];
     }
   }
   return turn;
@@ -335,7 +389,7 @@ __device__ inline void tournament(int pi, int round, int m1, int& u, int& v) {
 
 template <int G, int EM>
 __device__ __attribute__((always_inline)) inline void
-jacobi_round(double* L, int ldl, int nr, int nd, int nc, int round, double thr, const double* nrm2,
+jacobi_round(double* L, int ldl, int nr, int nc, int round, double thr, const double* nrm2,
              double tol, int* rotated) {
   constexpr int SLOTS = 1024 / G;
   const int tid = threadIdx.x, grp = tid / G, j = tid % G;
@@ -350,7 +404,7 @@ jacobi_round(double* L, int ldl, int nr, int nd, int nc, int round, double thr, 
       if (u < nc && v < nc && !(thr >= 0.0 && nrm2[u] < thr && nrm2[v] < thr)) { p = u; q = v; }
     }
     const bool live = p >= 0;
-    any |= pair_step<G, EM>(L + (live ? p : 0) * ldl, L + (live ? q : 0) * ldl, j, nr, nd, live, tol, thr);
+    any |= pair_step<G, EM>(L + (live ? p : 0) * ldl, L + (live ? q : 0) * ldl, j, nr, live, tol, thr);
   }
   if (any) *rotated = 1;
 }
@@ -358,14 +412,14 @@ jacobi_round(double* L, int ldl, int nr, int nd, int nc, int round, double thr, 
 // All sweeps on W (ld ldw): LDS copy or A itself.
 template <int G, int EM>
 __device__ __attribute__((always_inline)) inline int
-jacobi_sweeps(double* W, int ldw, int nr, int nd, int nc, double tol, int maxsweep, int topk, double* nrm2,
+jacobi_sweeps(double* W, int ldw, int nr, int nc, double tol, int maxsweep, int topk, double* nrm2,
               int* scratch, double* kth_slot) {
   const int tid = threadIdx.x, wave = tid >> 6, ln = tid & 63;
   const int nc2 = nc + (nc & 1);
   for (int sweep = 0; sweep < maxsweep; ++sweep) {
     for (int c = wave; c < nc; c += 16) {
       double s = 0.0;
-      for (int i = ln; i < nd; i += 64) { const double v = W[(int64_t)c * ldw + i]; s += v * v; }
+      for (int i = ln; i < nr; i += 64) { const double v = W[(int64_t)c * ldw + i]; s += v * v; }
       s = wave_sum(s);
       if (ln == 0) nrm2[c] = s;
     }
@@ -383,7 +437,7 @@ jacobi_sweeps(double* W, int ldw, int nr, int nd, int nc, double tol, int maxswe
       thr = 0.25 * *kth_slot;
     }
     for (int round = 0; round < nc2 - 1; ++round) {
-      jacobi_round<G, EM>(W, ldw, nr, nd, nc, round, thr, nrm2, tol, scratch);
+      jacobi_round<G, EM>(W, ldw, nr, nc, round, thr, nrm2, tol, scratch);
       __syncthreads();
     }
     const int any = scratch[0];
@@ -395,18 +449,18 @@ jacobi_sweeps(double* W, int ldw, int nr, int nd, int nc, double tol, int maxswe
 
 template <int G, int EM>
 __device__ __attribute__((always_inline)) inline int
-jacobi_os(double* A, int lda, int nr, int nd, int nc, double tol, int maxsweep, int topk, double* nrm2,
+jacobi_os(double* A, int lda, int nr, int nc, double tol, int maxsweep, int topk, double* nrm2,
           int* scratch, double* kth_slot, double* lds, int cap) {
   const int tid = threadIdx.x;
   if (nc < 2) return 0;
   if ((int64_t)nc * nr > cap)
-    return jacobi_sweeps<G, EM>(A, lda, nr, nd, nc, tol, maxsweep, topk, nrm2, scratch, kth_slot);
+    return jacobi_sweeps<G, EM>(A, lda, nr, nc, tol, maxsweep, topk, nrm2, scratch, kth_slot);
   for (int e = tid; e < nc * nr; e += 1024) {
     const int c = e / nr, r = e - c * nr;
     lds[e] = A[(int64_t)c * lda + r];
   }
   __syncthreads();
-  const int sw = jacobi_sweeps<G, EM>(lds, nr, nr, nd, nc, tol, maxsweep, topk, nrm2, scratch, kth_slot);
+  const int sw = jacobi_sweeps<G, EM>(lds, nr, nr, nc, tol, maxsweep, topk, nrm2, scratch, kth_slot);
   for (int e = tid; e < nc * nr; e += 1024) {
     const int c = e / nr, r = e - c * nr;
     A[(int64_t)c * lda + r] = lds[e];
@@ -502,10 +556,10 @@ jacobi_any(double* A, int lda, int nr, int nc, double tol, int maxsweep, int top
   double* k = sh.keys;
   int* sc = sh.scratch;
   double* kt = &sh.kth;
-  if (nr <= 64) return jacobi_os<16, 4>(A, lda, nr, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
-  if (nr <= 128) return jacobi_os<16, 8>(A, lda, nr, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
-  if (nr <= 256) return jacobi_os<16, 16>(A, lda, nr, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
-  return jacobi_os<32, 16>(A, lda, nr, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
+  if (nr <= 64) return jacobi_os<16, 4>(A, lda, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
+  if (nr <= 128) return jacobi_os<16, 8>(A, lda, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
+  if (nr <= 256) return jacobi_os<16, 16>(A, lda, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
+  return jacobi_os<32, 16>(A, lda, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
 }
 
 // Block Jacobi hand-over: the state for a factor of nc columns and nr rows
@@ -712,8 +766,9 @@ __global__ __launch_bounds__(1024) void k_small(const SmallJob* __restrict__ job
 // blocks.  Each pair of columns is therefore visited once per sweep, as in
 // the single-workgroup sweeps, with the same rotation and skip rules.
 
-// Sweep start: a sweep without rotations ends the run; otherwise squared
-// column norms and the skip threshold (a quarter of the topk-th largest).
+// Sweep start: a sweep without rotations ends the run; otherwise the skip
+// threshold (a quarter of the topk-th largest squared column norm; the
+// norms come from the previous sweep's last round, or from A at sweep 0).
 __global__ __launch_bounds__(1024) void k_bjinit(const BJJob* __restrict__ jobs, int nj, int sweep) {
   __shared__ double n2[SMALL_MAXN];
   __shared__ double kth;
@@ -726,14 +781,20 @@ __global__ __launch_bounds__(1024) void k_bjinit(const BJJob* __restrict__ jobs,
     return;
   }
   const int nc = S->nc, nr = J.nr, topk = S->topk;
-  for (int c = wave; c < nc; c += 16) {
-    double v2 = 0.0;
-    for (int i = ln; i < nr; i += 64) { const double v = J.A[(int64_t)c * nr + i]; v2 += v * v; }
-    v2 = wave_sum(v2);
-    if (ln == 0) n2[c] = v2;
+  if (sweep == 0) {
+    for (int c = wave; c < nc; c += 16) {
+      double v2 = 0.0;
+      for (int i = ln; i < nr; i += 64) { const double v = J.A[(int64_t)c * nr + i]; v2 += v * v; }
+      v2 = wave_sum(v2);
+      if (ln == 0) n2[c] = v2;
+    }
+    __syncthreads();
+    for (int c = tid; c < nc; c += 1024) J.nrm2[c] = n2[c];
+  } else {
+    // left by the last round of the previous sweep
+    for (int c = tid; c < nc; c += 1024) n2[c] = J.nrm2[c];
   }
   __syncthreads();
-  for (int c = tid; c < nc; c += 1024) J.nrm2[c] = n2[c];
   double thr = -1.0;
   if (topk > 0 && topk < nc) {
     if (tid < nc) {
@@ -757,13 +818,30 @@ bj_visit(const BJJob& J, BJState* S, int w, int sweep, int round, double* lds, d
   tournament(w, round, J.nblk - 1, bu, bv);
   const int c0u = bu * B, c0v = bv * B;
   const int cu = min(max(nc - c0u, 0), B), cv = min(max(nc - c0v, 0), B);
-  if (cu + cv < 2) return;
+  if (cu + cv < 2 && round != J.nblk - 2) return;   // the last round still refreshes norms
   // local column c < B is column c0u + c, c >= B is column c0v + c - B
   auto gcol = [&](int c) { return c < B ? c0u + c : c0v + c - B; };
   auto valid = [&](int c) { return c < B ? c < cu : c - B < cv; };
-  for (int e = tid; e < 2 * B * nr; e += BJ_THREADS) {
-    const int c = e / nr, r = e - c * nr;
-    lds[e] = valid(c) ? J.A[(int64_t)gcol(c) * nr + r] : 0.0;
+  // staging: TPC threads per column, rows sc_j + TPC i, all loads in flight;
+  // LDS columns padded to LD = G EM rows, zero past nr
+  constexpr int TPC = BJ_THREADS / (2 * B), RPT = 16, LD = G * EM;   // nr <= TPC * RPT = LD
+  static_assert(TPC * RPT == LD, "staging covers the padded column");
+  typedef __attribute__((address_space(1))) double gdouble;
+  gdouble* gA = (gdouble*)J.A;
+  const int sc_c = tid / TPC, sc_j = tid % TPC;
+  const bool sc_ok = valid(sc_c);
+  const gdouble* src = gA + (int64_t)(sc_ok ? gcol(sc_c) : 0) * nr;
+  double* col = lds + sc_c * LD;
+  {
+    double v[RPT];
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) {
+      const int r = sc_j + TPC * i;
+      const double w = src[r < nr ? r : nr - 1];
+      v[i] = (sc_ok && r < nr) ? w : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < RPT; ++i) col[sc_j + TPC * i] = v[i];
   }
   if (tid < 2 * B) n0[tid] = valid(tid) ? J.nrm2[gcol(tid)] : 0.0;
   __syncthreads();
@@ -779,18 +857,30 @@ bj_visit(const BJJob& J, BJState* S, int w, int sweep, int round, double* lds, d
       int u, v;
       tournament(pi, s2, B - 1, u, v);
       const int a = side * B + u, b = side * B + v;
-      any |= pair_step<G, EM>(lds + a * nr, lds + b * nr, j, nr, nr, live(a, b), J.tol, thr);
+      any |= pair_step_padded<G, EM>(lds + a * LD, lds + b * LD, j, live(a, b), J.tol, thr);
       __syncthreads();
     }
   }
   for (int s2 = 0; s2 < B; ++s2) {
     const int a = g, b = B + ((g + s2) & (B - 1));
-    any |= pair_step<G, EM>(lds + a * nr, lds + b * nr, j, nr, nr, live(a, b), J.tol, thr);
+    any |= pair_step_padded<G, EM>(lds + a * LD, lds + b * LD, j, live(a, b), J.tol, thr);
     __syncthreads();
   }
-  for (int e = tid; e < 2 * B * nr; e += BJ_THREADS) {
-    const int c = e / nr, r = e - c * nr;
-    if (valid(c)) J.A[(int64_t)gcol(c) * nr + r] = lds[e];
+  // write back; in the last round of the sweep every column passes through
+  // exactly one workgroup, which leaves its squared norm for the next sweep
+  double n2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = sc_j + TPC * i;
+    if (r < nr) {
+      const double v = col[r];
+      n2 += v * v;
+      if (sc_ok) gA[(int64_t)gcol(sc_c) * nr + r] = v;
+    }
+  }
+  if (round == J.nblk - 2) {
+    n2 = group_sum<TPC>(n2);
+    if (sc_ok && sc_j == 0) J.nrm2[gcol(sc_c)] = n2;
   }
   if (__syncthreads_or(any) && tid == 0) atomicOr(&S->rot[sweep & 1], 1);
 }

@@ -25,7 +25,7 @@ constexpr int FLAG_NONFINITE = 0x80;
 // most BJ_SWEEPS sweeps are launched, the single-workgroup sweeps finish a
 // factor that has not converged by then.
 constexpr int BJ_B = 16;
-constexpr int BJ_SWEEPS = 12;
+constexpr int BJ_SWEEPS = 10;
 constexpr int BJ_THREADS = 512;
 
 // State of a block Jacobi run, shared by the staged small kernel and the
