@@ -549,17 +549,53 @@ struct SmallShared {
   double kth;
 };
 
-// G lanes per column pair and EM entries per lane: G * EM >= nr
+// G lanes per column pair and EM entries per lane (G * EM >= nr): 16 x 8
+// for small factors in LDS, 32 x 16 otherwise (the global-memory sweeps
+// only finish factors that the block Jacobi left unconverged)
 __device__ __attribute__((always_inline)) inline int
 jacobi_any(double* A, int lda, int nr, int nc, double tol, int maxsweep, int topk, SmallShared& sh,
            double* lds, int cap) {
   double* k = sh.keys;
   int* sc = sh.scratch;
   double* kt = &sh.kth;
-  if (nr <= 64) return jacobi_os<16, 4>(A, lda, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
-  if (nr <= 128) return jacobi_os<16, 8>(A, lda, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
-  if (nr <= 256) return jacobi_os<16, 16>(A, lda, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
+  if (nr <= 128 && (int64_t)nc * nr <= cap)
+    return jacobi_os<16, 8>(A, lda, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
   return jacobi_os<32, 16>(A, lda, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
+}
+
+// C = A B in one workgroup on FP64 MFMA (16 x 16 output tiles, one per
+// wave at a time, k in steps of 4): element (i, k) of A at
+// A[i sai + k sak], element (k, j) of B at B[k sbk + j sbj]; I x J output,
+// inner order K.  store(i, j, v) receives every output element once; with
+// SYM (A B symmetric, I == J) only tiles on or above the diagonal are formed
+// and store(i, j, v) is called for i <= j.
+template <bool SYM, typename Store>
+__device__ __attribute__((always_inline)) inline void
+wg_gemm64(const double* A, int64_t sai, int64_t sak, const double* B, int64_t sbk, int64_t sbj, int I, int J,
+          int K, Store store) {
+  const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63, r16 = ln & 15, g = ln >> 4;
+  const int ti = (I + 15) / 16, tj = (J + 15) / 16;
+  for (int tile = wave; tile < ti * tj; tile += 16) {
+    const int bi = tile / tj, bj = tile - bi * tj;
+    if (SYM && bi > bj) continue;
+    const int ia = bi * 16 + r16, jb = bj * 16 + r16;
+    const bool oka = ia < I, okb = jb < J;
+    const double* pa = A + (oka ? ia : 0) * sai;
+    const double* pb = B + (okb ? jb : 0) * sbj;
+    d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < K; k0 += 4) {
+      const int k = k0 + g;
+      const double a = (oka && k < K) ? pa[k * sak] : 0.0;
+      const double b = (okb && k < K) ? pb[k * sbk] : 0.0;
+      acc = mma64(a, b, acc);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = bi * 16 + out_row<0>(g, q);
+      if (i < I && jb < J && (!SYM || i <= jb)) store(i, jb, acc[q]);
+    }
+  }
 }
 
 // Block Jacobi hand-over: the state for a factor of nc columns and nr rows
@@ -569,14 +605,12 @@ __device__ inline void bj_start(BJState* S, int nc, int nr, int topk) {
   S->sweeps = 0; S->rot[0] = 1; S->rot[1] = 1; S->thr = -1.0;
 }
 
-// After the launched block sweeps: their count when converged (a sweep
-// without rotations), else the single-workgroup sweeps continue on A.
-__device__ __attribute__((always_inline)) inline int
-bj_finish(const BJState* S, double* A, int nr, int nc, int topk, double tol, int maxsweep, SmallShared& sh,
-          double* lds, int cap) {
+// Sweeps already run by the block Jacobi, and whether single-workgroup
+// sweeps must continue (the last launched sweep still rotated).
+__device__ inline int bj_sweeps(const BJState* S, bool& more) {
   const int nsw = S->sweeps;
-  if (S->done || nsw < 1 || S->rot[(nsw - 1) & 1] == 0) return nsw;
-  return nsw + jacobi_any(A, nr, nr, nc, tol, maxsweep - nsw, topk, sh, lds, cap);
+  more = !(S->done || nsw < 1 || S->rot[(nsw - 1) & 1] == 0);
+  return nsw;
 }
 
 // Per pair (one workgroup):
@@ -605,20 +639,20 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
   double* FH = F;
   if (stage <= 2) {
     // ---- 1. eigen-decomposition of M
-    int rank, tt;
+    int rank, base = 0;
+    bool more = true;
     if (stage <= 1) {
       rank = pivoted_cholesky(J.M, J.ldm, N, F, sh.diag, sh.act, sh.frow, &sh.piv_j, &sh.piv_d, 0.0);
-      tt = t < rank ? t : rank;
       if (stage == 1) {
-        if (tid == 0) { S->rank = rank; bj_start(S, rank, N, tt); }
+        if (tid == 0) { S->rank = rank; bj_start(S, rank, N, t < rank ? t : rank); }
         return;
       }
-      sw1 = jacobi_any(F, N, N, rank, J.tol, J.maxsweep, tt, sh, lds, cap);
     } else {
       rank = S->rank;
-      tt = t < rank ? t : rank;
-      sw1 = bj_finish(S, F, N, rank, tt, J.tol, J.maxsweep, sh, lds, cap);
+      base = bj_sweeps(S, more);
     }
+    const int tt = t < rank ? t : rank;
+    sw1 = base + (more ? jacobi_any(F, N, N, rank, J.tol, J.maxsweep - base, tt, sh, lds, cap) : 0);
     for (int c = tid; c < N; c += 1024) {
       double s = 0.0;
       if (c < rank)
@@ -647,24 +681,27 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
     }
     __syncthreads();
     // ---- 3. H = L1^T L1 + eps I, its eigenvectors Y (F is free again)
-    for (int e = tid; e < t * t; e += 1024) {
-      const int c = e / t, c2 = e - c * t;
-      double v = 0.0;
-      for (int r = 0; r < l1; ++r) v += Lg[(int64_t)c * N + r] * Lg[(int64_t)c2 * N + r];
-      Hg[e] = v;
-    }
+    wg_gemm64<true>(Lg, N, 1, Lg, 1, N, t, t, l1, [&](int i, int j, double v) {
+      Hg[(int64_t)i * t + j] = v;
+      Hg[(int64_t)j * t + i] = v;
+    });
     __syncthreads();
     rh = pivoted_cholesky(Hg, t, t, FH, sh.diag, sh.act, sh.frow, &sh.piv_j, &sh.piv_d, 1e-12);
     if (J.bjh) {
       if (tid == 0) { S->sw1 = sw1; bj_start(S, rh, t, 0); }
       return;
     }
-    sw2 = jacobi_any(FH, t, t, rh, J.tol, J.maxsweep, 0, sh, lds, cap);
-  } else {
-    // ---- 3 (continued): the block Jacobi on H has run
-    sw1 = S->sw1;
-    rh = S->nc;
-    sw2 = bj_finish(S, FH, t, rh, 0, J.tol, J.maxsweep, sh, lds, cap);
+  }
+  {
+    // Jacobi on the factor of H (after the block sweeps in stage 3)
+    int base = 0;
+    bool more = true;
+    if (stage == 3) {
+      sw1 = S->sw1;
+      rh = S->nc;
+      base = bj_sweeps(S, more);
+    }
+    sw2 = base + (more ? jacobi_any(FH, t, t, rh, J.tol, J.maxsweep - base, 0, sh, lds, cap) : 0);
   }
   for (int c = tid; c < t; c += 1024) {
     double s = 0.0;
@@ -674,16 +711,11 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
   }
   __syncthreads();
   // ---- 4. L Y (rows of Rcoef), alpha, beta (sorted by alpha)
-  for (int e = tid; e < t * N; e += 1024) {
-    const int c = e / N, r = e - c * N;      // column c of Y, row r
+  // row r, column c of L Y (column c of Y = column c of FH / its norm)
+  wg_gemm64<false>(Lg, 1, N, FH, 1, t, N, t, t, [&](int r, int c, double v) {
     const double nv = keys[c];
-    double v = 0.0;
-    if (c < rh && nv > 0.0) {
-      for (int k = 0; k < t; ++k) v += Lg[(int64_t)k * N + r] * FH[(int64_t)c * t + k];
-      v /= nv;
-    }
-    J.Rcoef[(int64_t)c * J.ldr + r] = v;    // unsorted for now
-  }
+    J.Rcoef[(int64_t)c * J.ldr + r] = (c < rh && nv > 0.0) ? v / nv : 0.0;    // unsorted for now
+  });
   __syncthreads();
   for (int c = tid; c < t; c += 1024) {
     double a = 0.0, b = 0.0;
