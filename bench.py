@@ -32,10 +32,12 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TF = {"fp64": 78.6, "fp32": 157.3, "mixed": 2516.6}
 # 256 CUs x 4 SIMDs x 16 FP64 FMA lanes x 2 flops x 2.4 GHz
 FP64_VEC_PEAK_TF = 78.6
-# HBM bytes per launch of the sketch kernel on the 20000/15000 x 5000 workload,
-# from FETCH_SIZE and WRITE_SIZE scaled by a copy kernel of known size
-# (profiles/hbm_counters_*.md)
-TRAFFIC_SKETCH = 756.06e6
+# HBM bytes per launch on the 20000/15000 x 5000 workload, from FETCH_SIZE and
+# WRITE_SIZE scaled by a copy kernel of known size (profiles/hbm_counters_*.md):
+# the sketch kernel, k_small (mean of its two launches), k_bjround
+TRAFFIC_SKETCH = 756.0e6
+TRAFFIC_SMALL = 1.27e6
+TRAFFIC_BJROUND = 0.65e6
 
 
 def log(*a):
@@ -222,11 +224,18 @@ def main():
         roof = {"bound": "alu", "achieved": flops / (dom_ms * 1e-3) / 1e12, "peak": FP64_VEC_PEAK_TF,
                 "unit": "TFLOP/s", "traffic": None}
     elif dom_tag == "small":
-        # one workgroup per pair: two dense symmetric eigendecompositions with
-        # vectors (M: N x N, H: k x k) at 9 n^3 flops each, FP64 vector ALU
-        flops = 9.0 * N ** 3 + 9.0 * k ** 3
-        roof = {"bound": "alu", "achieved": flops / (avg_ms * 1e-3) / 1e12, "peak": FP64_VEC_PEAK_TF,
-                "unit": "TFLOP/s", "traffic": None}
+        # k_small (one workgroup per pair, its launches summed): pivoted
+        # Cholesky of M (N^3 / 3), H = L1^T L1 (l t (t + 1)), pivoted Cholesky
+        # of H (t^3 / 3), one-sided Jacobi on the factor of H (info[6] sweeps
+        # of t (t - 1) / 2 pairs at 12 t flops), L Y (2 N t^2), and the
+        # Jacobi on the factor of M when it is not the block Jacobi's
+        t = k
+        sw1, sw2 = int(res[flag]["info"][5]), int(res[flag]["info"][6])
+        flops = N ** 3 / 3.0 + l * t * (t + 1.0) + t ** 3 / 3.0 + sw2 * 6.0 * t * t * (t - 1) + 2.0 * N * t * t
+        if "bjacobi" not in agg:
+            flops += sw1 * 6.0 * N * N * (N - 1)
+        roof = {"bound": "alu", "achieved": flops / (dom_ms * 1e-3) / 1e12, "peak": FP64_VEC_PEAK_TF,
+                "unit": "TFLOP/s", "traffic": TRAFFIC_SMALL if args.workload == "medium" else None}
     elif dom_tag in ("nn", "tn") and flag == "mixed":
         roof = {"bound": "hbm", "achieved": gbytes / (avg_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "traffic": None}

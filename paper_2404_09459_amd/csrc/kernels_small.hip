@@ -31,6 +31,7 @@ __device__ void chol_regs(const CholJob& J, double* lds) {
   const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
   double* rowk = lds;            // scaled pivot row (np)
   double* xd = lds + 128;        // diagonal of R^{-T} (np)
+  double* d0 = lds + 256;        // diagonal of the Gram (np)
   __shared__ double piv_s, maxd_s;
   __shared__ int bad_s;
   double w[4][4];
@@ -41,6 +42,7 @@ __device__ void chol_regs(const CholJob& J, double* lds) {
     maxd_s = md;
     trace_s = tr;
   }
+  for (int i = tid; i < 128; i += 1024) d0[i] = i < N ? J.gram[(int64_t)i * np + i] : 0.0;
   __syncthreads();
   const double maxdiag = maxd_s;
   double shift = J.shift0 > 0.0 ? J.shift0 * trace_s : 0.0;
@@ -71,7 +73,7 @@ __device__ void chol_regs(const CholJob& J, double* lds) {
       }
       __syncthreads();
       const double piv = piv_s;
-      const double d0k = J.gram[(int64_t)k * np + k];
+      const double d0k = d0[k];
       if (J.trunc && isfinite(piv) && !(piv > CHOL_TRUNC_REL * d0k && piv > 0.0)) {
         // row k is numerically dependent on the rows before it: zero row of
         // L^{-1}, no elimination step
@@ -246,7 +248,7 @@ __device__ void chol_global(const CholJob& J, double* W, double* xd, double* d0)
 
 __global__ __launch_bounds__(1024) void k_chol(const CholJob* __restrict__ jobs, int nj,
                                                double* __restrict__ gscratch) {
-  __shared__ double lds[256];
+  __shared__ double lds[384];
   const CholJob J = jobs[blockIdx.x];
   if (J.npad <= 128) {
     chol_regs(J, lds);
