@@ -704,7 +704,7 @@ int build(rgsvd_plan_s* P, void* ws) {
       SmallJob x{};
       x.stage = stage; x.bjh = bjh(pr) ? 1 : 0;
       x.st = (BJState*)WS(ws, pr.bjs);
-      x.M = (const double*)WS(ws, pr.M); x.ldm = pr.Npad;
+      x.M = (double*)WS(ws, pr.M); x.ldm = pr.Npad;
       x.l1 = pr.l1; x.l2 = pr.l2; x.t = pr.t; x.maxsweep = 40; x.tol = 1e-15;
       x.work = (double*)WS(ws, pr.work);
       x.sigma = pr.out.sigma_B ? pr.out.sigma_B : (double*)WS(ws, pr.sigma);

@@ -483,88 +483,6 @@ __device__ inline int rank_desc(const double* key, int n, int i) {
 }
 
 // --------------------------------------------------------------- k_small --
-// Left-looking diagonally pivoted Cholesky of a K x K PSD matrix S (read
-// from global, ld lds_): P^T S P = R^T R.  Column k of F (K x K, column-major,
-// ld K) is row k of R scattered back to S's row order, so F F^T = S and the
-// columns of F are graded (large first).  Stops at the numerical rank;
-// returns the rank.  diag/act/frow: shared scratch of K entries.
-__device__ int pivoted_cholesky(const double* S, int64_t lds_, int K, double* F, double* diag, int* act,
-                                double* frow, int* piv_j, double* piv_d, double shift) {
-  const int tid = threadIdx.x;
-  for (int e = tid; e < K * K; e += 1024) F[e] = 0.0;
-  for (int i = tid; i < K; i += 1024) { diag[i] = S[(int64_t)i * lds_ + i] + shift; act[i] = 1; }
-  __syncthreads();
-  double dmax0 = 0.0;
-  for (int i = 0; i < K; ++i) dmax0 = fmax(dmax0, diag[i]);
-  int TPR = 1;
-  while (TPR * 2 * K <= 1024 && TPR < 16) TPR *= 2;
-  const int row = tid / TPR, part = tid % TPR;
-  int rank = 0;
-  for (int k = 0; k < K; ++k) {
-    if (tid < 64) {
-      double best = -1.0; int bj = -1;
-      for (int j = tid; j < K; j += 64)
-        if (act[j] && diag[j] > best) { best = diag[j]; bj = j; }
-      for (int o = 32; o > 0; o >>= 1) {
-        double b2 = __shfl_xor(best, o, 64);
-        int j2 = __shfl_xor(bj, o, 64);
-        if (b2 > best || (b2 == best && j2 >= 0 && (bj < 0 || j2 < bj))) { best = b2; bj = j2; }
-      }
-      if (tid == 0) { *piv_j = bj; *piv_d = best; }
-    }
-    __syncthreads();
-    const int js = *piv_j;
-    const double d = *piv_d;
-    if (js < 0 || !(d > 1e-15 * dmax0) || !(d > 0.0)) break;
-    for (int kk = tid; kk < k; kk += 1024) frow[kk] = F[(int64_t)kk * K + js];
-    __syncthreads();
-    const double sd = sqrt(d), rd = 1.0 / sd;
-    double acc = 0.0;
-    if (row < K && act[row])
-      for (int kk = part; kk < k; kk += TPR) acc += F[(int64_t)kk * K + row] * frow[kk];
-    for (int o = TPR / 2; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-    __syncthreads();
-    if (row < K && part == 0) {
-      double v = 0.0;
-      if (row == js) v = sd;
-      else if (act[row]) v = (S[(int64_t)row * lds_ + js] + (row == js ? shift : 0.0) - acc) * rd;
-      F[(int64_t)k * K + row] = v;
-      if (act[row] && row != js) diag[row] -= v * v;
-    }
-    if (tid == 0) act[js] = 0;
-    __syncthreads();
-    rank = k + 1;
-  }
-  __syncthreads();
-  return rank;
-}
-
-struct SmallShared {
-  double keys[SMALL_MAXN];
-  double diag[SMALL_MAXN];
-  double frow[SMALL_MAXN];
-  int perm[SMALL_MAXN];
-  int act[SMALL_MAXN];
-  int scratch[8];
-  int piv_j;
-  double piv_d;
-  double kth;
-};
-
-// G lanes per column pair and EM entries per lane (G * EM >= nr): 16 x 8
-// for small factors in LDS, 32 x 16 otherwise (the global-memory sweeps
-// only finish factors that the block Jacobi left unconverged)
-__device__ __attribute__((always_inline)) inline int
-jacobi_any(double* A, int lda, int nr, int nc, double tol, int maxsweep, int topk, SmallShared& sh,
-           double* lds, int cap) {
-  double* k = sh.keys;
-  int* sc = sh.scratch;
-  double* kt = &sh.kth;
-  if (nr <= 128 && (int64_t)nc * nr <= cap)
-    return jacobi_os<16, 8>(A, lda, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
-  return jacobi_os<32, 16>(A, lda, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
-}
-
 // C = A B in one workgroup on FP64 MFMA (16 x 16 output tiles, one per
 // wave at a time, k in steps of 4): element (i, k) of A at
 // A[i sai + k sak], element (k, j) of B at B[k sbk + j sbj]; I x J output,
@@ -598,6 +516,111 @@ wg_gemm64(const double* A, int64_t sai, int64_t sak, const double* B, int64_t sb
       if (i < I && jb < J && (!SYM || i <= jb)) store(i, jb, acc[q]);
     }
   }
+}
+
+// Diagonally pivoted Cholesky of a K x K PSD matrix S (row-major, ld ld,
+// both triangles; overwritten): P^T (S + shift I) P = R^T R.  Column k of F
+// (K x K, column-major, ld K) is row k of R scattered back to S's row order,
+// so F F^T = S + shift I and the columns of F are graded (large first).
+// Stops at the numerical rank (pivot <= 1e-15 of the largest diagonal) and
+// returns it; *trace receives the trace of S + shift I.
+//
+// Right-looking in panels of PC_B columns: a step reads the pivot's row of
+// the trailing matrix (contiguous, by symmetry its column), subtracts the
+// panel's earlier columns (held in LDS, Fb: PC_B x K), and scales; after a
+// panel the trailing matrix takes the panel's rank-PC_B update on MFMA.
+// diag/act: shared scratch of K entries; one thread per row.
+constexpr int PC_B = 16;
+__device__ int pivoted_cholesky(double* S, int64_t ld, int K, double* F, double* diag, int* act, double* Fb,
+                                int* piv_j, double* piv_d, double shift, double* trace) {
+  const int tid = threadIdx.x;
+  for (int e = tid; e < K * K; e += 1024) F[e] = 0.0;
+  for (int i = tid; i < K; i += 1024) { diag[i] = S[(int64_t)i * ld + i] + shift; act[i] = 1; }
+  __syncthreads();
+  double dmax0 = 0.0;
+  for (int i = 0; i < K; ++i) dmax0 = fmax(dmax0, diag[i]);
+  if (tid == 0) {
+    double tr = 0.0;
+    for (int i = 0; i < K; ++i) tr += diag[i];
+    *trace = tr;
+  }
+  int rank = 0;
+  for (int k0 = 0; k0 < K; k0 += PC_B) {
+    const int kend = k0 + PC_B < K ? k0 + PC_B : K;
+    int k = k0;
+    for (; k < kend; ++k) {
+      if (tid < 64) {
+        double best = -1.0; int bj = -1;
+        for (int j = tid; j < K; j += 64)
+          if (act[j] && diag[j] > best) { best = diag[j]; bj = j; }
+        for (int o = 32; o > 0; o >>= 1) {
+          double b2 = __shfl_xor(best, o, 64);
+          int j2 = __shfl_xor(bj, o, 64);
+          if (b2 > best || (b2 == best && j2 >= 0 && (bj < 0 || j2 < bj))) { best = b2; bj = j2; }
+        }
+        if (tid == 0) { *piv_j = bj; *piv_d = best; }
+      }
+      __syncthreads();
+      const int js = *piv_j;
+      const double d = *piv_d;
+      if (js < 0 || !(d > 1e-15 * dmax0) || !(d > 0.0)) break;
+      const double sd = sqrt(d), rd = 1.0 / sd;
+      if (tid < K) {
+        double v = 0.0;
+        const bool on = act[tid];
+        if (tid == js) {
+          v = sd;
+          act[tid] = 0;
+        } else if (on) {
+          double a = S[(int64_t)js * ld + tid];
+          for (int c = 0; c < k - k0; ++c) a -= Fb[c * K + tid] * Fb[c * K + js];
+          v = a * rd;
+          diag[tid] -= v * v;
+        }
+        Fb[(k - k0) * K + tid] = v;
+        F[(int64_t)k * K + tid] = v;
+      }
+      __syncthreads();
+      rank = k + 1;
+    }
+    if (k < kend) break;
+    if (kend < K) {
+      wg_gemm64<true>(Fb, 1, K, Fb, K, 1, K, K, kend - k0, [&](int i, int j, double v) {
+        S[(int64_t)i * ld + j] -= v;
+        if (i != j) S[(int64_t)j * ld + i] -= v;
+      });
+      __syncthreads();
+    }
+  }
+  __syncthreads();
+  return rank;
+}
+
+struct SmallShared {
+  double keys[SMALL_MAXN];
+  double diag[SMALL_MAXN];
+  double frow[SMALL_MAXN];
+  int perm[SMALL_MAXN];
+  int act[SMALL_MAXN];
+  int scratch[8];
+  int piv_j;
+  double piv_d;
+  double kth;
+  double trace;
+};
+
+// G lanes per column pair and EM entries per lane (G * EM >= nr): 16 x 8
+// for small factors in LDS, 32 x 16 otherwise (the global-memory sweeps
+// only finish factors that the block Jacobi left unconverged)
+__device__ __attribute__((always_inline)) inline int
+jacobi_any(double* A, int lda, int nr, int nc, double tol, int maxsweep, int topk, SmallShared& sh,
+           double* lds, int cap) {
+  double* k = sh.keys;
+  int* sc = sh.scratch;
+  double* kt = &sh.kth;
+  if (nr <= 128 && (int64_t)nc * nr <= cap)
+    return jacobi_os<16, 8>(A, lda, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
+  return jacobi_os<32, 16>(A, lda, nr, nc, tol, maxsweep, topk, k, sc, kt, lds, cap);
 }
 
 // Block Jacobi hand-over: the state for a factor of nc columns and nr rows
@@ -642,15 +665,18 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
   if (stage <= 2) {
     // ---- 1. eigen-decomposition of M
     int rank, base = 0;
+    double trM;
     bool more = true;
     if (stage <= 1) {
-      rank = pivoted_cholesky(J.M, J.ldm, N, F, sh.diag, sh.act, sh.frow, &sh.piv_j, &sh.piv_d, 0.0);
+      rank = pivoted_cholesky(J.M, J.ldm, N, F, sh.diag, sh.act, lds, &sh.piv_j, &sh.piv_d, 0.0, &sh.trace);
+      trM = sh.trace;
       if (stage == 1) {
-        if (tid == 0) { S->rank = rank; bj_start(S, rank, N, t < rank ? t : rank); }
+        if (tid == 0) { S->rank = rank; S->trM = trM; bj_start(S, rank, N, t < rank ? t : rank); }
         return;
       }
     } else {
       rank = S->rank;
+      trM = S->trM;
       base = bj_sweeps(S, more);
     }
     const int tt = t < rank ? t : rank;
@@ -666,8 +692,7 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
     __syncthreads();
     // sigma_B: t dominant singular values of B, then the tail's Frobenius norm
     if (tid == 0) {
-      double tr = 0.0, top = 0.0;
-      for (int i = 0; i < N; ++i) tr += J.M[(int64_t)i * J.ldm + i];
+      double tr = trM, top = 0.0;
       for (int i = 0; i < t; ++i) { double v = keys[perm[i]]; top += v * v; }
       sh.kth = sqrt(fmax(0.0, tr - top));
     }
@@ -688,7 +713,7 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
       Hg[(int64_t)j * t + i] = v;
     });
     __syncthreads();
-    rh = pivoted_cholesky(Hg, t, t, FH, sh.diag, sh.act, sh.frow, &sh.piv_j, &sh.piv_d, 1e-12);
+    rh = pivoted_cholesky(Hg, t, t, FH, sh.diag, sh.act, lds, &sh.piv_j, &sh.piv_d, 1e-12, &sh.trace);
     if (J.bjh) {
       if (tid == 0) { S->sw1 = sw1; bj_start(S, rh, t, 0); }
       return;

@@ -35,7 +35,8 @@ struct BJState {
   int32_t sweeps, rank, sw1, pad;   // sweeps started; rank of M; sweeps on M
   int32_t rot[2];                   // rotations seen in the sweep of that parity
   double thr;                       // skip threshold of the sweep (-1: none)
-  double pad2[3];
+  double trM;                       // trace of M (M is overwritten by its factorisation)
+  double pad2[2];
 };
 
 // One compressed pair: M = B B^T (N x N, ldm), the Gram of the stacked
@@ -46,7 +47,7 @@ struct BJState {
 // forms H, factors it and stops before its Jacobi when bjh is set (else
 // runs to the end); 3 finishes the Jacobi on H and runs to the end.
 struct SmallJob {
-  const double* M; int64_t ldm;
+  double* M; int64_t ldm;           // overwritten by the pivoted Cholesky
   int32_t l1, l2, t, maxsweep;
   double tol;
   int32_t stage, bjh;
