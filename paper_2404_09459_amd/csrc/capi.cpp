@@ -46,7 +46,7 @@ inline int ct_of(int L) {
 }
 
 enum Kind { K_ZERO, K_COPY, K_GEN, K_NN, K_AB, K_GRAM, K_RED, K_CHOL, K_SMALL, K_SIGN, K_SCALE, K_GW, K_GTQ,
-            K_CVT, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP, K_BJINIT, K_BJROUND };
+            K_PACK, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP, K_BJINIT, K_BJROUND };
 
 enum Tag { T_ZERO, T_COPY, T_GEN, T_NN, T_TN, T_RED, T_GRAM, T_CHOL, T_SX, T_SMALL, T_RECOVER, T_SIGN,
            T_MGRAM, T_BJAC, T_NTAGS };
@@ -65,14 +65,15 @@ struct Stage {
 };
 
 struct CopyJob { const uint32_t* src; uint32_t* dst; int64_t nwords; };
-struct CvtJobH { const float* src; void* dst; int64_t ld; int32_t rows, cols; };
+struct PackJobH { const float* src; void* dst; int64_t ld; int32_t L, nst, bf16, pad; };
 
 struct SideLay {
   int m = 0, n = 0, l = 0, L = 0, which = 0, pair = 0;
   int ldy = 0, ldw = 0;
   int nchunk = 1, mchunk = 0;
   int gch_m = 1, gcl_m = 0, gch_n = 1, gcl_n = 0;
-  size_t Yt = 0, Wt = 0, part = 0, gpart = 0, gram = 0, sinv = 0, Yt16 = 0, Wt16 = 0;
+  size_t Yt = 0, Wt = 0, part = 0, gpart = 0, gram = 0, sinv = 0;
+  size_t Yt16 = 0, Wt16 = 0, Yp32 = 0, Wp32 = 0;   // packed BF16 / FP32 operands (fragment order)
   const void* G = nullptr; int64_t ldg = 0;
   uint64_t seed = 0; int stream = 1;
   // adaptive basis (Algorithm 1): Omega block buffer, rows formed so far,
@@ -195,6 +196,10 @@ int layout(rgsvd_plan_s* P) {
       if (prec == PBF) {
         s.Yt16 = take((size_t)s.L * s.ldy * 2);
         s.Wt16 = take((size_t)s.L * s.ldw * 2);
+      }
+      if (prec != P64) {
+        s.Yp32 = take((size_t)s.L * s.ldy * 4);
+        s.Wp32 = take((size_t)s.L * s.ldw * 4);
       }
       s.part = take((size_t)s.nchunk_max * s.L * s.ldw * psz);
       int gch = std::max(s.gch_m, s.gch_n);
@@ -356,11 +361,23 @@ int build(rgsvd_plan_s* P, void* ws) {
       }
       Stage& st = B.add(K_GEN, j, tl); st.f64 = (pw == P64); st.tag = T_GEN;
     }
+    if (pw != P64) {
+      // the 16 probe columns in FP32 fragment order
+      std::vector<PackJobH> j; std::vector<int> tl;
+      for (auto& s : S) {
+        PackJobH c{};
+        c.src = (const float*)WS(ws, s.Wt); c.dst = WS(ws, s.Wp32);
+        c.ld = s.ldw; c.L = 16; c.nst = (s.n + 15) / 16; c.bf16 = 0;
+        j.push_back(c);
+        tl.push_back((int)(((int64_t)c.nst * 64 + 255) / 256));
+      }
+      B.add(K_PACK, j, tl).tag = T_ZERO;
+    }
     {
       std::vector<NnJob> j; std::vector<int> tl;
       for (auto& s : S) {
         NnJob x{};
-        x.G = s.G; x.Wt = WS(ws, s.Wt); x.Yt = WS(ws, s.Yt);
+        x.G = s.G; x.Wt = WS(ws, pw == P64 ? s.Wt : s.Wp32); x.Yt = WS(ws, s.Yt);
         x.ldg = s.ldg; x.ldw = s.ldw; x.ldy = s.ldy; x.m = s.m; x.n = s.n; x.L = 16;
         j.push_back(x);
         tl.push_back((s.m + 15) / 16);
@@ -412,28 +429,34 @@ int build(rgsvd_plan_s* P, void* ws) {
     st.f64 = (prec == P64); st.tag = T_GEN;
   }
 
-  // bf16 copies of the W (ymat = false) or Q (ymat = true) buffers
-  auto add_cvt = [&](bool ymat) {
-    std::vector<CvtJobH> j; std::vector<int> tl;
+  // the W (ymat = false) or Q (ymat = true) buffers packed in MFMA fragment
+  // order for a BF16 or FP32 pass (k-steps of 32 or 16 columns)
+  auto pack_dst = [&](const SideLay& s, bool ymat, int p) -> size_t {
+    return p == PBF ? (ymat ? s.Yt16 : s.Wt16) : (ymat ? s.Yp32 : s.Wp32);
+  };
+  auto add_pack = [&](bool ymat, int p) {
+    std::vector<PackJobH> j; std::vector<int> tl;
+    const int ks = p == PBF ? 32 : 16;
     for (auto& s : S) {
-      CvtJobH c{};
+      PackJobH c{};
+      const int len = ymat ? s.m : s.n;
       c.src = (const float*)WS(ws, ymat ? s.Yt : s.Wt);
-      c.dst = WS(ws, ymat ? s.Yt16 : s.Wt16);
-      c.ld = ymat ? s.ldy : s.ldw; c.rows = s.L; c.cols = (int)c.ld;
+      c.dst = WS(ws, pack_dst(s, ymat, p));
+      c.ld = ymat ? s.ldy : s.ldw; c.L = s.L; c.nst = (len + ks - 1) / ks; c.bf16 = p == PBF;
       j.push_back(c);
-      tl.push_back((int)(((int64_t)s.L * c.ld / 4 + 255) / 256));
+      tl.push_back((int)(((int64_t)c.nst * (s.L / 16) * 64 + 255) / 256));
     }
-    B.add(K_CVT, j, tl).tag = T_ZERO;
+    B.add(K_PACK, j, tl).tag = T_ZERO;
   };
 
   auto add_nn = [&](int p) {
-    if (p == PBF) add_cvt(false);
+    if (p != P64) add_pack(false, p);
     std::vector<NnJob> j; std::vector<int> tl;
     const bool rt4_ok = !(p == P64 || gt == 0 || ctL > 8);
     int rt = P->tune_rt ? (P->tune_rt == 4 && rt4_ok ? 4 : 1) : (rt4_ok ? 4 : 1);
     for (auto& s : S) {
       NnJob x{};
-      x.G = s.G; x.Wt = WS(ws, p == PBF ? s.Wt16 : s.Wt); x.Yt = WS(ws, s.Yt);
+      x.G = s.G; x.Wt = WS(ws, p == P64 ? s.Wt : pack_dst(s, false, p)); x.Yt = WS(ws, s.Yt);
       x.ldg = s.ldg; x.ldw = s.ldw; x.ldy = s.ldy; x.m = s.m; x.n = s.n; x.L = s.L;
       j.push_back(x);
       tl.push_back((s.m + 16 * rt - 1) / (16 * rt));
@@ -488,7 +511,7 @@ int build(rgsvd_plan_s* P, void* ws) {
 
   // G^T Q (or Q^T G) into the Wt buffers: split over row chunks then reduced
   auto add_tn = [&](int p) {
-    if (p == PBF) add_cvt(true);
+    if (p != P64) add_pack(true, p);
     std::vector<AbJob> aj; std::vector<int> atl;
     std::vector<RedJob> rj; std::vector<int> rtl;
     const bool js4_ok = !(p == P64 || gt == 0 || ctL > 8);
@@ -500,7 +523,10 @@ int build(rgsvd_plan_s* P, void* ws) {
         int r0 = c * s.mchunk;
         int rows = std::min(s.mchunk, s.m - r0);
         AbJob a{};
-        a.A = (const char*)WS(ws, p == PBF ? s.Yt16 : s.Yt) + (size_t)r0 * asz; a.lda = s.ldy;
+        // packed operands start at the chunk's first k-step (r0 is a multiple of 32)
+        a.A = p == P64 ? (const char*)WS(ws, s.Yt) + (size_t)r0 * asz
+                       : (const char*)WS(ws, pack_dst(s, true, p)) + (size_t)r0 * s.L * asz;
+        a.lda = s.ldy;
         a.B = (const char*)s.G + (size_t)r0 * s.ldg * (gt == 0 ? 8 : 4); a.ldb = s.ldg;
         a.D = WS(ws, s.part) + (size_t)c * s.L * s.ldw * psz; a.ldd = s.ldw;
         a.rows = s.L; a.K = rows; a.J = s.n; a.accumulate = 0; a.colscale = nullptr;
@@ -946,7 +972,7 @@ int enqueue(rgsvd_plan_s* P, void* ws, hipStream_t st) {
       case K_SCALE: launch_scale((const SignJob*)j, pre, s.nj, s.tiles, st); break;
       case K_GW: launch_gw(s.prec, s.gdt, s.rt, s.ct, (const NnJob*)j, pre, s.nj, s.tiles, st); break;
       case K_GTQ: launch_gtq(s.prec, s.gdt, s.ct, s.js, (const AbJob*)j, pre, s.nj, s.tiles, st); break;
-      case K_CVT: launch_cvt(j, pre, s.nj, s.tiles, st); break;
+      case K_PACK: launch_pack(j, pre, s.nj, s.tiles, st); break;
       case K_SUMSQ: hipLaunchKernelGGL(k_sumsq, dim3(s.tiles), dim3(256), 0, st, (const SumsqJob*)j, pre, s.nj); break;
       case K_SUMFIN:
         hipLaunchKernelGGL(k_sumfin, dim3((s.nj + 63) / 64), dim3(64), 0, st, (const SumsqFin*)j, s.nj);

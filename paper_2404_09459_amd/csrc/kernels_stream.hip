@@ -3,14 +3,17 @@
 //  k_gw  : Y = G W          (the sketch G Omega and the power step G W)
 //  k_gtq : partial Q^T G    (the power step G^T Q and the projection B = Q^T G
 //                            of Algorithm 2, one row chunk of G per job)
-//  k_cvt : fp32 -> bf16 copy of a small operand (mixed precision)
+//  k_pack: the small operand (W^T or Q^T, FP32) in MFMA fragment order, in
+//          the compute type of the pass (BF16 or FP32)
 //
 // Design: one wave per workgroup, no LDS and no barriers.  G is streamed from
 // HBM straight into registers (each lane a contiguous run of k values); the
 // small operand (W^T or Q^T, a few MB, L2-resident) is read as MFMA fragments
-// directly from L2 (each lane one contiguous 16-32 byte run).  Both operands
-// use the same k assignment (lane group g = lane/16 owns k = g*KL .. g*KL+KL-1
-// of each KS-wide step), so no operand is ever transposed.
+// directly from L2.  Both operands use the same k assignment (lane group
+// g = lane/16 owns k = g*KL .. g*KL+KL-1 of each KS-wide step), so no operand
+// is ever transposed.  In the BF16 and FP32 passes the small operand is
+// packed in fragment order (k_pack): the fragment of one k-step and one
+// 16-row tile is 64 x KL contiguous elements, one 1 KB load per wave.
 #include "common.hpp"
 #include "gemm.hpp"
 #include "jobs.hpp"
@@ -106,6 +109,13 @@ __device__ inline void sload(typename St<P>::cT* out, const typename St<P>::cT* 
   }
 }
 
+// Fragment order of a packed small operand with ctn 16-row tiles: element
+// (row c, column k) sits at frag_off(k / KS, c / 16, lane, ctn) * KL + k % KL,
+// lane = ((k % KS) / KL) * 16 + c % 16.
+__device__ __host__ inline int64_t frag_off(int64_t st, int b, int ln, int ctn) {
+  return (st * ctn + b) * 64 + ln;
+}
+
 // ------------------------------------------------------------------ k_gw --
 // Job: Yt (L x ldy) = (G W)^T with W given as Wt (L x ldw, compute type,
 // zero beyond column n).  Wave tile: RT*16 rows of G, all CT column tiles.
@@ -129,9 +139,10 @@ __global__ __launch_bounds__(64) void k_gw(const NnJob* __restrict__ jobs, const
   int roff[RT];
 #pragma unroll
   for (int a = 0; a < RT; ++a) roff[a] = (a * 16 + li) * (int)J.ldg * esz;
+  constexpr bool PK = P != P64;     // packed W (fragment order)
   const cT* wrow[CT];
 #pragma unroll
-  for (int b = 0; b < CT; ++b) wrow[b] = (const cT*)J.Wt + (int64_t)(b * 16 + li) * J.ldw;
+  for (int b = 0; b < CT; ++b) wrow[b] = (const cT*)J.Wt + (PK ? 0 : (int64_t)(b * 16 + li) * J.ldw);
 
   acc_t acc[RT][CT];
 #pragma unroll
@@ -148,7 +159,7 @@ __global__ __launch_bounds__(64) void k_gw(const NnJob* __restrict__ jobs, const
     for (int a = 0; a < RT; ++a) gload<TG, aT, KL>(ga[buf][a], rs, roff[a] + k * esz);
 #pragma unroll
     for (int b = 0; b < CT; ++b)
-      if (b < ctn) sload<P>(wb[buf][b], wrow[b] + k);
+      if (b < ctn) sload<P>(wb[buf][b], PK ? wrow[b] + frag_off(st, b, ln, ctn) * KL : wrow[b] + k);
   };
 #pragma unroll
   for (int b = 0; b < NB - 1; ++b)
@@ -232,9 +243,10 @@ __global__ __launch_bounds__(64) void k_gtq(const AbJob* __restrict__ jobs, cons
   bool cok[JS];
 #pragma unroll
   for (int q = 0; q < JS; ++q) cok[q] = col0 + q < J.J;
+  constexpr bool PK = P != P64;     // packed Q^T (fragment order, from the chunk's first step)
   const cT* arow[CT];
 #pragma unroll
-  for (int b = 0; b < CT; ++b) arow[b] = (const cT*)J.A + (int64_t)(b * 16 + li) * J.lda;
+  for (int b = 0; b < CT; ++b) arow[b] = (const cT*)J.A + (PK ? 0 : (int64_t)(b * 16 + li) * J.lda);
 
   acc_t acc[CT][JS];
 #pragma unroll
@@ -251,7 +263,7 @@ __global__ __launch_bounds__(64) void k_gtq(const AbJob* __restrict__ jobs, cons
     for (int e = 0; e < KL; ++e) gload<TG, bT, JS>(gb[buf][e], rs, (k + e) * (int)J.ldb * esz + coff);
 #pragma unroll
     for (int b = 0; b < CT; ++b)
-      if (b < ctn) sload<P>(af[buf][b], arow[b] + k);
+      if (b < ctn) sload<P>(af[buf][b], PK ? arow[b] + frag_off(st, b, ln, ctn) * KL : arow[b] + k);
   };
 #pragma unroll
   for (int b = 0; b < NB - 1; ++b)
@@ -300,23 +312,35 @@ __global__ __launch_bounds__(64) void k_gtq(const AbJob* __restrict__ jobs, cons
   }
 }
 
-// ----------------------------------------------------------------- k_cvt --
-// fp32 -> bf16 copy of rows x cols (ld in elements for both)
-struct CvtJob { const float* src; __bf16* dst; int64_t ld; int32_t rows, cols; };
+// ---------------------------------------------------------------- k_pack --
+// FP32 operand (L x ld, Xt layout) -> fragment order in BF16 (KL = 8) or
+// FP32 (KL = 4) for nst k-steps of KS = 4 KL columns; nst * KS <= ld.  One
+// thread per fragment piece (KL elements); consecutive threads write
+// consecutive pieces.
+struct PackJob { const float* src; void* dst; int64_t ld; int32_t L, nst, bf16, pad; };
 
-__global__ __launch_bounds__(256) void k_cvt(const CvtJob* __restrict__ jobs, const int* __restrict__ pre,
-                                             int nj) {
+__global__ __launch_bounds__(256) void k_pack(const PackJob* __restrict__ jobs, const int* __restrict__ pre,
+                                              int nj) {
   const int jb = find_side(pre, nj, blockIdx.x);
-  const CvtJob J = jobs[jb];
-  const int64_t i = ((int64_t)(blockIdx.x - pre[jb]) * 256 + threadIdx.x) * 4;
-  const int64_t tot = (int64_t)J.rows * J.ld;
-  if (i >= tot) return;
-  if (i + 4 <= tot) {
-    f4 v = *(const f4*)(J.src + i);
+  const PackJob J = jobs[jb];
+  const int ctn = J.L >> 4, KL = J.bf16 ? 8 : 4;
+  const int64_t piece = (int64_t)(blockIdx.x - pre[jb]) * 256 + threadIdx.x;
+  if (piece >= (int64_t)J.nst * ctn * 64) return;
+  const int ln = (int)(piece & 63);
+  const int64_t q = piece >> 6;
+  const int b = (int)(q % ctn);
+  const int64_t st = q / ctn;
+  const int c = b * 16 + (ln & 15);
+  const int64_t k = st * 4 * KL + (ln >> 4) * KL;
+  const float* src = J.src + (int64_t)c * J.ld + k;
+  if (J.bf16) {
+    const f4 v0 = *(const f4*)src, v1 = *(const f4*)(src + 4);
+    __bf16 o[8];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) J.dst[i + e] = (__bf16)v[e];
+    for (int e = 0; e < 4; ++e) { o[e] = (__bf16)v0[e]; o[4 + e] = (__bf16)v1[e]; }
+    __builtin_memcpy((__bf16*)J.dst + piece * 8, o, 16);
   } else {
-    for (int64_t e = i; e < tot; ++e) J.dst[e] = (__bf16)J.src[e];
+    *(f4*)((float*)J.dst + piece * 4) = *(const f4*)src;
   }
 }
 
@@ -375,8 +399,8 @@ void launch_gtq(int prec, int gdt, int ct, int js, const AbJob* j, const int* pr
   }
 }
 
-void launch_cvt(const void* j, const int* pre, int nj, int tiles, hipStream_t st) {
-  hipLaunchKernelGGL(k_cvt, dim3(tiles), dim3(256), 0, st, (const CvtJob*)j, pre, nj);
+void launch_pack(const void* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack, dim3(tiles), dim3(256), 0, st, (const PackJob*)j, pre, nj);
 }
 
 }  // namespace rg

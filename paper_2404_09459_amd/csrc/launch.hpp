@@ -27,5 +27,5 @@ void launch_gw(int prec, int gdt, int rt, int ct, const NnJob* j, const int* pre
                hipStream_t st);
 void launch_gtq(int prec, int gdt, int ct, int js, const AbJob* j, const int* pre, int nj, int tiles,
                 hipStream_t st);
-void launch_cvt(const void* j, const int* pre, int nj, int tiles, hipStream_t st);
+void launch_pack(const void* j, const int* pre, int nj, int tiles, hipStream_t st);
 }  // namespace rg
