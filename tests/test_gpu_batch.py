@@ -155,3 +155,49 @@ def test_batch_mixed_accuracy_gate(dev, batch, refs):
             full += 1
             assert dd <= 1e-5
     assert full >= 3
+
+
+def test_batch_block_jacobi_sizes(dev):
+    """A batch whose pairs take both Jacobi paths: l1 + l2 = 60 (one workgroup,
+    LDS), 160 (block Jacobi, 16-column blocks) and 300 (block Jacobi, 8-column
+    blocks, and t = 140 > 100, so H's factor takes the block Jacobi too).
+    Shared rank exactly k over a 1e-7 floor, so every GSV is pinned: FP64
+    parity 1e-10 per pair, and bit-identical replays of the captured graph."""
+    from oracle import rgsvd as O
+    from paper_2404_09459_amd import inputs as I
+    from paper_2404_09459_amd import rgsvd as R
+    cfg = [(700, 600, 200, 20), (1200, 1000, 300, 70), (1500, 1400, 400, 140)]
+    specs, pairs, refs = [], [], []
+    for i, (m, p, n, k) in enumerate(cfg):
+        j = np.arange(k)
+        G1, G2 = I.lowrank_pair(m, p, n, k, 0.97 ** j, 0.95 ** j, 31 + i, noise_entry=1e-7)
+        specs.append(dict(m=m, p=p, n=n, k=k))
+        pairs.append((G1, G2))
+        refs.append(O.rgsvd(G1, G2, k, OVERSAMPLE, Q, 2000 + i))
+    descs = [R.make_desc(s["m"], s["p"], s["n"], s["k"], OVERSAMPLE, Q, 2000 + i, R.F64, "fp64")
+             for i, s in enumerate(specs)]
+    plan = R.BatchPlan(descs, dev)
+    dpairs = [(torch.from_numpy(a).to(dev), torch.from_numpy(b).to(dev)) for a, b in pairs]
+    plan.bind(dpairs)
+    plan.run()
+    torch.cuda.synchronize()
+    first = _host(plan.outs)
+    for i, (got, ref, s) in enumerate(zip(first, refs, specs)):
+        da = np.max(np.abs(got["alpha"] - ref["alpha"]))
+        db = np.max(np.abs(got["beta"] - ref["beta"]))
+        dth = np.max(np.abs(got["theta"] - ref["theta"]))
+        dd = np.max(np.abs(got["D"] - [ref["D1"], ref["D2"]]))
+        _say(f"  pair {i} l1+l2={2 * (s['k'] + OVERSAMPLE)} k={s['k']}: |da|={da:.1e} |db|={db:.1e}"
+             f" |dtheta|={dth:.1e} |dD|={dd:.1e} info={got['info'].tolist()}")
+        assert max(da, db, dth, dd) <= 1e-10
+        assert got["info"][0] == 0 and got["info"][4] == 0
+    for rep in range(2):
+        for o in plan.outs:
+            for v in o.values():
+                v.fill_(float("nan")) if v.is_floating_point() else v.zero_()
+        plan.run()
+        torch.cuda.synchronize()
+        again = _host(plan.outs)
+        for a, b in zip(first, again):
+            for key in a:
+                assert np.array_equal(a[key], b[key]), (rep, key)

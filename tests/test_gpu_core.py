@@ -218,6 +218,25 @@ def test_gap_separated_parity(dev, m, p, n, k, o, q, dt):
     _check_pair(got, ref)
 
 
+def test_rank_deficient_block_jacobi(dev):
+    """Exactly rank 40 (no noise) with l1 + l2 = 160: the pivoted Cholesky of M
+    stops at rank 40, so the block Jacobi runs on 40 of 160 columns (blocks
+    past the rank are empty).  The spectrum drops by 1e-4 after the first k = 30
+    components, which pins the top-k subspace: FP64 parity 1e-10."""
+    from oracle import rgsvd as O
+    from paper_2404_09459_amd import inputs as I
+    k, r = 30, 40
+    j = np.arange(r)
+    s1 = np.where(j < k, 0.95 ** j, 1e-4 * 0.9 ** (j - k))
+    s2 = np.where(j < k, 0.9 ** j, 1e-4 * 0.8 ** (j - k))
+    G1, G2 = I.lowrank_pair(900, 800, 300, r, s1, s2, 77)
+    _say("parity rank-deficient M: 900/800 x 300, rank 40, k=30, o=50")
+    got = _run(dev, G1, G2, k, 50, 1, 5)
+    ref = O.rgsvd(G1, G2, k, 50, 1, 5)
+    _say(f"   info {got['info'].tolist()}")
+    _check_pair(got, ref, vecs=False)
+
+
 def test_determinism_bitwise(dev):
     from paper_2404_09459_amd import inputs as I
     w = I.small_fp64_pair()
