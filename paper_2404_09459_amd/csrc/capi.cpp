@@ -46,7 +46,7 @@ inline int ct_of(int L) {
 }
 
 enum Kind { K_ZERO, K_COPY, K_GEN, K_NN, K_AB, K_GRAM, K_RED, K_CHOL, K_SMALL, K_SIGN, K_SCALE, K_GW, K_GTQ,
-            K_PACK, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP, K_BJINIT, K_BJROUND };
+            K_PACK, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP, K_BJINIT, K_BJROUND, K_GW4 };
 
 enum Tag { T_ZERO, T_COPY, T_GEN, T_NN, T_TN, T_RED, T_GRAM, T_CHOL, T_SX, T_SMALL, T_RECOVER, T_SIGN,
            T_MGRAM, T_BJAC, T_NTAGS };
@@ -451,6 +451,22 @@ int build(rgsvd_plan_s* P, void* ws) {
 
   auto add_nn = [&](int p) {
     if (p != P64) add_pack(false, p);
+    if (p == P32 && gt == 1) {
+      // FP32 pass over FP32 G (MFMA-bound): 4-wave workgroups of 64 rows
+      // sharing the packed W through LDS.  The HBM-bound BF16 passes keep the
+      // single-wave 64-row tiles, measured faster.
+      std::vector<NnJob> j; std::vector<int> tl;
+      for (auto& s : S) {
+        NnJob x{};
+        x.G = s.G; x.Wt = WS(ws, pack_dst(s, false, p)); x.Yt = WS(ws, s.Yt);
+        x.ldg = s.ldg; x.ldw = s.ldw; x.ldy = s.ldy; x.m = s.m; x.n = s.n; x.L = s.L;
+        j.push_back(x);
+        tl.push_back((s.m + 63) / 64);
+      }
+      Stage& st = B.add(K_GW4, j, tl);
+      st.prec = p; st.gdt = gt; st.ct = ctL; st.tag = T_NN;
+      return;
+    }
     std::vector<NnJob> j; std::vector<int> tl;
     const bool rt4_ok = !(p == P64 || gt == 0 || ctL > 8);
     int rt = P->tune_rt ? (P->tune_rt == 4 && rt4_ok ? 4 : 1) : (rt4_ok ? 4 : 1);
@@ -971,6 +987,7 @@ int enqueue(rgsvd_plan_s* P, void* ws, hipStream_t st) {
       case K_SIGN: launch_sign((const SignJob*)j, pre, s.nj, s.tiles, st); break;
       case K_SCALE: launch_scale((const SignJob*)j, pre, s.nj, s.tiles, st); break;
       case K_GW: launch_gw(s.prec, s.gdt, s.rt, s.ct, (const NnJob*)j, pre, s.nj, s.tiles, st); break;
+      case K_GW4: launch_gw4(s.prec, s.ct, (const NnJob*)j, pre, s.nj, s.tiles, st); break;
       case K_GTQ: launch_gtq(s.prec, s.gdt, s.ct, s.js, (const AbJob*)j, pre, s.nj, s.tiles, st); break;
       case K_PACK: launch_pack(j, pre, s.nj, s.tiles, st); break;
       case K_SUMSQ: hipLaunchKernelGGL(k_sumsq, dim3(s.tiles), dim3(256), 0, st, (const SumsqJob*)j, pre, s.nj); break;

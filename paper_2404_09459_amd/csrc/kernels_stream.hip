@@ -218,6 +218,118 @@ __global__ __launch_bounds__(64) void k_gw(const NnJob* __restrict__ jobs, const
   }
 }
 
+// ----------------------------------------------------------------- k_gw4 --
+// The same product for FP32 G with the packed W shared by a workgroup: 4
+// waves, wave w streams the 16 rows row0 + 16 w .. row0 + 16 w + 15 of G
+// through an NB-deep register pipeline, and the packed W of a k-step
+// (ctn x 64 x KL contiguous elements) is staged once per workgroup into LDS
+// (two buffers, one barrier per step), where the four waves read their
+// fragments.  16-row waves keep every SIMD busy in the MFMA-bound FP32 pass
+// while W's L2 traffic stays that of 64-row tiles.  Used for the FP32
+// passes; the HBM-bound BF16 passes measured faster with k_gw's single-wave
+// 64-row tiles.
+template <int P, int CT, int NB>
+__global__ __launch_bounds__(256) void k_gw4(const NnJob* __restrict__ jobs, const int* __restrict__ pre,
+                                             int nj) {
+  using cT = typename St<P>::cT;
+  using acc_t = typename St<P>::acc;
+  constexpr int KL = St<P>::KL, KS = 4 * KL;
+  constexpr int CH = (CT * 64 + 255) / 256;       // 16-byte chunks of a W step per thread
+  static_assert(KL * sizeof(cT) == 16, "a lane's fragment is 16 bytes");
+  __shared__ u4v wl[2][CT * 64];
+  const int jb = find_side(pre, nj, blockIdx.x);
+  const NnJob J = jobs[jb];
+  const int tile = blockIdx.x - pre[jb];
+  const int tid = threadIdx.x, wave = tid >> 6, ln = tid & 63, g = ln >> 4, li = ln & 15;
+  const int row0 = tile * 64 + wave * 16;
+  const int ctn = J.L >> 4;
+  const int nch = ctn * 64;                        // 16-byte chunks per W step
+  const __amdgpu_buffer_rsrc_t rs =
+      make_rsrc((const char*)J.G + (int64_t)row0 * J.ldg * 4, (int64_t)(J.m - row0) * J.ldg * 4);
+  const int roff = li * (int)J.ldg * 4;
+  const u4v* wsrc = (const u4v*)J.Wt;             // packed, nch chunks per step
+
+  acc_t acc[CT];
+#pragma unroll
+  for (int b = 0; b < CT; ++b) acc[b] = acc_t{0, 0, 0, 0};
+  // W of a step is fetched into a register ring WR steps ahead and stored
+  // into the LDS buffer of its step one step ahead
+  constexpr int WR = 4;
+  static_assert(NB % WR == 0, "ring indices stay compile-time");
+  float ga[NB][KL];
+  u4v wt[WR][CH];
+  const int nsteps = (J.n + KS - 1) / KS;
+  auto gl = [&](int buf, int st) { gload<float, float, KL>(ga[buf], rs, roff + (st * KS + g * KL) * 4); };
+  auto wfetch = [&](int slot, int st) {
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int c = tid + 256 * i;
+      if (c < nch) wt[slot][i] = *(gptr<u4v>)(wsrc + (int64_t)st * nch + c);
+    }
+  };
+  auto wstore = [&](int slot, int buf) {
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int c = tid + 256 * i;
+      if (c < nch) wl[buf][c] = wt[slot][i];
+    }
+  };
+#pragma unroll
+  for (int b = 0; b < NB - 1; ++b)
+    if (b < nsteps) gl(b, b);
+  // tiles past ctn stay zero, so the MFMAs below run unconditionally
+  for (int c = nch + tid; c < CT * 64; c += 256) { wl[0][c] = u4v{0, 0, 0, 0}; wl[1][c] = u4v{0, 0, 0, 0}; }
+#pragma unroll
+  for (int b = 0; b < WR; ++b)
+    if (b < nsteps) wfetch(b, b);
+  wstore(0, 0);
+  __syncthreads();
+  for (int st0 = 0; st0 < nsteps; st0 += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int st = st0 + u;
+      if (st >= nsteps) break;
+      if (st + NB - 1 < nsteps) gl((u + NB - 1) % NB, st + NB - 1);
+      const bool more = st + 1 < nsteps;
+      cT av[KL];
+      const int k = st * KS + g * KL;
+      const bool last = (st + 1) * KS > J.n;      // wave-uniform
+#pragma unroll
+      for (int e = 0; e < KL; ++e) {
+        float v = ga[u][e];
+        if (last && k + e >= J.n) v = 0.0f;      // user padding between rows
+        av[e] = to_c<P>(v);
+      }
+      const u4v* wb = wl[st & 1];
+#pragma unroll
+      for (int b = 0; b < CT; ++b) {
+        const u4v wv = wb[b * 64 + ln];
+        cT wf[KL];
+        __builtin_memcpy(wf, &wv, 16);
+        mma_run<P>(acc[b], av, wf);
+      }
+      if (more) wstore((u + 1) % WR, (st + 1) & 1);
+      if (st + WR < nsteps) wfetch(u % WR, st + WR);   // its slot held W(st), already in LDS
+      __syncthreads();
+    }
+  }
+  // lane holds Y[row0 + out_row(g, ii)][b*16 + li]: four consecutive rows
+  float* Yt = (float*)J.Yt;
+#pragma unroll
+  for (int b = 0; b < CT; ++b) {
+    if (b < ctn) {
+      float* dst = Yt + (int64_t)(b * 16 + li) * J.ldy;
+      const int r = row0 + 4 * g;
+      if (r + 3 < J.m) {
+        *(f4*)(dst + r) = f4{acc[b][0], acc[b][1], acc[b][2], acc[b][3]};
+      } else {
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) if (r + ii < J.m) dst[r + ii] = acc[b][ii];
+      }
+    }
+  }
+}
+
 // ----------------------------------------------------------------- k_gtq --
 // Job (AbJob): D (rows x J, partial, ldd) = A (rows x K) B (K x J): A = Q^T
 // columns of this row chunk in the compute type (lda, zero beyond m), B = the
@@ -354,6 +466,22 @@ static void gw_ct(int ct, const NnJob* j, const int* pre, int nj, int tiles, hip
     case 8: hipLaunchKernelGGL((k_gw<P, TG, RT, 8>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
     default: hipLaunchKernelGGL((k_gw<P, TG, RT, 16>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
   }
+}
+
+template <int P, int NB>
+static void gw4_ct(int ct, const NnJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  switch (ct) {
+    case 1: hipLaunchKernelGGL((k_gw4<P, 1, NB>), dim3(tiles), dim3(256), 0, st, j, pre, nj); break;
+    case 2: hipLaunchKernelGGL((k_gw4<P, 2, NB>), dim3(tiles), dim3(256), 0, st, j, pre, nj); break;
+    case 4: hipLaunchKernelGGL((k_gw4<P, 4, NB>), dim3(tiles), dim3(256), 0, st, j, pre, nj); break;
+    case 8: hipLaunchKernelGGL((k_gw4<P, 8, NB>), dim3(tiles), dim3(256), 0, st, j, pre, nj); break;
+    default: hipLaunchKernelGGL((k_gw4<P, 16, NB>), dim3(tiles), dim3(256), 0, st, j, pre, nj); break;
+  }
+}
+
+void launch_gw4(int prec, int ct, const NnJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  (void)prec;   // FP32 passes only
+  gw4_ct<P32, 8>(ct, j, pre, nj, tiles, st);
 }
 
 void launch_gw(int prec, int gdt, int rt, int ct, const NnJob* j, const int* pre, int nj, int tiles,
