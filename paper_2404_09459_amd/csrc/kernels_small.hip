@@ -246,11 +246,202 @@ __device__ void chol_global(const CholJob& J, double* W, double* xd, double* d0)
   if (tid == 0 && shifted && J.info) atomicOr(J.info + 4, 1 << J.flagbit);
 }
 
+// ------------------------------------------------------ blocked Cholesky --
+// Order N <= CB_MAXN, no truncation: right-looking in 16 x 16 blocks with the
+// working array A (N16 x CB_LDA, N16 = N rounded up to 16, padded with the
+// identity) in LDS.  Per block column kb: one wave factors the diagonal block
+// and inverts its factor in registers (lane j holds column j; scalar
+// broadcasts by readlane); the panel R[kb, jb] = R_kk^{-T} A[kb, jb] and the
+// trailing update A[ib, jb] -= R[kb, ib]^T R[kb, jb] (ib <= jb) run on FP64
+// MFMA, one 16 x 16 block per wave.  R^{-1} then follows by block diagonals,
+// X_ij = -R_ii^{-1} sum_{k=i+1..j} R_ik X_kj.  The upper triangle of A ends
+// holding R and the lower triangle R^{-T} (diagonal separately), the layout
+// the register path produces.  A non-positive or tiny pivot restarts with a
+// shift, as there.
+constexpr int CB_MAXN = 112, CB_LDA = 113;
+constexpr size_t CB_LDS_BYTES = (size_t)(CB_MAXN * CB_LDA + 2 * CB_MAXN) * sizeof(double);
+
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ void chol_blocked(const CholJob& J, double* lds) {
+  const int N = J.N, np = J.npad;
+  const int N16 = (N + 15) & ~15, nb = N16 >> 4;
+  const int tid = threadIdx.x, wave = tid >> 6, ln = tid & 63, g = ln >> 4, r16 = ln & 15;
+  double* A = lds;                               // N16 x CB_LDA
+  double* rdiag = lds + CB_MAXN * CB_LDA;        // diagonal of R^{-T}
+  double* d0 = rdiag + CB_MAXN;                  // Gram diagonal (pivot test)
+  __shared__ int bad_s;
+  __shared__ double trace_s, maxd_s;
+  if (tid == 0) {
+    double md = 0.0, tr = 0.0;
+    for (int i = 0; i < N; ++i) { const double d = J.gram[(int64_t)i * np + i]; md = fmax(md, d); tr += d; }
+    maxd_s = md;
+    trace_s = tr;
+  }
+  for (int i = tid; i < N16; i += 1024) d0[i] = i < N ? J.gram[(int64_t)i * np + i] : 1.0;
+  __syncthreads();
+  const double maxdiag = maxd_s;
+  double shift = J.shift0 > 0.0 ? J.shift0 * trace_s : 0.0;
+  bool shifted = false;
+  for (int attempt = 0;; ++attempt) {
+    for (int e = tid; e < N16 * N16; e += 1024) {
+      const int i = e / N16, j = e - i * N16;
+      double v;
+      if (i < N && j < N) v = J.gram[(int64_t)i * np + j] + (i == j ? shift : 0.0);
+      else v = (i == j) ? 1.0 : 0.0;
+      A[i * CB_LDA + j] = v;
+    }
+    if (tid == 0) bad_s = 0;
+    __syncthreads();
+    for (int kb = 0; kb < nb; ++kb) {
+      const int o = 16 * kb;
+      if (wave == 0) {
+        // factor the diagonal block: lane j < 16 holds column j (upper part)
+        const int j = ln;
+        double d[16];
+        double myinv = 0.0;    // 1 / R_jj of this lane's column
+#pragma unroll
+        for (int i = 0; i < 16; ++i) d[i] = (j < 16 && i <= j) ? A[(o + i) * CB_LDA + o + j] : 0.0;
+        bool bad = false;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+          const double piv = readlane_f64(d[k], k);
+          if (!(piv > 1e-15 * d0[o + k]) || !(piv > 0.0) || !isfinite(piv)) bad = true;
+          const double r = sqrt(piv), ri = 1.0 / r;
+          if (j == k) myinv = ri;
+          if (j >= k) d[k] = (j == k) ? r : d[k] * ri;
+#pragma unroll
+          for (int i = k + 1; i < 16; ++i) {
+            const double rki = readlane_f64(d[k], i);
+            if (j >= i) d[i] -= rki * d[k];
+          }
+        }
+        // R_kk (upper) and 1 / R_jj to LDS; then X = R_kk^{-1}, column j per
+        // lane, from R read back as broadcasts: x_j = 1 / R_jj,
+        // x_i = -(sum_{m=i+1..j} R_im x_m) / R_ii
+        if (j < 16) {
+#pragma unroll
+          for (int i = 0; i < 16; ++i)
+            if (i <= j) A[(o + i) * CB_LDA + o + j] = d[i];
+          rdiag[o + j] = myinv;
+        }
+        double x[16];
+#pragma unroll
+        for (int i = 15; i >= 0; --i) {
+          double acc = 0.0;
+#pragma unroll
+          for (int m = i + 1; m < 16; ++m)
+            if (m <= j) acc += A[(o + i) * CB_LDA + o + m] * x[m];
+          const double rinv = rdiag[o + i];
+          x[i] = (i < j) ? -acc * rinv : (i == j ? rinv : 0.0);
+        }
+        if (j < 16) {
+#pragma unroll
+          for (int i = 0; i < 16; ++i)
+            if (i < j) A[(o + j) * CB_LDA + o + i] = x[i];    // R^{-T} (strict lower)
+        }
+        if (bad && ln == 0) bad_s = 1;
+      }
+      __syncthreads();
+      if (bad_s) break;
+      // panel: R[kb, jb] = R_kk^{-T} A[kb, jb], one block per wave
+      for (int jb = kb + 1 + wave; jb < nb; jb += 16) {
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int m = 4 * kk + g;
+          const double a = m < r16 ? A[(o + r16) * CB_LDA + o + m] : (m == r16 ? rdiag[o + m] : 0.0);
+          const double b = A[(o + m) * CB_LDA + 16 * jb + r16];
+          acc = mma64(a, b, acc);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) A[(o + out_row<0>(g, q)) * CB_LDA + 16 * jb + r16] = acc[q];
+      }
+      __syncthreads();
+      // trailing update of the blocks (ib, jb), kb < ib <= jb
+      const int rem = nb - kb - 1;
+      for (int t = wave; t < rem * (rem + 1) / 2; t += 16) {
+        int ib = 0, tt = t;
+        while (tt >= rem - ib) { tt -= rem - ib; ++ib; }
+        const int jb = kb + 1 + ib + tt;
+        ib += kb + 1;
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int m = 4 * kk + g;
+          acc = mma64(A[(o + m) * CB_LDA + 16 * ib + r16], A[(o + m) * CB_LDA + 16 * jb + r16], acc);
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) A[(16 * ib + out_row<0>(g, q)) * CB_LDA + 16 * jb + r16] -= acc[q];
+      }
+      __syncthreads();
+    }
+    if (!bad_s) break;
+    if (attempt >= 8 || !(maxdiag > 0.0) || !isfinite(maxdiag)) {
+      for (int e = tid; e < np * np; e += 1024) J.sinv[e] = 0.0;
+      if (tid == 0 && J.info)
+        atomicOr(J.info + 4, isfinite(maxdiag) ? (1 << J.flagbit) | FLAG_CHOL_FAIL : FLAG_NONFINITE);
+      return;
+    }
+    shift = (shift == 0.0) ? 1e-14 * maxdiag * (double)N : shift * 100.0;
+    shifted = true;
+    __syncthreads();
+  }
+  // R^{-1} by block diagonals: X_ij (j = i + dd), stored transposed in the
+  // lower block (j, i)
+  for (int dd = 1; dd < nb; ++dd) {
+    for (int i = wave; i + dd < nb; i += 16) {
+      const int j = i + dd;
+      d4 tacc = {0.0, 0.0, 0.0, 0.0};
+      for (int k = i + 1; k <= j; ++k) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int m = 4 * kk + g;
+          const double a = A[(16 * i + r16) * CB_LDA + 16 * k + m];                 // R_ik
+          double b;                                                                   // X_kj[m][r16]
+          if (k < j) b = A[(16 * j + r16) * CB_LDA + 16 * k + m];
+          else b = m < r16 ? A[(16 * j + r16) * CB_LDA + 16 * j + m] : (m == r16 ? rdiag[16 * j + m] : 0.0);
+          tacc = mma64(a, b, tacc);
+        }
+      }
+      // X_ij = -X_ii T; T's accumulator layout is the B operand's
+      d4 xacc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int m = 4 * kk + g;
+        const double a = r16 < m ? A[(16 * i + m) * CB_LDA + 16 * i + r16] : (r16 == m ? rdiag[16 * i + r16] : 0.0);
+        xacc = mma64(a, tacc[kk], xacc);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) A[(16 * j + r16) * CB_LDA + 16 * i + out_row<0>(g, q)] = -xacc[q];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < np * np; e += 1024) {
+    const int i = e / np, j = e - i * np;
+    double v = 0.0;
+    if (i < N && j < N) {
+      if (j < i) v = A[i * CB_LDA + j];
+      else if (j == i) v = rdiag[i];
+    }
+    J.sinv[e] = v;
+  }
+  if (tid == 0 && shifted && J.info) atomicOr(J.info + 4, 1 << J.flagbit);
+}
+
 __global__ __launch_bounds__(1024) void k_chol(const CholJob* __restrict__ jobs, int nj,
                                                double* __restrict__ gscratch) {
   __shared__ double lds[384];
+  extern __shared__ double big[];
   const CholJob J = jobs[blockIdx.x];
-  if (J.npad <= 128) {
+  if (!J.trunc && !J.r && J.N <= CB_MAXN) {
+    chol_blocked(J, big);
+  } else if (J.npad <= 128) {
     chol_regs(J, lds);
   } else {
     double* W = gscratch + (int64_t)blockIdx.x * (CHOL_MAX * CHOL_MAX + 2 * CHOL_MAX);
@@ -1002,7 +1193,12 @@ __global__ __launch_bounds__(256) void k_scale_rows(const SignJob* __restrict__ 
 // ---------------------------------------------------------------- launch --
 void launch_chol(const CholJob* j, int nj, int npad_max, double* gscratch, hipStream_t st) {
   (void)npad_max;
-  hipLaunchKernelGGL(k_chol, dim3(nj), dim3(1024), 0, st, j, nj, gscratch);
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)CB_LDS_BYTES);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_chol, dim3(nj), dim3(1024), CB_LDS_BYTES, st, j, nj, gscratch);
 }
 
 void launch_small(const SmallJob* j, int nj, hipStream_t st) {
