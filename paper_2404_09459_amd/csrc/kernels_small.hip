@@ -722,6 +722,20 @@ wg_gemm64(const double* A, int64_t sai, int64_t sak, const double* B, int64_t sb
 // panel the trailing matrix takes the panel's rank-PC_B update on MFMA.
 // diag/act: shared scratch of K entries; one thread per row.
 constexpr int PC_B = 16;
+
+// (value, index) maximum over the 64 lanes of a wave, ties to the smaller
+// index (negative index: no candidate); every lane ends with the result.
+__device__ __forceinline__ void wave_argmax(double& v, int& j) {
+  auto take = [&](double v2, int j2) {
+    if (v2 > v || (v2 == v && j2 >= 0 && (j < 0 || j2 < j))) { v = v2; j = j2; }
+  };
+  take(dpp_f64<0xB1>(v), __builtin_amdgcn_update_dpp(0, j, 0xB1, 0xF, 0xF, false));
+  take(dpp_f64<0x4E>(v), __builtin_amdgcn_update_dpp(0, j, 0x4E, 0xF, 0xF, false));
+  take(dpp_f64<0x141>(v), __builtin_amdgcn_update_dpp(0, j, 0x141, 0xF, 0xF, false));
+  take(dpp_f64<0x140>(v), __builtin_amdgcn_update_dpp(0, j, 0x140, 0xF, 0xF, false));
+  take(swz16_f64(v), __builtin_amdgcn_ds_swizzle(j, 0x401F));
+  take(__shfl_xor(v, 32, 64), __shfl_xor(j, 32, 64));
+}
 __device__ int pivoted_cholesky(double* S, int64_t ld, int K, double* F, double* diag, int* act, double* Fb,
                                 int* piv_j, double* piv_d, double shift, double* trace) {
   const int tid = threadIdx.x;
@@ -744,11 +758,7 @@ __device__ int pivoted_cholesky(double* S, int64_t ld, int K, double* F, double*
         double best = -1.0; int bj = -1;
         for (int j = tid; j < K; j += 64)
           if (act[j] && diag[j] > best) { best = diag[j]; bj = j; }
-        for (int o = 32; o > 0; o >>= 1) {
-          double b2 = __shfl_xor(best, o, 64);
-          int j2 = __shfl_xor(bj, o, 64);
-          if (b2 > best || (b2 == best && j2 >= 0 && (bj < 0 || j2 < bj))) { best = b2; bj = j2; }
-        }
+        wave_argmax(best, bj);
         if (tid == 0) { *piv_j = bj; *piv_d = best; }
       }
       __syncthreads();
