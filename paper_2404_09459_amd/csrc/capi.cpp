@@ -513,7 +513,9 @@ int build(rgsvd_plan_s* P, void* ws) {
         a.A = WS(ws, s.sinv); a.lda = P->npadG; a.B = X; a.ldb = ld; a.D = X; a.ldd = ld;
         a.rows = s.L; a.K = s.L; a.J = len; a.accumulate = 0; a.colscale = nullptr;
         aj.push_back(a);
-        int js = (sxp == P64) ? 2 : (ctL <= 8 ? 4 : 2);
+        // one column per lane in the FP32 update Q = Y R^{-1}: twice the
+        // workgroups of two, measured faster at l = 110 (the update is latency-bound)
+        int js = (sxp == P64) ? 2 : 1;
         atl.push_back((len + 64 * js - 1) / (64 * js));
       }
       Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = wt; gs.tag = T_GRAM;
@@ -521,7 +523,7 @@ int build(rgsvd_plan_s* P, void* ws) {
       Stage& c = B.add(K_CHOL, cj, ctl); c.npad_max = P->npadG; c.tag = T_CHOL;
       Stage& a = B.add(K_AB, aj, atl);
       a.prec = sxp; a.ta = 0; a.tb = wt; a.td = wt; a.ct = ctL; a.tag = T_SX;
-      a.js = (sxp == P64) ? 2 : (ctL <= 8 ? 4 : 2);
+      a.js = (sxp == P64) ? 2 : 1;
     }
   };
 
@@ -829,11 +831,11 @@ int build(rgsvd_plan_s* P, void* ws) {
         a.rows = pr.t; a.K = seg ? pr.l2 : pr.l1; a.J = (int)pr.n; a.accumulate = seg;
         a.colscale = nullptr;
         aj.push_back(a);
-        atl.push_back((int)((pr.n + 127) / 128));
+        atl.push_back((int)((pr.n + 63) / 64));
       }
       if (!aj.empty()) {
         Stage& a = B.add(K_AB, aj, atl);
-        a.prec = (prec == P64) ? P64 : P32; a.ta = 0; a.tb = wt; a.td = 0; a.ct = ctT; a.js = 2;
+        a.prec = (prec == P64) ? P64 : P32; a.ta = 0; a.tb = wt; a.td = 0; a.ct = ctT; a.js = 1;
         a.tag = T_RECOVER;
       }
     }
@@ -864,12 +866,12 @@ int build(rgsvd_plan_s* P, void* ws) {
         a.rows = pr.t; a.K = s.l; a.J = s.m; a.accumulate = 0;
         a.colscale = pr.out.R ? (const double*)WS(ws, pr.sgn) : nullptr;
         aj.push_back(a);
-        atl.push_back((s.m + 127) / 128);
+        atl.push_back((s.m + 63) / 64);
       }
     }
     if (!aj.empty()) {
       Stage& a = B.add(K_AB, aj, atl);
-      a.prec = (prec == P64) ? P64 : P32; a.ta = 0; a.tb = wt; a.td = 0; a.ct = ctT; a.js = 2;
+      a.prec = (prec == P64) ? P64 : P32; a.ta = 0; a.tb = wt; a.td = 0; a.ct = ctT; a.js = 1;
       a.tag = T_RECOVER;
     }
   }
