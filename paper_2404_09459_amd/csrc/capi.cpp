@@ -46,7 +46,7 @@ inline int ct_of(int L) {
 }
 
 enum Kind { K_ZERO, K_COPY, K_GEN, K_NN, K_AB, K_GRAM, K_RED, K_CHOL, K_SMALL, K_SIGN, K_SCALE, K_GW, K_GTQ,
-            K_PACK, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP, K_BJINIT, K_BJROUND, K_GW4 };
+            K_PACK, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP, K_BJINIT, K_BJROUND, K_GW4, K_ZEROG };
 
 enum Tag { T_ZERO, T_COPY, T_GEN, T_NN, T_TN, T_RED, T_GRAM, T_CHOL, T_SX, T_SMALL, T_RECOVER, T_SIGN,
            T_MGRAM, T_BJAC, T_NTAGS };
@@ -184,11 +184,13 @@ int layout(rgsvd_plan_s* P) {
       s.nchunk_max = std::max(1, std::min(2 * nch, (s.m + 31) / 32));
       // Gram chunks over m and over n
       int nb = P->npadG / 64, nblk = nb * (nb + 1) / 2;
+      // (about 512 tiles in all, but no chunk longer than 1024 rows: a batch of
+      // many sides would otherwise leave one long chunk per side)
       int gt = std::max(1, 512 / std::max(1, nblk * nsides));
-      s.gch_m = std::max(1, std::min((s.m + 255) / 256, gt));
+      s.gch_m = std::max(1, std::min((s.m + 255) / 256, std::max(gt, (s.m + 1023) / 1024)));
       s.gcl_m = (int)upi((s.m + s.gch_m - 1) / s.gch_m, 32);
       s.gch_m = (s.m + s.gcl_m - 1) / s.gcl_m;
-      s.gch_n = std::max(1, std::min((s.n + 255) / 256, gt));
+      s.gch_n = std::max(1, std::min((s.n + 255) / 256, std::max(gt, (s.n + 1023) / 1024)));
       s.gcl_n = (int)upi((s.n + s.gch_n - 1) / s.gch_n, 32);
       s.gch_n = (s.n + s.gcl_n - 1) / s.gcl_n;
       s.Yt = take((size_t)s.L * s.ldy * wsz);
@@ -221,7 +223,7 @@ int layout(rgsvd_plan_s* P) {
     pr.Npad = (int)upi(pr.N, 64);
     int nb = pr.Npad / 64, nblk = nb * (nb + 1) / 2;
     int gt = std::max(1, 512 / std::max(1, nblk * (int)P->pairs.size()));
-    pr.gch = std::max(1, std::min((int)((pr.n + 255) / 256), gt));
+    pr.gch = std::max(1, std::min((int)((pr.n + 255) / 256), std::max(gt, (int)((pr.n + 1023) / 1024))));
     pr.gcl = (int)upi((pr.n + pr.gch - 1) / pr.gch, 32);
     pr.gch = (int)((pr.n + pr.gcl - 1) / pr.gcl);
     pr.mpart = take((size_t)pr.gch * pr.Npad * pr.Npad * 8);
@@ -305,13 +307,18 @@ int build(rgsvd_plan_s* P, void* ws) {
   const bool tail = (part == rgsvd_plan_s::FIXED || part == rgsvd_plan_s::TAIL);
   // 0. zero the W buffers (their padding rows must read as zero) and copy
   //    the info templates
-  if (head) for (auto& s : S) {
-    Stage z; z.kind = K_ZERO; z.tag = T_ZERO; z.zoff = s.Wt;
-    z.zbytes = (size_t)s.L * s.ldw * (prec == P64 ? 8 : 4);
-    P->stages.push_back(z);
-    Stage y = z; y.zoff = s.Yt;
-    y.zbytes = (size_t)s.L * s.ldy * (prec == P64 ? 8 : 4);
-    P->stages.push_back(y);
+  if (head) {
+    // one grouped launch for every side's W and Y buffers
+    std::vector<ZeroJob> zj; std::vector<int> zt;
+    const size_t esz = prec == P64 ? 8 : 4;
+    for (auto& s : S) {
+      for (int y = 0; y < 2; ++y) {
+        const size_t bytes = (size_t)s.L * (y ? s.ldy : s.ldw) * esz;
+        zj.push_back(ZeroJob{(uint32_t*)WS(ws, y ? s.Yt : s.Wt), (int64_t)(bytes / 4)});
+        zt.push_back((int)((bytes / 4 + 4095) / 4096));
+      }
+    }
+    B.add(K_ZEROG, zj, zt).tag = T_ZERO;
   }
   if (head || part == rgsvd_plan_s::TAIL) {
     // the tail of an adaptive run rewrites the words with the final sizes
@@ -977,6 +984,7 @@ int enqueue(rgsvd_plan_s* P, void* ws, hipStream_t st) {
     const void* j = jb + s.joff;
     switch (s.kind) {
       case K_ZERO: launch_zero((char*)ws + s.zoff, (int64_t)s.zbytes, st); break;
+      case K_ZEROG: launch_zerog((const ZeroJob*)j, pre, s.nj, s.tiles, st); break;
       case K_COPY: hipLaunchKernelGGL(k_copy, dim3(s.tiles), dim3(64), 0, st, (const CopyJob*)j, pre, s.nj); break;
       case K_GEN: launch_gen(s.f64, (const GenJob*)j, pre, s.nj, s.tiles, st); break;
       case K_AB: launch_ab(s.prec, s.ta, s.tb, s.td, s.ct, s.js, (const AbJob*)j, pre, s.nj, s.tiles, st); break;

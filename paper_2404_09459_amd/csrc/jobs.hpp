@@ -62,6 +62,11 @@ struct CholJob {
   double shift0;
 };
 
+// Zero fill of nwords 32-bit words (one grouped launch for many buffers).
+struct ZeroJob {
+  uint32_t* p; int64_t nwords;
+};
+
 // Sum of squares of a rows x cols block (row stride ld, FP64 or FP32
 // elements): tile t of the job writes the partial of rows
 // [t*rpt, (t+1)*rpt) to part[t]; the finishing job adds the ntiles partials

@@ -23,6 +23,19 @@ __global__ void k_zero(uint32_t* __restrict__ p, int64_t nwords) {
   for (; i < nwords; i += stride) p[i] = 0u;
 }
 
+// Grouped zero fill: a tile clears 4096 consecutive words of its job's buffer.
+__global__ __launch_bounds__(256) void k_zerog(const ZeroJob* __restrict__ jobs, const int* __restrict__ pre,
+                                               int nj) {
+  const int jb = find_side(pre, nj, blockIdx.x);
+  const ZeroJob J = jobs[jb];
+  const int64_t base = (int64_t)(blockIdx.x - pre[jb]) * 4096;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int64_t i = base + k * 256 + threadIdx.x;
+    if (i < J.nwords) J.p[i] = 0u;
+  }
+}
+
 // ---------------------------------------------------------------- k_gen --
 template <typename TW, bool F64>
 __global__ __launch_bounds__(256) void k_gen(const GenJob* __restrict__ jobs,
@@ -320,6 +333,10 @@ void launch_reduce(int ti, int to, bool sym, const RedJob* j, const int* pre, in
   else if (ti == 1 && to == 1) hipLaunchKernelGGL((k_reduce<float, float, false>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
   else if (ti == 1 && to == 0) hipLaunchKernelGGL((k_reduce<float, double, false>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
   else hipLaunchKernelGGL((k_reduce<double, float, false>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
+}
+
+void launch_zerog(const ZeroJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  hipLaunchKernelGGL(k_zerog, dim3(tiles), dim3(256), 0, st, j, pre, nj);
 }
 
 void launch_zero(void* p, int64_t bytes, hipStream_t st) {

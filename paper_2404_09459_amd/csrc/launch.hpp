@@ -7,6 +7,7 @@
 namespace rg {
 
 void launch_zero(void* p, int64_t bytes, hipStream_t st);
+void launch_zerog(const ZeroJob* j, const int* pre, int nj, int tiles, hipStream_t st);
 void launch_gen(bool f64, const GenJob* j, const int* pre, int nj, int tiles, hipStream_t st);
 void launch_ab(int prec, int ta, int tb, int td, int ct, int js, const AbJob* j, const int* pre,
                int nj, int tiles, hipStream_t st);
