@@ -195,12 +195,14 @@ __global__ __launch_bounds__(256) void k_ab(const AbJob* __restrict__ jobs,
 // --------------------------------------------------------------- k_gram --
 // Partial Gram X[:, k0:k1] X[:, k0:k1]^T in fp64 MFMA.  Output blocks of
 // 64 x 64; only blocks on or above the diagonal are formed (the reduction
-// mirrors them).  Each wave: 16 rows x 64 columns.
-template <typename TX>
+// mirrors them).  Each wave: 16 rows x 64 columns (four 16 x 16 tiles).
+// No LDS: lane (g, li) reads 4 consecutive k of its A row and of the four
+// B rows straight from L2 (16 or 32 bytes per row), NB steps of 16 k ahead.
+// The 4-wide loads need k0, clen, ld1 and ld2 to be multiples of 4 (the
+// plans pad leading dimensions to 64 and chunk lengths to 32).
+template <typename TX, int NB = 4>
 __global__ __launch_bounds__(256) void k_gram(const GramJob* __restrict__ jobs,
                                               const int* __restrict__ pre, int nj) {
-  constexpr int KC = 32, KL = 8, RL = KC + 2;
-  __shared__ double Xs[128 * RL];   // rows 0..63: row block, 64..127: column block
   const int jb = find_side(pre, nj, blockIdx.x);
   const GramJob J = jobs[jb];
   int tile = blockIdx.x - pre[jb];
@@ -221,29 +223,65 @@ __global__ __launch_bounds__(256) void k_gram(const GramJob* __restrict__ jobs,
     if (c < J.r1 + J.r2) return X2 + (int64_t)(c - J.r1) * J.ld2;
     return nullptr;
   };
+  // rows past r1 + r2 read row 0 scaled by zero (loads stay unconditional)
+  const TX* pa = rowptr(rb * 64 + wave * 16 + li);
+  const double wa = pa ? 1.0 : 0.0;
+  if (!pa) pa = X1;
+  const TX* pb[4];
+  double wb[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    pb[q] = rowptr(cb * 64 + q * 16 + li);
+    wb[q] = pb[q] ? 1.0 : 0.0;
+    if (!pb[q]) pb[q] = X1;
+  }
   d4 acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
-  for (int k = kb; k < ke; k += KC) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < 128 * KC; e += 256) {
-      int rr = e / KC, kk = e - rr * KC;
-      int c = (rr < 64 ? rb * 64 + rr : cb * 64 + rr - 64);
-      const TX* p = rowptr(c);
-      int kx = k + kk;
-      Xs[rr * RL + kk] = (p && kx < ke) ? (double)p[kx] : 0.0;
+  double ra[NB][4], rbv[NB][4][4];
+  // 4 consecutive k from kx (kx % 4 == 0, kx < ke <= ld), zero at and past ke
+  auto ld4 = [&](double* o, const TX* p, int kx, double w) {
+    if constexpr (sizeof(TX) == 4) {
+      const f4 v = *(const f4*)(p + kx);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) o[e] = (kx + e < ke) ? (double)v[e] * w : 0.0;
+    } else {
+      const d2 v0 = *(const d2*)(p + kx), v1 = *(const d2*)(p + kx + 2);
+      o[0] = (kx < ke) ? v0[0] * w : 0.0;
+      o[1] = (kx + 1 < ke) ? v0[1] * w : 0.0;
+      o[2] = (kx + 2 < ke) ? v1[0] * w : 0.0;
+      o[3] = (kx + 3 < ke) ? v1[1] * w : 0.0;
     }
-    __syncthreads();
-    double a[KL];
+  };
+  const int nsteps = (ke - kb + 15) / 16;
+  auto load = [&](int buf, int st) {
+    const int kx = kb + st * 16 + g * 4;
+    if (kx < ke) {
+      ld4(ra[buf], pa, kx, wa);
 #pragma unroll
-    for (int e = 0; e < KL; ++e) a[e] = Xs[(wave * 16 + li) * RL + g * KL + e];
+      for (int q = 0; q < 4; ++q) ld4(rbv[buf][q], pb[q], kx, wb[q]);
+    } else {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      double b[KL];
+      for (int e = 0; e < 4; ++e) {
+        ra[buf][e] = 0.0;
 #pragma unroll
-      for (int e = 0; e < KL; ++e) b[e] = Xs[(64 + q * 16 + li) * RL + g * KL + e];
+        for (int q = 0; q < 4; ++q) rbv[buf][q][e] = 0.0;
+      }
+    }
+  };
 #pragma unroll
-      for (int e = 0; e < KL; ++e) acc[q] = mma64(a[e], b[e], acc[q]);
+  for (int b = 0; b < NB - 1; ++b)
+    if (b < nsteps) load(b, b);
+  for (int st0 = 0; st0 < nsteps; st0 += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int st = st0 + u;
+      if (st >= nsteps) break;
+      if (st + NB - 1 < nsteps) load((u + NB - 1) % NB, st + NB - 1);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] = mma64(ra[u][e], rbv[u][q][e], acc[q]);
     }
   }
   // lane holds D[out_row(g, ii)][li] of tile (wave, q)
