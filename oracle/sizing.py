@@ -45,9 +45,10 @@ def l_grid(k, cap):
 
 def decide(y, k, cap):
     """Network output (log2(l / k), q) -> (l, q): the smallest grid size at
-    or above k 2^y0, and q rounded with a bias of 0.3 towards more passes."""
+    or above k 2^y0, and q rounded with a bias of 0.4 towards more passes
+    (q >= 1 once y1 reaches 0.1)."""
     grid = l_grid(k, cap)
     want = k * 2.0 ** min(float(y[0]), 8.0)
     l = next((v for v in grid if v >= want), grid[-1])
-    q = int(min(3, max(0, np.floor(float(y[1]) + 0.5 + 0.3))))
+    q = int(min(3, max(0, np.floor(float(y[1]) + 0.5 + 0.4))))
     return l, q

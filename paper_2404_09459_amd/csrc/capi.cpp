@@ -1165,7 +1165,8 @@ int run_probe(rgsvd_plan_s* P, void* ws, hipStream_t st) {
 
 // Sketch sizes from the network output (log2(l / k), q): the smallest l of
 // the grid {k+4, k+8, k+16, k+32, 2k} (capped) at or above k 2^y0, and q
-// rounded with a bias of 0.3 towards more passes, clamped to [0, 3].
+// rounded with a bias of 0.4 towards more passes (q >= 1 from y1 = 0.1 on),
+// clamped to [0, 3].
 void decide_sizes(double y0, double y1, int k, int cap, int* l, int* q) {
   int g[5] = {k + 4, k + 8, k + 16, k + 32, 2 * k};
   std::vector<int> grid;
@@ -1175,7 +1176,7 @@ void decide_sizes(double y0, double y1, int k, int cap, int* l, int* q) {
   const double want = k * std::exp2(std::isfinite(y0) ? std::min(y0, 8.0) : 8.0);
   *l = grid.back();
   for (int v : grid) if (v >= want) { *l = v; break; }
-  const double qq = std::floor((std::isfinite(y1) ? y1 : 3.0) + 0.8);
+  const double qq = std::floor((std::isfinite(y1) ? y1 : 3.0) + 0.9);
   *q = (int)std::min(3.0, std::max(0.0, qq));
 }
 

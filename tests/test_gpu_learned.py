@@ -112,13 +112,15 @@ def test_learned_run_uses_network_choice(dev):
 
 def test_trained_network_gain(dev):
     """Train on GPU-labelled pairs, evaluate on held-out pairs: the learned
-    sizes must keep the angular tolerance on (nearly) every held-out pair at a
-    lower cost (passes over G) than the safe fixed setting (2k, q = 3), and
-    pass more often than the cheap fixed default (k + 10, q = 2) or at lower
-    cost."""
+    sizes must keep the angular tolerance on at least 90% of 64 held-out
+    pairs at a lower cost (passes over G) than the safe fixed setting
+    (2k, q = 3), and pass more often than the cheap fixed default
+    (k + 10, q = 2) or at lower cost.  The label margin, the training-set
+    size and the rounding of q were settled on pairs of another seed; these
+    pairs are fresh draws."""
     from paper_2404_09459_amd import sizing as S
-    specs = S.pair_specs(112, seed=21)
-    train_specs, test_specs = specs[:80], specs[80:]
+    specs = S.pair_specs(224, seed=21)
+    train_specs, test_specs = specs[:160], specs[160:]
     X, T, kept = [], [], []
     for s in train_specs:
         G1, G2 = S.make_pair(s)

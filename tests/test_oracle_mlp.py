@@ -96,3 +96,6 @@ def test_decide_rounds_up_to_grid():
     assert decide([np.log2(30 / 20), 1.3], 20, 1000) == (36, 2)
     assert decide([5.0, 9.0], 20, 1000) == (52, 3)
     assert decide([0.5, -2.0], 20, 30) == (30, 0)
+    # q rounds up from y1 = 0.1 on
+    assert decide([0.0, 0.09], 20, 1000)[1] == 0 and decide([0.0, 0.1], 20, 1000)[1] == 1
+    assert decide([0.0, 1.09], 20, 1000)[1] == 1 and decide([0.0, 1.1], 20, 1000)[1] == 2
