@@ -401,11 +401,11 @@ int build(rgsvd_plan_s* P, void* ws) {
         GramJob g{};
         g.X1 = WS(ws, s.Yt); g.X2 = nullptr; g.out = (double*)WS(ws, s.gpart);
         g.ld1 = s.ldy; g.ld2 = 0; g.r1 = 16; g.r2 = 0; g.k0 = 0; g.k1 = s.m; g.npad = 64; g.clen = s.gcl_m;
-        gj.push_back(g); gtl.push_back(s.gch_m);
+        gj.push_back(g); gtl.push_back(gram_strips(16) * s.gch_m);
         RedJob r{};
         r.in = WS(ws, s.gpart); r.out = WS(ws, s.gram); r.sq = nullptr;
         r.stride = 64 * 64; r.count = r.stride;
-        r.nparts = s.gch_m; r.rows = 64; r.cols = 64; r.ldo = 64; r.ldi = 64;
+        r.nparts = s.gch_m; r.rows = 64; r.cols = 64; r.ldo = 64; r.ldi = 64; r.nz = 16;
         rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
         fj.push_back(FeatJob{(const double*)WS(ws, s.gram), (float*)WS(ws, P->off_feat) + 16 * i, 64, 0});
         ftl.push_back(1);
@@ -506,11 +506,12 @@ int build(rgsvd_plan_s* P, void* ws) {
         g.X1 = X; g.X2 = nullptr; g.out = (double*)WS(ws, s.gpart);
         g.ld1 = ld; g.ld2 = 0; g.r1 = s.L; g.r2 = 0; g.k0 = 0; g.k1 = len;
         g.npad = P->npadG; g.clen = gcl;
-        gj.push_back(g); gtl.push_back(nblk * gch);
+        gj.push_back(g); gtl.push_back(gram_strips(s.L) * gch);
         RedJob r{};
         r.in = WS(ws, s.gpart); r.out = WS(ws, s.gram); r.sq = nullptr;
         r.stride = (int64_t)P->npadG * P->npadG; r.count = r.stride;
         r.nparts = gch; r.rows = P->npadG; r.cols = P->npadG; r.ldo = P->npadG; r.ldi = P->npadG;
+        r.nz = s.L;
         rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
         CholJob c{};
         c.gram = (const double*)WS(ws, s.gram); c.sinv = (double*)WS(ws, s.sinv); c.r = nullptr;
@@ -647,11 +648,12 @@ int build(rgsvd_plan_s* P, void* ws) {
         g.X1 = WS(ws, s->Yt); g.X2 = nullptr; g.out = (double*)WS(ws, s->gpart);
         g.ld1 = s->ldy; g.ld2 = 0; g.r1 = N; g.r2 = 0; g.k0 = 0; g.k1 = s->m;
         g.npad = P->npadG; g.clen = s->gcl_m;
-        gj.push_back(g); gtl.push_back(nblk * s->gch_m);
+        gj.push_back(g); gtl.push_back(gram_strips(N) * s->gch_m);
         RedJob r{};
         r.in = WS(ws, s->gpart); r.out = WS(ws, s->gram); r.sq = nullptr;
         r.stride = (int64_t)P->npadG * P->npadG; r.count = r.stride;
         r.nparts = s->gch_m; r.rows = P->npadG; r.cols = P->npadG; r.ldo = P->npadG; r.ldi = P->npadG;
+        r.nz = N;
         rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
         CholJob c{};
         c.gram = (const double*)WS(ws, s->gram); c.sinv = (double*)WS(ws, s->sinv); c.r = nullptr;
@@ -732,11 +734,12 @@ int build(rgsvd_plan_s* P, void* ws) {
       g.X1 = WS(ws, s1.Wt); g.X2 = WS(ws, s2.Wt); g.out = (double*)WS(ws, pr.mpart);
       g.ld1 = s1.ldw; g.ld2 = s2.ldw; g.r1 = pr.l1; g.r2 = pr.l2; g.k0 = 0; g.k1 = (int)pr.n;
       g.npad = pr.Npad; g.clen = pr.gcl;
-      gj.push_back(g); gtl.push_back(nblk * pr.gch);
+      gj.push_back(g); gtl.push_back(gram_strips(pr.l1 + pr.l2) * pr.gch);
       RedJob r{};
       r.in = WS(ws, pr.mpart); r.out = WS(ws, pr.M); r.sq = nullptr;
       r.stride = (int64_t)pr.Npad * pr.Npad; r.count = r.stride;
       r.nparts = pr.gch; r.rows = pr.Npad; r.cols = pr.Npad; r.ldo = pr.Npad; r.ldi = pr.Npad;
+      r.nz = pr.l1 + pr.l2;
       rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
     }
     Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = wt; gs.tag = T_MGRAM;

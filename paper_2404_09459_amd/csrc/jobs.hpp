@@ -26,20 +26,33 @@ struct AbJob {
 // Partial Grams of a row-stacked matrix X = [X1 (r1 rows); X2 (r2 rows)]
 // over column chunks [k0 + c*clen, k0 + (c+1)*clen) of [k0, k1):
 //   out[c] = X[:, chunk c] X[:, chunk c]^T   (npad x npad, double)
-// Only 64 x 64 blocks on or above the diagonal are written.
+// Only the 16 x 16 groups on or above the diagonal with both indices below
+// r1 + r2 are written; one tile per strip (gram_strips per chunk).
 struct GramJob {
   const void* X1; const void* X2; double* out;
   int64_t ld1, ld2;
   int32_t r1, r2, k0, k1, npad, clen;
 };
 
+// Strips of a Gram over R rows: row group rg (16 rows) meets the 64-column
+// blocks from rg / 4 to the last one that starts below R.
+__host__ __device__ inline int gram_strips(int R) {
+  const int ngr = (R + 15) / 16, ncb = (R + 63) / 64;
+  int s = 0;
+  for (int rg = 0; rg < ngr; ++rg) s += ncb - rg / 4;
+  return s;
+}
+
 // out[r][c] = sum_{p < nparts} in[p*stride + r*ldi + c] in fixed order,
-// converted to the output type.
+// converted to the output type.  Symmetric (Gram) reductions read the upper
+// 16 x 16 groups for the lower ones and write zero at and past row or
+// column nz.
 struct RedJob {
   const void* in; void* out; double* sq;
   int64_t stride; int64_t count;
   int32_t nparts, rows, cols, ldo;   // output viewed as rows x cols with ld ldo
   int64_t ldi;                       // input row stride (cols <= ldi)
+  int32_t nz, pad;                   // symmetric reductions: rows / columns kept
 };
 
 // Omega^T generation: Wt[c][r] = Omega[r][col0 + c] for c < ncols, r < n;

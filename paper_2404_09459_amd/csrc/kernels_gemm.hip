@@ -193,29 +193,21 @@ __global__ __launch_bounds__(256) void k_ab(const AbJob* __restrict__ jobs,
 }
 
 // --------------------------------------------------------------- k_gram --
-// Partial Gram X[:, k0:k1] X[:, k0:k1]^T in fp64 MFMA.  Output blocks of
-// 64 x 64; only blocks on or above the diagonal are formed (the reduction
-// mirrors them).  Each wave: 16 rows x 64 columns (four 16 x 16 tiles).
-// No LDS: lane (g, li) reads 4 consecutive k of its A row and of the four
-// B rows straight from L2 (16 or 32 bytes per row), NB steps of 16 k ahead.
+// Partial Gram X[:, k0:k1] X[:, k0:k1]^T in fp64 MFMA over the R = r1 + r2
+// rows of X (X1's rows, then X2's).  One single-wave workgroup per strip: a
+// group of 16 rows against the NQ (1..4) groups of 16 columns of one 64-column
+// block that lie on or above the diagonal and start below R.  Only those
+// 16 x 16 groups are written; the reduction mirrors them into the lower
+// triangle and zeroes rows and columns at and past R.
+// No LDS: lane (g, li) reads 4 consecutive k of its A row and of its NQ B
+// rows straight from L2 (16 or 32 bytes per row), NB steps of 16 k ahead.
 // The 4-wide loads need k0, clen, ld1 and ld2 to be multiples of 4 (the
 // plans pad leading dimensions to 64 and chunk lengths to 32).
-template <typename TX, int NB = 4>
-__global__ __launch_bounds__(256) void k_gram(const GramJob* __restrict__ jobs,
-                                              const int* __restrict__ pre, int nj) {
-  const int jb = find_side(pre, nj, blockIdx.x);
-  const GramJob J = jobs[jb];
-  int tile = blockIdx.x - pre[jb];
-  const int nb = J.npad / 64;
-  const int nblk = nb * (nb + 1) / 2;
-  const int chunk = tile / nblk;
-  int bt = tile - chunk * nblk;
+template <typename TX, int NB, int NQ>
+__device__ __forceinline__ void gram_strip(const GramJob& J, int chunk, int rg, int cb, int q0) {
+  const int ln = threadIdx.x & 63, g = ln >> 4, li = ln & 15;
   const int kb = J.k0 + chunk * J.clen;
   const int ke = min(J.k1, kb + J.clen);
-  int rb = 0;
-  while (bt >= nb - rb) { bt -= nb - rb; ++rb; }
-  const int cb = rb + bt;
-  const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63, g = ln >> 4, li = ln & 15;
   const TX* X1 = (const TX*)J.X1;
   const TX* X2 = (const TX*)J.X2;
   auto rowptr = [&](int c) -> const TX* {
@@ -223,22 +215,22 @@ __global__ __launch_bounds__(256) void k_gram(const GramJob* __restrict__ jobs,
     if (c < J.r1 + J.r2) return X2 + (int64_t)(c - J.r1) * J.ld2;
     return nullptr;
   };
-  // rows past r1 + r2 read row 0 scaled by zero (loads stay unconditional)
-  const TX* pa = rowptr(rb * 64 + wave * 16 + li);
+  // rows past R read row 0 of X1 scaled by zero (loads stay unconditional)
+  const TX* pa = rowptr(rg * 16 + li);
   const double wa = pa ? 1.0 : 0.0;
   if (!pa) pa = X1;
-  const TX* pb[4];
-  double wb[4];
+  const TX* pb[NQ];
+  double wb[NQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    pb[q] = rowptr(cb * 64 + q * 16 + li);
+  for (int q = 0; q < NQ; ++q) {
+    pb[q] = rowptr(cb * 64 + (q0 + q) * 16 + li);
     wb[q] = pb[q] ? 1.0 : 0.0;
     if (!pb[q]) pb[q] = X1;
   }
-  d4 acc[4];
+  d4 acc[NQ];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) acc[q] = d4{0, 0, 0, 0};
-  double ra[NB][4], rbv[NB][4][4];
+  for (int q = 0; q < NQ; ++q) acc[q] = d4{0, 0, 0, 0};
+  double ra[NB][4], rbv[NB][NQ][4];
   // 4 consecutive k from kx (kx % 4 == 0, kx < ke <= ld), zero at and past ke
   auto ld4 = [&](double* o, const TX* p, int kx, double w) {
     if constexpr (sizeof(TX) == 4) {
@@ -259,13 +251,13 @@ __global__ __launch_bounds__(256) void k_gram(const GramJob* __restrict__ jobs,
     if (kx < ke) {
       ld4(ra[buf], pa, kx, wa);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) ld4(rbv[buf][q], pb[q], kx, wb[q]);
+      for (int q = 0; q < NQ; ++q) ld4(rbv[buf][q], pb[q], kx, wb[q]);
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         ra[buf][e] = 0.0;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) rbv[buf][q][e] = 0.0;
+        for (int q = 0; q < NQ; ++q) rbv[buf][q][e] = 0.0;
       }
     }
   };
@@ -281,24 +273,49 @@ __global__ __launch_bounds__(256) void k_gram(const GramJob* __restrict__ jobs,
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] = mma64(ra[u][e], rbv[u][q][e], acc[q]);
+        for (int q = 0; q < NQ; ++q) acc[q] = mma64(ra[u][e], rbv[u][q][e], acc[q]);
     }
   }
-  // lane holds D[out_row(g, ii)][li] of tile (wave, q)
+  // lane holds D[out_row(g, ii)][li] of column group q0 + q
   double* out = J.out + (int64_t)chunk * J.npad * J.npad;
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
+  for (int q = 0; q < NQ; ++q)
 #pragma unroll
     for (int ii = 0; ii < 4; ++ii) {
-      int r = rb * 64 + wave * 16 + out_row<P64>(g, ii);
-      int c = cb * 64 + q * 16 + li;
+      const int r = rg * 16 + out_row<P64>(g, ii);
+      const int c = cb * 64 + (q0 + q) * 16 + li;
       out[(int64_t)r * J.npad + c] = acc[q][ii];
     }
 }
 
+template <typename TX, int NB = 4>
+__global__ __launch_bounds__(64) void k_gram(const GramJob* __restrict__ jobs,
+                                             const int* __restrict__ pre, int nj) {
+  const int jb = find_side(pre, nj, blockIdx.x);
+  const GramJob J = jobs[jb];
+  const int R = J.r1 + J.r2;
+  const int tile = blockIdx.x - pre[jb];
+  const int chunk = tile / gram_strips(R);
+  int s = tile - chunk * gram_strips(R);
+  // strip s -> (row group rg, column block cb), in the order gram_strips counts
+  const int ncb = (R + 63) / 64;
+  int rg = 0;
+  while (s >= ncb - rg / 4) { s -= ncb - rg / 4; ++rg; }
+  const int cb = rg / 4 + s;
+  const int q0 = (cb == rg / 4) ? (rg & 3) : 0;
+  const int q1 = min(4, (R - cb * 64 + 15) / 16);
+  switch (q1 - q0) {
+    case 1: gram_strip<TX, NB, 1>(J, chunk, rg, cb, q0); break;
+    case 2: gram_strip<TX, NB, 2>(J, chunk, rg, cb, q0); break;
+    case 3: gram_strip<TX, NB, 3>(J, chunk, rg, cb, q0); break;
+    default: gram_strip<TX, NB, 4>(J, chunk, rg, cb, q0); break;
+  }
+}
+
 // ------------------------------------------------------------- k_reduce --
-// Fixed-order sum over partials.  SYM: the input holds only blocks with
-// (row block <= column block) of 64 x 64; entries below are mirrored.
+// Fixed-order sum over partials.  SYM: the input holds only the 16 x 16
+// groups with (row group <= column group) below nz (k_gram's strips); entries
+// below them are mirrored, rows and columns at and past nz are zero.
 template <typename TI, typename TO, bool SYM>
 __global__ __launch_bounds__(256) void k_reduce(const RedJob* __restrict__ jobs,
                                                 const int* __restrict__ pre, int nj) {
@@ -309,11 +326,12 @@ __global__ __launch_bounds__(256) void k_reduce(const RedJob* __restrict__ jobs,
   if (i < cnt) {
     int r = (int)(i / J.cols), c = (int)(i - (int64_t)r * J.cols);
     int64_t src;
-    if (SYM && (r >> 6) > (c >> 6)) src = (int64_t)c * J.ldi + r;
+    if (SYM && (r >> 4) > (c >> 4)) src = (int64_t)c * J.ldi + r;
     else src = (int64_t)r * J.ldi + c;
     const TI* in = (const TI*)J.in;
     double s = 0.0;
-    for (int p = 0; p < J.nparts; ++p) s += (double)in[p * J.stride + src];
+    if (!SYM || (r < J.nz && c < J.nz))
+      for (int p = 0; p < J.nparts; ++p) s += (double)in[p * J.stride + src];
     ((TO*)J.out)[(int64_t)r * J.ldo + c] = (TO)s;
   }
 }
@@ -360,8 +378,8 @@ void launch_gen(bool f64, const GenJob* j, const int* pre, int nj, int tiles, hi
 }
 
 void launch_gram(int tx, const GramJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
-  if (tx == 0) hipLaunchKernelGGL((k_gram<double>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
-  else hipLaunchKernelGGL((k_gram<float>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
+  if (tx == 0) hipLaunchKernelGGL((k_gram<double>), dim3(tiles), dim3(64), 0, st, j, pre, nj);
+  else hipLaunchKernelGGL((k_gram<float>), dim3(tiles), dim3(64), 0, st, j, pre, nj);
 }
 
 void launch_reduce(int ti, int to, bool sym, const RedJob* j, const int* pre, int nj, int tiles,
