@@ -52,6 +52,15 @@ struct Side {
   int32_t lcur;        // active width for adaptive runs (<= l)
 };
 
+// XCD-aware tile order.  Workgroups are handed to the 8 XCDs round-robin
+// (block b to XCD b % 8), each XCD with its own L2.  Launching
+// xcd_grid(tiles) blocks and running logical tile xcd_tile(b) gives every
+// XCD one contiguous eighth of the tiles, so neighbouring tiles that read
+// the same operand slice share an L2.  Blocks with xcd_tile(b) >= tiles exit.
+constexpr int NXCD = 8;
+__host__ __device__ inline int xcd_grid(int tiles) { return (tiles + NXCD - 1) / NXCD * NXCD; }
+__device__ inline int xcd_tile(int b, int grid) { return (b % NXCD) * (grid / NXCD) + b / NXCD; }
+
 // find the side that owns flat tile index `tile` in a prefix table pre[0..ns]
 __device__ inline int find_side(const int* __restrict__ pre, int ns, int tile) {
   int lo = 0, hi = ns - 1;

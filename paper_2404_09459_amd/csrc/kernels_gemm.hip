@@ -288,13 +288,17 @@ __device__ __forceinline__ void gram_strip(const GramJob& J, int chunk, int rg, 
     }
 }
 
+// Strips run in XCD order, so the strips of one chunk (which share its rows)
+// run on one XCD and share its L2.
 template <typename TX, int NB = 4>
 __global__ __launch_bounds__(64) void k_gram(const GramJob* __restrict__ jobs,
-                                             const int* __restrict__ pre, int nj) {
-  const int jb = find_side(pre, nj, blockIdx.x);
+                                             const int* __restrict__ pre, int nj, int ntiles) {
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= ntiles) return;
+  const int jb = find_side(pre, nj, t);
   const GramJob J = jobs[jb];
   const int R = J.r1 + J.r2;
-  const int tile = blockIdx.x - pre[jb];
+  const int tile = t - pre[jb];
   const int chunk = tile / gram_strips(R);
   int s = tile - chunk * gram_strips(R);
   // strip s -> (row group rg, column block cb), in the order gram_strips counts
@@ -378,8 +382,9 @@ void launch_gen(bool f64, const GenJob* j, const int* pre, int nj, int tiles, hi
 }
 
 void launch_gram(int tx, const GramJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
-  if (tx == 0) hipLaunchKernelGGL((k_gram<double>), dim3(tiles), dim3(64), 0, st, j, pre, nj);
-  else hipLaunchKernelGGL((k_gram<float>), dim3(tiles), dim3(64), 0, st, j, pre, nj);
+  const dim3 grid(xcd_grid(tiles));
+  if (tx == 0) hipLaunchKernelGGL((k_gram<double>), grid, dim3(64), 0, st, j, pre, nj, tiles);
+  else hipLaunchKernelGGL((k_gram<float>), grid, dim3(64), 0, st, j, pre, nj, tiles);
 }
 
 void launch_reduce(int ti, int to, bool sym, const RedJob* j, const int* pre, int nj, int tiles,

@@ -335,17 +335,21 @@ __global__ __launch_bounds__(256) void k_gw4(const NnJob* __restrict__ jobs, con
 // columns of this row chunk in the compute type (lda, zero beyond m), B = the
 // row chunk of G (ldb, K rows; rows past K read as zero through the buffer
 // resource).  Wave tile: 16*JS columns of G (lane li owns JS consecutive
-// columns, one per MFMA sub-tile), all CT row tiles of D.
+// columns, one per MFMA sub-tile), all CT row tiles of D.  Tiles run in XCD
+// order: the column tiles of one row chunk read the same Q^T slice, which
+// then stays in one XCD's L2.
 template <int P, typename TG, int CT, int JS, int NB = 3>
 __global__ __launch_bounds__(64) void k_gtq(const AbJob* __restrict__ jobs, const int* __restrict__ pre,
-                                            int nj) {
+                                            int nj, int ntiles) {
   using cT = typename St<P>::cT;
   using acc_t = typename St<P>::acc;
   using bT = typename std::conditional<P == P64, double, float>::type;
   constexpr int KL = St<P>::KL, KS = 4 * KL;
-  const int jb = find_side(pre, nj, blockIdx.x);
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= ntiles) return;
+  const int jb = find_side(pre, nj, t);
   const AbJob J = jobs[jb];
-  const int tile = blockIdx.x - pre[jb];
+  const int tile = t - pre[jb];
   const int ln = threadIdx.x, g = ln >> 4, li = ln & 15;
   const int col0 = tile * 16 * JS + JS * li;
   const int ctn = (J.rows + 15) >> 4;
@@ -502,12 +506,13 @@ void launch_gw(int prec, int gdt, int rt, int ct, const NnJob* j, const int* pre
 
 template <int P, typename TG, int JS>
 static void gtq_ct(int ct, const AbJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  const dim3 grid(xcd_grid(tiles));
   switch (ct) {
-    case 1: hipLaunchKernelGGL((k_gtq<P, TG, 1, JS>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
-    case 2: hipLaunchKernelGGL((k_gtq<P, TG, 2, JS>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
-    case 4: hipLaunchKernelGGL((k_gtq<P, TG, 4, JS>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
-    case 8: hipLaunchKernelGGL((k_gtq<P, TG, 8, JS>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
-    default: hipLaunchKernelGGL((k_gtq<P, TG, 16, JS>), dim3(tiles), dim3(64), 0, st, j, pre, nj); break;
+    case 1: hipLaunchKernelGGL((k_gtq<P, TG, 1, JS>), grid, dim3(64), 0, st, j, pre, nj, tiles); break;
+    case 2: hipLaunchKernelGGL((k_gtq<P, TG, 2, JS>), grid, dim3(64), 0, st, j, pre, nj, tiles); break;
+    case 4: hipLaunchKernelGGL((k_gtq<P, TG, 4, JS>), grid, dim3(64), 0, st, j, pre, nj, tiles); break;
+    case 8: hipLaunchKernelGGL((k_gtq<P, TG, 8, JS>), grid, dim3(64), 0, st, j, pre, nj, tiles); break;
+    default: hipLaunchKernelGGL((k_gtq<P, TG, 16, JS>), grid, dim3(64), 0, st, j, pre, nj, tiles); break;
   }
 }
 
