@@ -170,12 +170,29 @@ int layout(rgsvd_plan_s* P) {
       s.L = (int)upi(s.l, 16) + spare;
       s.ldy = (int)upi(s.m, 64); s.ldw = (int)upi(s.n, 64);
       s.seed = pr.seed; s.stream = w ? 2 : 1;
-      // G^T Q row chunks: enough single-wave tiles to fill the wave slots once
+      // G^T Q row chunks.  One pair: enough single-wave tiles to fill the
+      // wave slots once, all waves of equal length.  A batch of uneven pairs:
+      // sides shorter than a slot's share would leave the long sides' waves
+      // running alone at the end, so waves get a quarter of the share (at
+      // least 8 L rows, so that a chunk's L x n partial adds at most an
+      // eighth to the pass's traffic) and the wave slots balance them.
       int js = (prec == P64 || P->gdt == RGSVD_F64 || s.L > 128) ? 2 : 4;
       int jt = (int)((s.n + 16 * js - 1) / (16 * js));
-      int64_t rows_all = 0;
-      for (auto& q : P->pairs) rows_all += q.m + q.p;
-      int nch = (int)std::max<int64_t>(1, (int64_t)P->wave_slots * s.m / std::max<int64_t>(1, rows_all * jt));
+      int nch;
+      if (P->pairs.size() == 1) {
+        int64_t rows_all = 0;
+        for (auto& q : P->pairs) rows_all += q.m + q.p;
+        nch = (int)std::max<int64_t>(1, (int64_t)P->wave_slots * s.m / std::max<int64_t>(1, rows_all * jt));
+      } else {
+        int64_t work = 0;   // sum over sides of rows x column tiles
+        for (auto& q : P->pairs) {
+          const int qjs = (prec == P64 || P->gdt == RGSVD_F64 || (int)upi(std::max(q.l1, q.l2), 16) > 128) ? 2 : 4;
+          work += (q.m + q.p) * ((q.n + 16 * qjs - 1) / (16 * qjs));
+        }
+        const int64_t share = work / std::max(1, P->wave_slots);
+        const int64_t rows = std::max<int64_t>({share / 4, 8 * (int64_t)s.L, 256});
+        nch = (int)((s.m + rows - 1) / rows);
+      }
       nch = std::max(1, std::min(nch, (s.m + 255) / 256));
       int mch = (int)upi((s.m + nch - 1) / nch, 32);
       nch = (s.m + mch - 1) / mch;
