@@ -507,7 +507,7 @@ __device__ __forceinline__ bool jacobi_turn(double al, double be, double ga, boo
 // whether the pair turned.
 template <int G, int EM>
 __device__ __attribute__((always_inline)) inline bool
-pair_step(double* Lp, double* Lq, int j, int nr, bool live, double tol, double thr) {
+pair_step(double* Lp, double* Lq, int j, int nr, bool live, double tol, double thr, double& rel2) {
   double x[EM], y[EM];
   double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
@@ -527,6 +527,7 @@ pair_step(double* Lp, double* Lq, int j, int nr, bool live, double tol, double t
   double c, s;
   const bool turn = jacobi_turn(al, be, ga, live, tol, thr, c, s);
   if (turn) {
+    rel2 = fmax(rel2, ga * ga / (al * be));
 #pragma unroll
     for (int e = 0; e < EM; ++e) {
       const int r = j + G * e;
@@ -583,7 +584,7 @@ __device__ inline void tournament(int pi, int round, int m1, int& u, int& v) {
 template <int G, int EM>
 __device__ __attribute__((always_inline)) inline void
 jacobi_round(double* L, int ldl, int nr, int nc, int round, double thr, const double* nrm2,
-             double tol, int* rotated) {
+             double tol, int* rotated, double& rel2) {
   constexpr int SLOTS = 1024 / G;
   const int tid = threadIdx.x, grp = tid / G, j = tid % G;
   const int nc2 = nc + (nc & 1), npairs = nc2 / 2, m1 = nc2 - 1;
@@ -597,7 +598,7 @@ jacobi_round(double* L, int ldl, int nr, int nc, int round, double thr, const do
       if (u < nc && v < nc && !(thr >= 0.0 && nrm2[u] < thr && nrm2[v] < thr)) { p = u; q = v; }
     }
     const bool live = p >= 0;
-    any |= pair_step<G, EM>(L + (live ? p : 0) * ldl, L + (live ? q : 0) * ldl, j, nr, live, tol, thr);
+    any |= pair_step<G, EM>(L + (live ? p : 0) * ldl, L + (live ? q : 0) * ldl, j, nr, live, tol, thr, rel2);
   }
   if (any) *rotated = 1;
 }
@@ -616,7 +617,7 @@ jacobi_sweeps(double* W, int ldw, int nr, int nc, double tol, int maxsweep, int 
       s = wave_sum(s);
       if (ln == 0) nrm2[c] = s;
     }
-    if (tid == 0) scratch[0] = 0;
+    if (tid == 0) { scratch[0] = 0; scratch[1] = 0; }
     __syncthreads();
     double thr = -1.0;
     if (topk > 0 && topk < nc) {
@@ -629,13 +630,21 @@ jacobi_sweeps(double* W, int ldw, int nr, int nc, double tol, int maxsweep, int 
       __syncthreads();
       thr = 0.25 * *kth_slot;
     }
+    double rel2 = 0.0;   // largest gamma^2 / (alpha beta) this thread turned
     for (int round = 0; round < nc2 - 1; ++round) {
-      jacobi_round<G, EM>(W, ldw, nr, nc, round, thr, nrm2, tol, scratch);
+      jacobi_round<G, EM>(W, ldw, nr, nc, round, thr, nrm2, tol, scratch, rel2);
       __syncthreads();
     }
-    const int any = scratch[0];
+    // Jacobi converges quadratically: a sweep whose turns all had
+    // |gamma| < sqrt(tol) sqrt(alpha beta) leaves the next sweep only turns
+    // below tol, so it ends the sweeps without that checking sweep
+    for (int o = 32; o > 0; o >>= 1) rel2 = fmax(rel2, __shfl_xor(rel2, o, 64));
+    if (ln == 0 && rel2 > 0.0) atomicMax(scratch + 1, __float_as_int((float)fmin(rel2, 1.0)));
     __syncthreads();
-    if (!any) return sweep + 1;
+    const int any = scratch[0];
+    const float rmax = __int_as_float(scratch[1]);
+    __syncthreads();
+    if (!any || rmax < (float)tol) return sweep + 1;
   }
   return maxsweep + 1;
 }
