@@ -544,7 +544,7 @@ pair_step(double* Lp, double* Lq, int j, int nr, bool live, double tol, double t
 // hold zeros (they stay zero under rotations): no bounds tests.
 template <int G, int EM>
 __device__ __attribute__((always_inline)) inline bool
-pair_step_padded(double* Lp, double* Lq, int j, bool live, double tol, double thr) {
+pair_step_padded(double* Lp, double* Lq, int j, bool live, double tol, double thr, double& rel2) {
   double x[EM], y[EM];
   double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
@@ -561,6 +561,7 @@ pair_step_padded(double* Lp, double* Lq, int j, bool live, double tol, double th
   double c, s;
   const bool turn = jacobi_turn(al, be, ga, live, tol, thr, c, s);
   if (turn) {
+    rel2 = fmax(rel2, ga * ga / (al * be));
 #pragma unroll
     for (int e = 0; e < EM; ++e) {
       Lp[j + G * e] = c * x[e] - s * y[e];
@@ -838,13 +839,21 @@ jacobi_any(double* A, int lda, int nr, int nc, double tol, int maxsweep, int top
 __device__ inline void bj_start(BJState* S, int nc, int nr, int topk) {
   S->nc = nc; S->nr = nr; S->topk = topk; S->done = 0;
   S->sweeps = 0; S->rot[0] = 1; S->rot[1] = 1; S->thr = -1.0;
+  S->rel[0] = 0; S->rel[1] = 0;
+}
+
+// Whether the sweep of parity `par` ended the Jacobi: no turns, or only
+// turns below sqrt(tol) relative, which leave the next sweep none above tol
+// (quadratic convergence).
+__device__ inline bool bj_converged(const BJState* S, int par, double tol) {
+  return S->rot[par] == 0 || __longlong_as_double((long long)S->rel[par]) < tol;
 }
 
 // Sweeps already run by the block Jacobi, and whether single-workgroup
 // sweeps must continue (the last launched sweep still rotated).
-__device__ inline int bj_sweeps(const BJState* S, bool& more) {
+__device__ inline int bj_sweeps(const BJState* S, double tol, bool& more) {
   const int nsw = S->sweeps;
-  more = !(S->done || nsw < 1 || S->rot[(nsw - 1) & 1] == 0);
+  more = !(S->done || nsw < 1 || bj_converged(S, (nsw - 1) & 1, tol));
   return nsw;
 }
 
@@ -887,7 +896,7 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
     } else {
       rank = S->rank;
       trM = S->trM;
-      base = bj_sweeps(S, more);
+      base = bj_sweeps(S, J.tol, more);
     }
     const int tt = t < rank ? t : rank;
     sw1 = base + (more ? jacobi_any(F, N, N, rank, J.tol, J.maxsweep - base, tt, sh, lds, cap) : 0);
@@ -936,7 +945,7 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
     if (stage == 3) {
       sw1 = S->sw1;
       rh = S->nc;
-      base = bj_sweeps(S, more);
+      base = bj_sweeps(S, J.tol, more);
     }
     sw2 = base + (more ? jacobi_any(FH, t, t, rh, J.tol, J.maxsweep - base, 0, sh, lds, cap) : 0);
   }
@@ -1045,7 +1054,7 @@ __global__ __launch_bounds__(1024) void k_bjinit(const BJJob* __restrict__ jobs,
   BJState* S = J.st;
   const int tid = threadIdx.x, wave = tid >> 6, ln = tid & 63;
   if (S->done) return;
-  if (sweep > 0 && S->rot[(sweep - 1) & 1] == 0) {
+  if (sweep > 0 && bj_converged(S, (sweep - 1) & 1, J.tol)) {
     if (tid == 0) { S->done = 1; S->sweeps = sweep; }
     return;
   }
@@ -1075,7 +1084,7 @@ __global__ __launch_bounds__(1024) void k_bjinit(const BJJob* __restrict__ jobs,
     __syncthreads();
     thr = 0.25 * kth;
   }
-  if (tid == 0) { S->rot[sweep & 1] = 0; S->sweeps = sweep + 1; S->thr = thr; }
+  if (tid == 0) { S->rot[sweep & 1] = 0; S->rel[sweep & 1] = 0; S->sweeps = sweep + 1; S->thr = thr; }
 }
 
 template <int B, int G, int EM>
@@ -1119,6 +1128,7 @@ bj_visit(const BJJob& J, BJState* S, int w, int sweep, int round, double* lds, d
     return valid(a) && valid(b) && !(thr >= 0.0 && n0[a] < thr && n0[b] < thr);
   };
   bool any = false;
+  double rel2 = 0.0;
   if (round == 0) {
     // pairs inside each block: slots [0, B/2) in block u, [B/2, B) in block v
     const int side = g / (B / 2), pi = g % (B / 2);
@@ -1126,15 +1136,18 @@ bj_visit(const BJJob& J, BJState* S, int w, int sweep, int round, double* lds, d
       int u, v;
       tournament(pi, s2, B - 1, u, v);
       const int a = side * B + u, b = side * B + v;
-      any |= pair_step_padded<G, EM>(lds + a * LD, lds + b * LD, j, live(a, b), J.tol, thr);
+      any |= pair_step_padded<G, EM>(lds + a * LD, lds + b * LD, j, live(a, b), J.tol, thr, rel2);
       __syncthreads();
     }
   }
   for (int s2 = 0; s2 < B; ++s2) {
     const int a = g, b = B + ((g + s2) & (B - 1));
-    any |= pair_step_padded<G, EM>(lds + a * LD, lds + b * LD, j, live(a, b), J.tol, thr);
+    any |= pair_step_padded<G, EM>(lds + a * LD, lds + b * LD, j, live(a, b), J.tol, thr, rel2);
     __syncthreads();
   }
+  for (int o = 32; o > 0; o >>= 1) rel2 = fmax(rel2, __shfl_xor(rel2, o, 64));
+  if ((tid & 63) == 0 && rel2 > 0.0)
+    atomicMax((unsigned long long*)&S->rel[sweep & 1], (unsigned long long)__double_as_longlong(rel2));
   // write back; in the last round of the sweep every column passes through
   // exactly one workgroup, which leaves its squared norm for the next sweep
   double n2 = 0.0;

@@ -36,7 +36,8 @@ struct BJState {
   int32_t rot[2];                   // rotations seen in the sweep of that parity
   double thr;                       // skip threshold of the sweep (-1: none)
   double trM;                       // trace of M (M is overwritten by its factorisation)
-  double pad2[2];
+  uint64_t rel[2];                  // largest gamma^2 / (alpha beta) turned in the sweep of
+                                    // that parity (bits of a non-negative double)
 };
 
 // One compressed pair: M = B B^T (N x N, ldm), the Gram of the stacked
