@@ -913,10 +913,11 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
     for (int c = tid; c < N; c += 1024) perm[rank_desc(keys, N, c)] = c;
     __syncthreads();
     // sigma_B: t dominant singular values of B, then the tail's Frobenius norm
-    if (tid == 0) {
-      double tr = trM, top = 0.0;
-      for (int i = 0; i < t; ++i) { double v = keys[perm[i]]; top += v * v; }
-      sh.kth = sqrt(fmax(0.0, tr - top));
+    if (tid < 64) {
+      double top = 0.0;
+      for (int i = tid; i < t; i += 64) { const double v = keys[perm[i]]; top += v * v; }
+      top = wave_sum(top);
+      if (tid == 0) sh.kth = sqrt(fmax(0.0, trM - top));
     }
     __syncthreads();
     for (int i = tid; i < N; i += 1024)
@@ -1013,6 +1014,9 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
       if (p2 > 0.0) h2 -= p2 * log(p2);
     }
     h1 = wave_sum(h1); h2 = wave_sum(h2);
+    bool bz = false;
+    for (int i = tid; i < t; i += 64) bz |= !(J.beta[i] > BETA_ZERO);
+    bz = __ballot(bz) != 0;
     if (tid == 0) {
       double lt = t > 1 ? log((double)t) : 1.0;
       J.D[0] = t > 1 ? h1 / lt : 0.0;
@@ -1023,7 +1027,7 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
         if (sw1 > J.maxsweep) fl2 |= FLAG_JACOBI_M;
         if (sw2 > J.maxsweep) fl2 |= FLAG_JACOBI_L1;
         if (!(sa > 0.0)) fl2 |= FLAG_ALPHA_ZERO;
-        for (int i = 0; i < t; ++i) if (!(J.beta[i] > BETA_ZERO)) fl2 |= FLAG_BETA_ZERO;
+        if (bz) fl2 |= FLAG_BETA_ZERO;
         if (fl2) atomicOr(J.info + 4, fl2);
       }
     }
