@@ -325,8 +325,10 @@ __device__ void chol_blocked(const CholJob& J, double* lds) {
           }
         }
         // R_kk (upper) and 1 / R_jj to LDS; then X = R_kk^{-1}, column j per
-        // lane, from R read back as broadcasts: x_j = 1 / R_jj,
-        // x_i = -(sum_{m=i+1..j} R_im x_m) / R_ii
+        // lane: x_j = 1 / R_jj, x_i = -(sum_{m=i+1..j} R_im x_m) / R_ii, with
+        // R_im and 1 / R_ii read from the lanes that hold them (lane m's d[i],
+        // lane i's myinv), not back from LDS: LDS loads inside this dependent
+        // chain made it 6.3 of the block's 9 us
         if (j < 16) {
 #pragma unroll
           for (int i = 0; i < 16; ++i)
@@ -339,8 +341,8 @@ __device__ void chol_blocked(const CholJob& J, double* lds) {
           double acc = 0.0;
 #pragma unroll
           for (int m = i + 1; m < 16; ++m)
-            if (m <= j) acc += A[(o + i) * CB_LDA + o + m] * x[m];
-          const double rinv = rdiag[o + i];
+            if (m <= j) acc += readlane_f64(d[i], m) * x[m];
+          const double rinv = readlane_f64(myinv, i);
           x[i] = (i < j) ? -acc * rinv : (i == j ? rinv : 0.0);
         }
         if (j < 16) {
