@@ -905,11 +905,14 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
     }
     const int tt = t < rank ? t : rank;
     sw1 = base + (more ? jacobi_any(F, N, N, rank, J.tol, J.maxsweep - base, tt, sh, lds, cap) : 0);
-    for (int c = tid; c < N; c += 1024) {
+    // column norms of F: one wave per column, lanes striding its rows (one
+    // thread walking a whole column serialises its loads)
+    for (int c = tid >> 6; c < N; c += 16) {
       double s = 0.0;
       if (c < rank)
-        for (int r = 0; r < N; ++r) { double v = F[(int64_t)c * N + r]; s += v * v; }
-      keys[c] = sqrt(s);
+        for (int r = tid & 63; r < N; r += 64) { const double v = F[(int64_t)c * N + r]; s += v * v; }
+      s = wave_sum(s);
+      if ((tid & 63) == 0) keys[c] = sqrt(s);
     }
     __syncthreads();
     for (int c = tid; c < N; c += 1024) perm[rank_desc(keys, N, c)] = c;
@@ -955,11 +958,12 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
     }
     sw2 = base + (more ? jacobi_any(FH, t, t, rh, J.tol, J.maxsweep - base, 0, sh, lds, cap) : 0);
   }
-  for (int c = tid; c < t; c += 1024) {
+  for (int c = tid >> 6; c < t; c += 16) {
     double s = 0.0;
     if (c < rh)
-      for (int r = 0; r < t; ++r) { double v = FH[(int64_t)c * t + r]; s += v * v; }
-    keys[c] = sqrt(s);
+      for (int r = tid & 63; r < t; r += 64) { const double v = FH[(int64_t)c * t + r]; s += v * v; }
+    s = wave_sum(s);
+    if ((tid & 63) == 0) keys[c] = sqrt(s);
   }
   __syncthreads();
   // ---- 4. L Y (rows of Rcoef), alpha, beta (sorted by alpha)
@@ -969,12 +973,15 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
     J.Rcoef[(int64_t)c * J.ldr + r] = (c < rh && nv > 0.0) ? v / nv : 0.0;    // unsorted for now
   });
   __syncthreads();
-  for (int c = tid; c < t; c += 1024) {
+  for (int c = tid >> 6; c < t; c += 16) {
     double a = 0.0, b = 0.0;
-    for (int r = 0; r < l1; ++r) { double v = J.Rcoef[(int64_t)c * J.ldr + r]; a += v * v; }
-    for (int r = l1; r < N; ++r) { double v = J.Rcoef[(int64_t)c * J.ldr + r]; b += v * v; }
-    keys[c] = sqrt(a);
-    sh.frow[c] = sqrt(b);
+    for (int r = tid & 63; r < N; r += 64) {
+      const double v = J.Rcoef[(int64_t)c * J.ldr + r];
+      if (r < l1) a += v * v; else b += v * v;
+    }
+    a = wave_sum(a);
+    b = wave_sum(b);
+    if ((tid & 63) == 0) { keys[c] = sqrt(a); sh.frow[c] = sqrt(b); }
   }
   __syncthreads();
   for (int c = tid; c < t; c += 1024) perm[rank_desc(keys, t, c)] = c;
