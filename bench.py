@@ -35,9 +35,9 @@ FP64_VEC_PEAK_TF = 78.6
 # HBM bytes per launch on the 20000/15000 x 5000 workload, from FETCH_SIZE and
 # WRITE_SIZE scaled by a copy kernel of known size (profiles/hbm_counters_*.md):
 # the sketch kernel, k_small (mean of its two launches), k_bjround
-TRAFFIC_SKETCH = 755.4e6
-TRAFFIC_SMALL = 1.41e6
-TRAFFIC_BJROUND = 0.57e6
+TRAFFIC_SKETCH = 755.5e6
+TRAFFIC_SMALL = 1.42e6
+TRAFFIC_BJROUND = 0.56e6
 
 
 def log(*a):
