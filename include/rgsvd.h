@@ -184,9 +184,11 @@ int rgsvd_profile_read(rgsvd_plan_t plan, int32_t max, float* ms, int32_t* tag, 
 /* Many independent pairs of different sizes in one sequence of grouped
  * launches (one launch per step serves every pair), captured once into a
  * HIP graph and replayed.  Shapes are fixed at plan time; fixed sizing only.
- * shapes: host array of npairs descriptors (only m, p, n, k, oversample,
- * power_iters, seed are read per pair; in_dtype, precision, mode from
- * shapes[0]). */
+ * shapes: host array of npairs descriptors (m, p, n, k, oversample, seed
+ * are read per pair).  in_dtype, precision and mode must agree across the
+ * batch (else RGSVD_EINVAL); power_iters must agree too and sizing must be
+ * RGSVD_SIZE_FIXED (else RGSVD_EUNSUPPORTED), because each grouped launch
+ * serves every pair at the same step of the subspace iteration. */
 typedef struct {
   const void* G1; const void* G2; int64_t ld1, ld2;
   rgsvd_out out;

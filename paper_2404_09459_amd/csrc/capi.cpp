@@ -59,7 +59,6 @@ struct Stage {
   int prec = 0, gdt = 0, rt = 1, ct = 1, js = 1;
   int ta = 0, tb = 0, td = 0;
   bool sym = false, f64 = false;
-  int npad_max = 0;
   size_t zoff = 0, zbytes = 0;  // K_ZERO: workspace range
   int sweep = 0, round = 0;     // K_BJINIT, K_BJROUND
 };
@@ -106,8 +105,7 @@ struct rgsvd_plan_s {
   int Lmax = 16, npadG = 64;
   std::vector<PairLay> pairs;
   std::vector<SideLay> sides;
-  size_t off_chol = 0, off_jobs = 0, jobs_cap = 0, ws = 0;
-  int nchol_slots = 0;
+  size_t off_jobs = 0, jobs_cap = 0, ws = 0;
   // adaptive sizing: which part build() emits, and the block size
   enum Part { FIXED, A_INIT, A_BLOCK, TAIL, PROBE } part = FIXED;
   bool adaptive = false, learned = false;
@@ -258,9 +256,6 @@ int layout(rgsvd_plan_s* P) {
     pr.alpha = take(t * 8 * 5 + 16);   // alpha, beta, theta, P1, P2, D when not given
   }
   P->off_feat = take((RGSVD_MLP_IN + RGSVD_MLP_OUT + 2 * 64 + 2) * sizeof(float));
-  P->nchol_slots = 0;
-  if (P->npadG > 128) P->nchol_slots = nsides;
-  P->off_chol = take((size_t)std::max(1, P->nchol_slots) * (CHOL_MAX * CHOL_MAX + 2 * CHOL_MAX) * 8);
   // job area: generous bound
   size_t per_side = 64 * 1024 + (size_t)(P->sides.empty() ? 0 : P->sides[0].nchunk_max) * 256;
   P->jobs_cap = up(per_side * nsides + 256 * 1024, ALIGN);
@@ -531,7 +526,7 @@ int build(rgsvd_plan_s* P, void* ws) {
         r.nz = s.L;
         rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
         CholJob c{};
-        c.gram = (const double*)WS(ws, s.gram); c.sinv = (double*)WS(ws, s.sinv); c.r = nullptr;
+        c.gram = (const double*)WS(ws, s.gram); c.sinv = (double*)WS(ws, s.sinv);
         c.info = info_of(s.pair); c.N = s.l; c.npad = P->npadG; c.flagbit = ymat ? 0 : 1;
         cj.push_back(c); ctl.push_back(1);
         AbJob a{};
@@ -545,7 +540,7 @@ int build(rgsvd_plan_s* P, void* ws) {
       }
       Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = wt; gs.tag = T_GRAM;
       Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.ta = 0; r.td = 0; r.tag = T_RED;
-      Stage& c = B.add(K_CHOL, cj, ctl); c.npad_max = P->npadG; c.tag = T_CHOL;
+      Stage& c = B.add(K_CHOL, cj, ctl); c.tag = T_CHOL;
       Stage& a = B.add(K_AB, aj, atl);
       a.prec = sxp; a.ta = 0; a.tb = wt; a.td = wt; a.ct = ctL; a.tag = T_SX;
       a.js = (sxp == P64) ? 2 : 1;
@@ -631,6 +626,17 @@ int build(rgsvd_plan_s* P, void* ws) {
     for (auto& s : S) if (s.active) A.push_back(&s);
     const size_t wsz = 8;
     {
+      // the generator writes the block's bcur rows of Omega^T; the product
+      // below reads them rounded up to 16, so the rows past bcur are cleared
+      std::vector<ZeroJob> zj; std::vector<int> zt;
+      for (auto* s : A) {
+        const size_t bytes = (size_t)upi(s->bcur, 16) * s->ldw * wsz;
+        zj.push_back(ZeroJob{(uint32_t*)WS(ws, s->Ot), (int64_t)(bytes / 4)});
+        zt.push_back((int)((bytes / 4 + 4095) / 4096));
+      }
+      B.add(K_ZEROG, zj, zt).tag = T_ZERO;
+    }
+    {
       std::vector<GenJob> j; std::vector<int> tl;
       for (auto* s : A) {
         GenJob g{};
@@ -673,7 +679,7 @@ int build(rgsvd_plan_s* P, void* ws) {
         r.nz = N;
         rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
         CholJob c{};
-        c.gram = (const double*)WS(ws, s->gram); c.sinv = (double*)WS(ws, s->sinv); c.r = nullptr;
+        c.gram = (const double*)WS(ws, s->gram); c.sinv = (double*)WS(ws, s->sinv);
         c.info = info_of(s->pair); c.N = N; c.npad = P->npadG; c.flagbit = 0;
         // rows of the block that lie (numerically) in the span of Q and of
         // the block's earlier rows become zero rows of the basis
@@ -689,7 +695,7 @@ int build(rgsvd_plan_s* P, void* ws) {
       }
       Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = 0; gs.tag = T_GRAM;
       Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.ta = 0; r.td = 0; r.tag = T_RED;
-      Stage& c = B.add(K_CHOL, cj, ctl); c.npad_max = P->npadG; c.tag = T_CHOL;
+      Stage& c = B.add(K_CHOL, cj, ctl); c.tag = T_CHOL;
       Stage& a = B.add(K_AB, aj, atl);
       a.prec = P64; a.ta = 0; a.tb = 0; a.td = 0; a.ct = ctL; a.js = 2; a.tag = T_SX;
     }
@@ -890,7 +896,9 @@ int build(rgsvd_plan_s* P, void* ws) {
         a.A = WS(ws, w ? pr.X2t : pr.X1t); a.lda = w ? pr.l2 : pr.l1;
         a.B = WS(ws, s.Yt); a.ldb = s.ldy;
         a.D = dst; a.ldd = w ? pr.out.ldv : pr.out.ldu;
-        a.rows = pr.t; a.K = s.l; a.J = s.m; a.accumulate = 0;
+        // the widths the run used (adaptive and learned runs end below the
+        // side's capacity s.l; X1t, X2t have leading dimension l1, l2)
+        a.rows = pr.t; a.K = w ? pr.l2 : pr.l1; a.J = s.m; a.accumulate = 0;
         a.colscale = pr.out.R ? (const double*)WS(ws, pr.sgn) : nullptr;
         aj.push_back(a);
         atl.push_back((s.m + 63) / 64);
@@ -1010,7 +1018,7 @@ int enqueue(rgsvd_plan_s* P, void* ws, hipStream_t st) {
       case K_AB: launch_ab(s.prec, s.ta, s.tb, s.td, s.ct, s.js, (const AbJob*)j, pre, s.nj, s.tiles, st); break;
       case K_GRAM: launch_gram(s.ta, (const GramJob*)j, pre, s.nj, s.tiles, st); break;
       case K_RED: launch_reduce(s.ta, s.td, s.sym, (const RedJob*)j, pre, s.nj, s.tiles, st); break;
-      case K_CHOL: launch_chol((const CholJob*)j, s.nj, s.npad_max, (double*)((char*)ws + P->off_chol), st); break;
+      case K_CHOL: launch_chol((const CholJob*)j, s.nj, st); break;
       case K_SMALL: launch_small((const SmallJob*)j, s.nj, st); break;
       case K_BJINIT: launch_bjinit((const BJJob*)j, s.nj, s.sweep, st); break;
       case K_BJROUND: launch_bjround((const BJJob*)j, pre, s.nj, s.tiles, s.sweep, s.round, st); break;
@@ -1423,6 +1431,10 @@ int rgsvd_batch_plan(const rgsvd_desc* shapes, int32_t npairs, rgsvd_plan_t* pla
     if (shapes[i].in_dtype != shapes[0].in_dtype || shapes[i].precision != shapes[0].precision ||
         shapes[i].mode != shapes[0].mode)
       return RGSVD_EINVAL;
+    // every grouped launch serves all pairs at one step of the subspace
+    // iteration, so the pairs of a batch share the power count
+    if (shapes[i].power_iters != shapes[0].power_iters || shapes[i].sizing != RGSVD_SIZE_FIXED)
+      return RGSVD_EUNSUPPORTED;
   }
   rgsvd_plan_s* P = new (std::nothrow) rgsvd_plan_s();
   if (!P) return RGSVD_ENOMEM;

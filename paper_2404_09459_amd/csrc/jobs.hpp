@@ -55,22 +55,22 @@ struct RedJob {
   int32_t nz, pad;                   // symmetric reductions: rows / columns kept
 };
 
-// Omega^T generation: Wt[c][r] = Omega[r][col0 + c] for c < ncols, r < n;
-// rows ncols..L-1 zero.
+// Omega^T generation: Wt[c][r] = Omega[r][col0 + c] for c < ncols, r < n.
+// Rows ncols..L-1 are not written: the caller clears them beforehand.
 struct GenJob {
   void* Wt; int64_t ldw;
   uint64_t seed;
   int32_t n, col0, ncols, L, stream, pad;
 };
 
-// Cholesky of an N x N SPD Gram (sum of partials already formed) and the
-// inverse of its lower factor: sinv = L^{-1} (lower, N_pad x N_pad).
-// shift0 > 0 adds shift0 * trace(Gram) to the diagonal from the start
-// (the first pass of shifted CholeskyQR).  trunc != 0: a row whose pivot is
-// below CHOL_TRUNC_REL times its original diagonal (numerically inside the
-// span of the rows before it) gets a zero row in L^{-1} instead of a restart.
+// Cholesky of an N x N SPD Gram (N <= 256; sum of partials already formed)
+// and the inverse of its lower factor: sinv = L^{-1} (lower, npad x npad,
+// zero past N).  shift0 > 0 adds shift0 * trace(Gram) to the diagonal from
+// the start.  trunc != 0: a row whose pivot is below CHOL_TRUNC_REL times
+// its original diagonal (numerically inside the span of the rows before it)
+// gets a zero row in L^{-1} instead of a restart.
 struct CholJob {
-  const double* gram; double* sinv; double* r; int32_t* info;
+  const double* gram; double* sinv; int32_t* info;
   int32_t N, npad, flagbit, trunc;
   double shift0;
 };

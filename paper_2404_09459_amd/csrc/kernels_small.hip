@@ -1,7 +1,8 @@
 // Small dense FP64 steps, one workgroup (1024 threads) per matrix or pair.
 //
 //  k_chol     : Cholesky of the CholeskyQR Gram and the inverse of its lower
-//               factor (the orthonormalisation replacing Algorithm 1's QR)
+//               factor (the orthonormalisation replacing Algorithm 1's QR),
+//               blocked, the Gram in registers
 //  k_small    : the compressed-pair GSVD of Algorithm 2 with the truncation
 //               reading: eigen-decomposition of M = B B^T (one-sided Jacobi),
 //               the rank-t joint basis L = [L1; L2], the SVD of L1 (one-sided
@@ -17,8 +18,9 @@ namespace rg {
 
 // ---------------------------------------------------------------- k_chol --
 // Largest entry and sum of the Gram's diagonal (N entries, ld np) into
-// *md_s and *tr_s: wave 0 strides the diagonal and reduces by shuffles (one
-// thread reading it entry by entry took 20 us of the factorisation).
+// *md_s and *tr_s: wave 0 strides the diagonal and reduces by shuffles.  A
+// NaN or infinity anywhere in the Gram shows in the sum of its diagonal (a
+// Gram's diagonal holds the squared norms its entries are formed from).
 __device__ __forceinline__ void gram_diag_stats(const CholJob& J, int N, int np, double* md_s, double* tr_s) {
   if (threadIdx.x < 64) {
     const int ln = threadIdx.x;
@@ -29,246 +31,6 @@ __device__ __forceinline__ void gram_diag_stats(const CholJob& J, int N, int np,
   }
 }
 
-// Row elimination on [A | I]: after N steps the left block is R (A = R^T R)
-// and the right block is R^{-T}.  One npad x npad working array keeps R's
-// upper triangle and R^{-T}'s strict lower triangle; R^{-T}'s diagonal is
-// kept separately.  On a non-positive (or tiny relative) pivot the Gram is
-// shifted by s I and the factorisation restarted.
-//
-// npad <= 128: the working array lives in registers, 32 x 32 threads owning
-// a block-cyclic 4 x 4 set of entries each, so a step only broadcasts the
-// pivot row through LDS (each thread reads the values of its own rows and
-// columns).  Larger orders use a global-memory array.
-__device__ void chol_regs(const CholJob& J, double* lds) {
-  const int N = J.N, np = J.npad;
-  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
-  double* rowk = lds;            // scaled pivot row (np)
-  double* xd = lds + 128;        // diagonal of R^{-T} (np)
-  double* d0 = lds + 256;        // diagonal of the Gram (np)
-  __shared__ double piv_s, maxd_s;
-  __shared__ int bad_s;
-  double w[4][4];
-  __shared__ double trace_s;
-  gram_diag_stats(J, N, np, &maxd_s, &trace_s);
-  for (int i = tid; i < 128; i += 1024) d0[i] = i < N ? J.gram[(int64_t)i * np + i] : 0.0;
-  __syncthreads();
-  const double maxdiag = maxd_s;
-  double shift = J.shift0 > 0.0 ? J.shift0 * trace_s : 0.0;
-  bool shifted = false;
-  for (int attempt = 0;; ++attempt) {
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        int i = ty + 32 * a, j = tx + 32 * b;
-        double v = 0.0;
-        if (i < N && j < N && j >= i) v = J.gram[(int64_t)i * np + j] + (i == j ? shift : 0.0);
-        w[a][b] = v;
-      }
-    for (int i = tid; i < 128; i += 1024) xd[i] = 1.0;
-    if (tid == 0) bad_s = 0;
-    __syncthreads();
-    for (int k = 0; k < N; ++k) {
-      const int ak = k >> 5, ok_ = k & 31;
-      // pivot value from its owner
-      if (ty == ok_ && tx == ok_) {
-        double pv = 0.0;
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) if (a == ak && b == ak) pv = w[a][b];
-        piv_s = pv;
-      }
-      __syncthreads();
-      const double piv = piv_s;
-      const double d0k = d0[k];
-      if (J.trunc && isfinite(piv) && !(piv > CHOL_TRUNC_REL * d0k && piv > 0.0)) {
-        // row k is numerically dependent on the rows before it: zero row of
-        // L^{-1}, no elimination step
-        if (ty == ok_) {
-#pragma unroll
-          for (int a = 0; a < 4; ++a)
-            if (a == ak)
-#pragma unroll
-              for (int b = 0; b < 4; ++b) w[a][b] = 0.0;
-        }
-        if (tid == 0) xd[k] = 0.0;
-        __syncthreads();
-        continue;
-      }
-      if (!(piv > 1e-15 * d0k) || !(piv > 0.0) || !isfinite(piv)) { if (tid == 0) bad_s = 1; break; }
-      const double d = sqrt(piv), rd = 1.0 / d;
-      // owners of row k scale it and publish it
-      if (ty == ok_) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          if (a != ak) continue;
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            int j = tx + 32 * b;
-            if (j < N) {
-              double v = (j == k) ? d : w[a][b] * rd;
-              w[a][b] = v;
-              rowk[j] = v;
-            }
-          }
-        }
-      }
-      if (tid == 0) xd[k] *= rd;
-      __syncthreads();
-      const double xk = xd[k];
-      double fr[4], fc[4];
-#pragma unroll
-      for (int a = 0; a < 4; ++a) { int i = ty + 32 * a; fr[a] = (i < N) ? rowk[i] : 0.0; }
-#pragma unroll
-      for (int b = 0; b < 4; ++b) { int j = tx + 32 * b; fc[b] = (j < N) ? rowk[j] : 0.0; }
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int i = ty + 32 * a;
-        if (i <= k || i >= N) continue;
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int j = tx + 32 * b;
-          if (j >= N) continue;
-          if (j >= i) w[a][b] -= fr[a] * fc[b];
-          else if (j < k) w[a][b] -= fr[a] * fc[b];
-          else if (j == k) w[a][b] -= fr[a] * xk;
-        }
-      }
-    }
-    __syncthreads();
-    if (!bad_s) break;
-    if (attempt >= 8 || !(maxdiag > 0.0) || !isfinite(maxdiag)) {
-      for (int e = tid; e < np * np; e += 1024) J.sinv[e] = 0.0;
-      if (tid == 0 && J.info)
-        atomicOr(J.info + 4, isfinite(maxdiag) ? (1 << J.flagbit) | FLAG_CHOL_FAIL : FLAG_NONFINITE);
-      return;
-    }
-    shift = (shift == 0.0) ? 1e-14 * maxdiag * (double)N : shift * 100.0;
-    shifted = true;
-    __syncthreads();
-  }
-  // write R^{-T} (strict lower from the array, diagonal from xd), zero elsewhere
-  for (int e = tid; e < np * np; e += 1024) J.sinv[e] = 0.0;
-  __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      int i = ty + 32 * a, j = tx + 32 * b;
-      if (i < N && j < N) {
-        if (j < i) J.sinv[(int64_t)i * np + j] = w[a][b];
-        else if (j == i) J.sinv[(int64_t)i * np + j] = xd[i];
-        if (J.r) J.r[(int64_t)i * np + j] = (j >= i) ? w[a][b] : 0.0;
-      }
-    }
-  if (tid == 0 && shifted && J.info) atomicOr(J.info + 4, 1 << J.flagbit);
-}
-
-__device__ void chol_global(const CholJob& J, double* W, double* xd, double* d0) {
-  const int N = J.N, np = J.npad;
-  __shared__ int bad;
-  __shared__ double shift;
-  __shared__ int shifted;
-  const int tid = threadIdx.x;
-  double maxdiag = 0.0, trace = 0.0;
-  for (int i = 0; i < N; ++i) {
-    const double d = J.gram[(int64_t)i * np + i];
-    maxdiag = fmax(maxdiag, d);
-    trace += d;
-  }
-  if (tid == 0) { shift = J.shift0 > 0.0 ? J.shift0 * trace : 0.0; shifted = 0; }
-  __syncthreads();
-  int attempt = 0;
-  for (;;) {
-    for (int e = tid; e < np * np; e += 1024) {
-      int i = e / np, j = e - i * np;
-      double v = 0.0;
-      if (i < N && j < N) {
-        if (j >= i) v = J.gram[(int64_t)i * np + j] + (i == j ? shift : 0.0);
-      }
-      W[e] = v;
-    }
-    for (int i = tid; i < np; i += 1024) {
-      xd[i] = 1.0;
-      d0[i] = (i < N) ? J.gram[(int64_t)i * np + i] : 0.0;
-    }
-    if (tid == 0) bad = 0;
-    __syncthreads();
-    const int tx = tid & 31, ty = tid >> 5;
-    for (int k = 0; k < N; ++k) {
-      const double piv = W[k * np + k];
-      __syncthreads();   // every thread holds the pivot before row k is rescaled
-      if (J.trunc && isfinite(piv) && !(piv > CHOL_TRUNC_REL * d0[k] && piv > 0.0)) {
-        for (int j = tid; j < np; j += 1024) W[k * np + j] = 0.0;
-        if (tid == 0) xd[k] = 0.0;
-        __syncthreads();
-        continue;
-      }
-      bool brk = !(piv > 1e-15 * d0[k]) || !(piv > 0.0) || !isfinite(piv);
-      if (brk) { if (tid == 0) bad = 1; break; }
-      double d = sqrt(piv), rd = 1.0 / d;
-      for (int j = tid; j < N; j += 1024) {
-        if (j != k) W[k * np + j] *= rd;
-        else { W[k * np + k] = d; xd[k] *= rd; }
-      }
-      __syncthreads();
-      const double xk = xd[k];
-      for (int i = k + 1 + ty; i < N; i += 32) {
-        const double f = W[k * np + i];
-        double* Wi = W + i * np;
-        const double* Wk = W + k * np;
-        for (int j = tx; j < N; j += 32) {
-          if (j >= i) Wi[j] -= f * Wk[j];
-          else if (j < k) Wi[j] -= f * Wk[j];
-          else if (j == k) Wi[j] -= f * xk;
-        }
-      }
-      __syncthreads();
-    }
-    __syncthreads();
-    if (!bad) break;
-    ++attempt;
-    if (attempt > 8 || !(maxdiag > 0.0) || !isfinite(maxdiag)) {
-      for (int e = tid; e < np * np; e += 1024) J.sinv[e] = 0.0;
-      if (tid == 0 && J.info)
-        atomicOr(J.info + 4, isfinite(maxdiag) ? (1 << J.flagbit) | FLAG_CHOL_FAIL : FLAG_NONFINITE);
-      return;
-    }
-    if (tid == 0) {
-      shift = (shift == 0.0) ? 1e-14 * maxdiag * (double)N : shift * 100.0;
-      shifted = 1;
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < np * np; e += 1024) {
-    int i = e / np, j = e - i * np;
-    double v = 0.0;
-    if (i < N && j < N) {
-      if (j < i) v = W[e];
-      else if (j == i) v = xd[i];
-    }
-    J.sinv[e] = v;
-    if (J.r) J.r[e] = (i < N && j < N && j >= i) ? W[e] : 0.0;
-  }
-  if (tid == 0 && shifted && J.info) atomicOr(J.info + 4, 1 << J.flagbit);
-}
-
-// ------------------------------------------------------ blocked Cholesky --
-// Order N <= CB_MAXN, no truncation: right-looking in 16 x 16 blocks with the
-// working array A (N16 x CB_LDA, N16 = N rounded up to 16, padded with the
-// identity) in LDS.  Per block column kb: one wave factors the diagonal block
-// and inverts its factor in registers (lane j holds column j; scalar
-// broadcasts by readlane); the panel R[kb, jb] = R_kk^{-T} A[kb, jb] and the
-// trailing update A[ib, jb] -= R[kb, ib]^T R[kb, jb] (ib <= jb) run on FP64
-// MFMA, one 16 x 16 block per wave.  R^{-1} then follows by block diagonals,
-// X_ij = -R_ii^{-1} sum_{k=i+1..j} R_ik X_kj.  The upper triangle of A ends
-// holding R and the lower triangle R^{-T} (diagonal separately), the layout
-// the register path produces.  A non-positive or tiny pivot restarts with a
-// shift, as there.
-constexpr int CB_MAXN = 112, CB_LDA = 113;
-constexpr size_t CB_LDS_BYTES = (size_t)(CB_MAXN * CB_LDA + 2 * CB_MAXN) * sizeof(double);
-
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)b, lane);
@@ -276,45 +38,116 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-__device__ void chol_blocked(const CholJob& J, double* lds) {
-  const int N = J.N, np = J.npad;
-  const int N16 = (N + 15) & ~15, nb = N16 >> 4;
-  const int tid = threadIdx.x, wave = tid >> 6, ln = tid & 63, g = ln >> 4, r16 = ln & 15;
-  double* A = lds;                               // N16 x CB_LDA
-  double* rdiag = lds + CB_MAXN * CB_LDA;        // diagonal of R^{-T}
-  double* d0 = rdiag + CB_MAXN;                  // Gram diagonal (pivot test)
+// Cholesky A = R^T R of an N x N Gram (N <= CB_MAXN) and X = R^{-T}, the
+// inverse of the lower factor L = R^T, right-looking in 16 x 16 blocks.
+//
+// The upper triangle's nb (nb + 1) / 2 blocks (nb = ceil(N / 16); the order
+// is padded to 16 nb with the identity) are numbered column by column; block
+// f lives in registers, in slot f / CB_W of wave f % CB_W, as one FP64 MFMA
+// accumulator (lane (g, c) holds rows 4q + g, q < 4, of column c).  The same
+// slots carry the inverse: block (i, j) holds A[i][j] until step i turns it
+// into R[i][j], and from then on T[j][i], the right-hand side of the block
+// forward substitution L X = I, until step j finishes X[j][i].  Step kb:
+//   1. the owner of A[kb][kb] publishes it; wave 0 factors it, R_kk^T R_kk,
+//      one column per lane with scalar broadcasts, and forms X_kk = R_kk^{-T};
+//   2. the panel R[kb][j] = X_kk A[kb][j] (j > kb) and the finished row of
+//      the inverse X[kb][i] = X_kk T[kb][i] (i < kb) go to LDS (X also to
+//      sinv);
+//   3. trailing updates on FP64 MFMA: A[i][j] -= R[kb][i]^T R[kb][j]
+//      (kb < i <= j) and T[j][i] -= R[kb][j]^T X[kb][i] (i <= kb < j).
+// Pivot test and recovery: a pivot that is not positive and above 1e-15 of
+// its original diagonal restarts the factorisation with a diagonal shift
+// (1e-14 N max diag, growing 100-fold, at most 8 times; the run's flag bit
+// records it), unless `trunc` is set, where a pivot below CHOL_TRUNC_REL of
+// its original diagonal marks a row numerically inside the span of the rows
+// before it: that row of R and of X becomes zero and it eliminates nothing.
+// A non-finite Gram leaves X = 0 and raises FLAG_NONFINITE.
+constexpr int CB_MAXN = 256, CB_MAXNB = CB_MAXN / 16, CB_W = 8;
+constexpr int CB_NBLK = CB_MAXNB * (CB_MAXNB + 1) / 2;
+constexpr int CB_SLOTS = (CB_NBLK + CB_W - 1) / CB_W;
+constexpr int CB_LD = CB_MAXN + 4;   // panel row stride (doubles): rows of a k-step fall on different banks
+constexpr size_t CB_LDS_BYTES = (size_t)(2 * 16 * CB_LD + 2 * 256 + CB_MAXN) * sizeof(double);
+
+__global__ __launch_bounds__(64 * CB_W) void k_chol(const CholJob* __restrict__ jobs, int nj) {
+  extern __shared__ double lds[];
+  __shared__ unsigned char bi_s[CB_NBLK], bj_s[CB_NBLK];
   __shared__ int bad_s;
   __shared__ double trace_s, maxd_s;
+  const CholJob J = jobs[blockIdx.x];
+  const int N = J.N, np = J.npad;
+  const int nb = (N + 15) >> 4, nblk = nb * (nb + 1) / 2;
+  const int tid = threadIdx.x, wave = tid >> 6, ln = tid & 63, g = ln >> 4, c16 = ln & 15;
+  double* panel = lds;                 // 16 x CB_LD: R[kb][j] in columns 16 j .. 16 j + 15
+  double* xrow = panel + 16 * CB_LD;   // 16 x CB_LD: X[kb][i] in columns 16 i .. 16 i + 15
+  double* Dk = xrow + 16 * CB_LD;      // A[kb][kb], row-major 16 x 16
+  double* Xk = Dk + 256;               // X_kk, row-major 16 x 16 (lower)
+  double* d0 = Xk + 256;               // the Gram's diagonal (pivot tests)
+  if (tid < nblk) {
+    int f = tid, j = 0;
+    while (f > j) { f -= j + 1; ++j; }   // column j of the upper triangle holds j + 1 blocks
+    bi_s[tid] = (unsigned char)f;
+    bj_s[tid] = (unsigned char)j;
+  }
   gram_diag_stats(J, N, np, &maxd_s, &trace_s);
-  for (int i = tid; i < N16; i += 1024) d0[i] = i < N ? J.gram[(int64_t)i * np + i] : 1.0;
+  for (int i = tid; i < 16 * nb; i += 64 * CB_W) d0[i] = i < N ? J.gram[(int64_t)i * np + i] : 1.0;
+  for (int e = tid; e < np * np; e += 64 * CB_W) J.sinv[e] = 0.0;
   __syncthreads();
+  if (!isfinite(trace_s)) {
+    if (tid == 0 && J.info) atomicOr(J.info + 4, FLAG_NONFINITE);
+    return;
+  }
   const double maxdiag = maxd_s;
   double shift = J.shift0 > 0.0 ? J.shift0 * trace_s : 0.0;
   bool shifted = false;
+  d4 S[CB_SLOTS];
   for (int attempt = 0;; ++attempt) {
-    for (int e = tid; e < N16 * N16; e += 1024) {
-      const int i = e / N16, j = e - i * N16;
-      double v;
-      if (i < N && j < N) v = J.gram[(int64_t)i * np + j] + (i == j ? shift : 0.0);
-      else v = (i == j) ? 1.0 : 0.0;
-      A[i * CB_LDA + j] = v;
+    // the Gram's upper blocks (+ shift on the diagonal; identity past N)
+#pragma unroll
+    for (int s = 0; s < CB_SLOTS; ++s) {
+      const int f = CB_W * s + wave;
+      d4 v = {0.0, 0.0, 0.0, 0.0};
+      if (f < nblk) {
+        const int col = 16 * bj_s[f] + c16;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int row = 16 * bi_s[f] + 4 * q + g;
+          v[q] = (row < N && col < N) ? J.gram[(int64_t)row * np + col] + (row == col ? shift : 0.0)
+                                      : (row == col ? 1.0 : 0.0);
+        }
+      }
+      S[s] = v;
     }
     if (tid == 0) bad_s = 0;
     __syncthreads();
     for (int kb = 0; kb < nb; ++kb) {
       const int o = 16 * kb;
+      // 1. the diagonal block, factored by wave 0
+      const int fd = kb * (kb + 1) / 2 + kb;
+      if (wave == fd % CB_W) {
+#pragma unroll
+        for (int s = 0; s < CB_SLOTS; ++s)
+          if (s == fd / CB_W)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) Dk[(4 * q + g) * 16 + c16] = S[s][q];
+      }
+      __syncthreads();
       if (wave == 0) {
-        // factor the diagonal block: lane j < 16 holds column j (upper part)
+        // lane j < 16 holds column j of the block's upper part
         const int j = ln;
         double d[16];
-        double myinv = 0.0;    // 1 / R_jj of this lane's column
+        double myinv = 0.0;    // 1 / R_jj of this lane's column (0 for a dropped row)
 #pragma unroll
-        for (int i = 0; i < 16; ++i) d[i] = (j < 16 && i <= j) ? A[(o + i) * CB_LDA + o + j] : 0.0;
+        for (int i = 0; i < 16; ++i) d[i] = (j < 16 && i <= j) ? Dk[i * 16 + j] : 0.0;
         bool bad = false;
 #pragma unroll
         for (int k = 0; k < 16; ++k) {
           const double piv = readlane_f64(d[k], k);
-          if (!(piv > 1e-15 * d0[o + k]) || !(piv > 0.0) || !isfinite(piv)) bad = true;
+          const double dk0 = d0[o + k];
+          if (J.trunc && isfinite(piv) && !(piv > CHOL_TRUNC_REL * dk0 && piv > 0.0)) {
+            if (j >= k) d[k] = 0.0;          // zero row k: it eliminates nothing
+            continue;
+          }
+          if (!(piv > 1e-15 * dk0) || !(piv > 0.0) || !isfinite(piv)) bad = true;
           const double r = sqrt(piv), ri = 1.0 / r;
           if (j == k) myinv = ri;
           if (j >= k) d[k] = (j == k) ? r : d[k] * ri;
@@ -324,17 +157,8 @@ __device__ void chol_blocked(const CholJob& J, double* lds) {
             if (j >= i) d[i] -= rki * d[k];
           }
         }
-        // R_kk (upper) and 1 / R_jj to LDS; then X = R_kk^{-1}, column j per
-        // lane: x_j = 1 / R_jj, x_i = -(sum_{m=i+1..j} R_im x_m) / R_ii, with
-        // R_im and 1 / R_ii read from the lanes that hold them (lane m's d[i],
-        // lane i's myinv), not back from LDS: LDS loads inside this dependent
-        // chain made it 6.3 of the block's 9 us
-        if (j < 16) {
-#pragma unroll
-          for (int i = 0; i < 16; ++i)
-            if (i <= j) A[(o + i) * CB_LDA + o + j] = d[i];
-          rdiag[o + j] = myinv;
-        }
+        // column j of R_kk^{-1}: x_j = 1 / R_jj, x_i = -(sum_{m=i+1..j} R_im x_m) / R_ii,
+        // R_im and 1 / R_ii read from the lanes that hold them
         double x[16];
 #pragma unroll
         for (int i = 15; i >= 0; --i) {
@@ -345,113 +169,77 @@ __device__ void chol_blocked(const CholJob& J, double* lds) {
           const double rinv = readlane_f64(myinv, i);
           x[i] = (i < j) ? -acc * rinv : (i == j ? rinv : 0.0);
         }
+        // row j of X_kk = R_kk^{-T} is column j of R_kk^{-1}
         if (j < 16) {
 #pragma unroll
-          for (int i = 0; i < 16; ++i)
-            if (i < j) A[(o + j) * CB_LDA + o + i] = x[i];    // R^{-T} (strict lower)
+          for (int i = 0; i < 16; ++i) {
+            const double v = i <= j ? x[i] : 0.0;
+            Xk[j * 16 + i] = v;
+            xrow[j * CB_LD + o + i] = v;
+            if (i <= j && o + j < N) J.sinv[(int64_t)(o + j) * np + o + i] = v;
+          }
         }
         if (bad && ln == 0) bad_s = 1;
       }
       __syncthreads();
       if (bad_s) break;
-      // panel: R[kb, jb] = R_kk^{-T} A[kb, jb], one block per wave
-      for (int jb = kb + 1 + wave; jb < nb; jb += 16) {
+      // 2. panel row kb of R and row kb of the inverse
+#pragma unroll
+      for (int s = 0; s < CB_SLOTS; ++s) {
+        const int f = CB_W * s + wave;
+        if (f >= nblk) continue;
+        const int bi = bi_s[f], bj = bj_s[f];
+        if (bi == bj || (bi != kb && bj != kb)) continue;
         d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int m = 4 * kk + g;
-          const double a = m < r16 ? A[(o + r16) * CB_LDA + o + m] : (m == r16 ? rdiag[o + m] : 0.0);
-          const double b = A[(o + m) * CB_LDA + 16 * jb + r16];
-          acc = mma64(a, b, acc);
-        }
+        for (int kk = 0; kk < 4; ++kk) acc = mma64(Xk[c16 * 16 + 4 * kk + g], S[s][kk], acc);
+        if (bi == kb) {
+          // R[kb][bj]; the slot now holds T[bj][kb], which starts at zero
 #pragma unroll
-        for (int q = 0; q < 4; ++q) A[(o + out_row<0>(g, q)) * CB_LDA + 16 * jb + r16] = acc[q];
+          for (int q = 0; q < 4; ++q) panel[(4 * q + g) * CB_LD + 16 * bj + c16] = acc[q];
+          S[s] = d4{0.0, 0.0, 0.0, 0.0};
+        } else {
+          // X[kb][bi] (bj == kb > bi), final
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int row = o + 4 * q + g;
+            xrow[(4 * q + g) * CB_LD + 16 * bi + c16] = acc[q];
+            if (row < N) J.sinv[(int64_t)row * np + 16 * bi + c16] = acc[q];
+          }
+        }
       }
       __syncthreads();
-      // trailing update of the blocks (ib, jb), kb < ib <= jb
-      const int rem = nb - kb - 1;
-      for (int t = wave; t < rem * (rem + 1) / 2; t += 16) {
-        int ib = 0, tt = t;
-        while (tt >= rem - ib) { tt -= rem - ib; ++ib; }
-        const int jb = kb + 1 + ib + tt;
-        ib += kb + 1;
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
+      // 3. trailing updates
+#pragma unroll
+      for (int s = 0; s < CB_SLOTS; ++s) {
+        const int f = CB_W * s + wave;
+        if (f >= nblk) continue;
+        const int bi = bi_s[f], bj = bj_s[f];
+        if (bj <= kb) continue;
+        // A[bi][bj] -= R[kb][bi]^T R[kb][bj]  or  T[bj][bi] -= R[kb][bj]^T X[kb][bi]
+        const double* pa = panel + 16 * (bi > kb ? bi : bj) + c16;
+        const double* pb = (bi > kb ? panel + 16 * bj : xrow + 16 * bi) + c16;
+        d4 acc = S[s];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
           const int m = 4 * kk + g;
-          acc = mma64(A[(o + m) * CB_LDA + 16 * ib + r16], A[(o + m) * CB_LDA + 16 * jb + r16], acc);
+          acc = mma64(-pa[m * CB_LD], pb[m * CB_LD], acc);
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) A[(16 * ib + out_row<0>(g, q)) * CB_LDA + 16 * jb + r16] -= acc[q];
+        S[s] = acc;
       }
       __syncthreads();
     }
     if (!bad_s) break;
-    if (attempt >= 8 || !(maxdiag > 0.0) || !isfinite(maxdiag)) {
-      for (int e = tid; e < np * np; e += 1024) J.sinv[e] = 0.0;
-      if (tid == 0 && J.info)
-        atomicOr(J.info + 4, isfinite(maxdiag) ? (1 << J.flagbit) | FLAG_CHOL_FAIL : FLAG_NONFINITE);
+    if (attempt >= 8 || !(maxdiag > 0.0)) {
+      for (int e = tid; e < np * np; e += 64 * CB_W) J.sinv[e] = 0.0;
+      if (tid == 0 && J.info) atomicOr(J.info + 4, (1 << J.flagbit) | FLAG_CHOL_FAIL);
       return;
     }
     shift = (shift == 0.0) ? 1e-14 * maxdiag * (double)N : shift * 100.0;
     shifted = true;
     __syncthreads();
   }
-  // R^{-1} by block diagonals: X_ij (j = i + dd), stored transposed in the
-  // lower block (j, i)
-  for (int dd = 1; dd < nb; ++dd) {
-    for (int i = wave; i + dd < nb; i += 16) {
-      const int j = i + dd;
-      d4 tacc = {0.0, 0.0, 0.0, 0.0};
-      for (int k = i + 1; k <= j; ++k) {
-#pragma unroll
-        for (int kk = 0; kk < 4; ++kk) {
-          const int m = 4 * kk + g;
-          const double a = A[(16 * i + r16) * CB_LDA + 16 * k + m];                 // R_ik
-          double b;                                                                   // X_kj[m][r16]
-          if (k < j) b = A[(16 * j + r16) * CB_LDA + 16 * k + m];
-          else b = m < r16 ? A[(16 * j + r16) * CB_LDA + 16 * j + m] : (m == r16 ? rdiag[16 * j + m] : 0.0);
-          tacc = mma64(a, b, tacc);
-        }
-      }
-      // X_ij = -X_ii T; T's accumulator layout is the B operand's
-      d4 xacc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int m = 4 * kk + g;
-        const double a = r16 < m ? A[(16 * i + m) * CB_LDA + 16 * i + r16] : (r16 == m ? rdiag[16 * i + r16] : 0.0);
-        xacc = mma64(a, tacc[kk], xacc);
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) A[(16 * j + r16) * CB_LDA + 16 * i + out_row<0>(g, q)] = -xacc[q];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < np * np; e += 1024) {
-    const int i = e / np, j = e - i * np;
-    double v = 0.0;
-    if (i < N && j < N) {
-      if (j < i) v = A[i * CB_LDA + j];
-      else if (j == i) v = rdiag[i];
-    }
-    J.sinv[e] = v;
-  }
   if (tid == 0 && shifted && J.info) atomicOr(J.info + 4, 1 << J.flagbit);
-}
-
-__global__ __launch_bounds__(1024) void k_chol(const CholJob* __restrict__ jobs, int nj,
-                                               double* __restrict__ gscratch) {
-  __shared__ double lds[384];
-  extern __shared__ double big[];
-  const CholJob J = jobs[blockIdx.x];
-  if (!J.trunc && !J.r && J.N <= CB_MAXN) {
-    chol_blocked(J, big);
-  } else if (J.npad <= 128) {
-    chol_regs(J, lds);
-  } else {
-    double* W = gscratch + (int64_t)blockIdx.x * (CHOL_MAX * CHOL_MAX + 2 * CHOL_MAX);
-    chol_global(J, W, W + (int64_t)J.npad * J.npad, W + (int64_t)J.npad * J.npad + J.npad);
-  }
 }
 
 // ------------------------------------------------------ one-sided Jacobi --
@@ -677,12 +465,14 @@ jacobi_os(double* A, int lda, int nr, int nc, double tol, int maxsweep, int topk
   return sw;
 }
 
-// rank of key[i] among n keys, descending, ties by index (for sorting)
+// rank of key[i] among n keys, descending, ties by index (for sorting).  A
+// NaN key ranks below every number, so the ranks stay a permutation and
+// every index formed from them stays in range.
 __device__ inline int rank_desc(const double* key, int n, int i) {
-  double v = key[i];
+  const double v = isnan(key[i]) ? -INFINITY : key[i];
   int r = 0;
   for (int j = 0; j < n; ++j) {
-    double w = key[j];
+    const double w = isnan(key[j]) ? -INFINITY : key[j];
     r += (w > v) || (w == v && j < i);
   }
   return r;
@@ -886,6 +676,33 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
   const int stage = J.stage;
   int rh, sw1, sw2;
   double* FH = F;
+  // A NaN or infinity in G reaches B and the diagonal of M = B B^T (the
+  // squared row norms of B).  Such a pair gets NaN GSVs and quantities, zero
+  // recovery coefficients and FLAG_NONFINITE; its later stages and block
+  // Jacobi launches return at once (rank -1 and done in its state).
+  if (stage <= 1) {
+    if (tid == 0) sh.scratch[4] = 0;
+    __syncthreads();
+    for (int i = tid; i < N; i += 1024)
+      if (!isfinite(J.M[(int64_t)i * J.ldm + i])) sh.scratch[4] = 1;
+    __syncthreads();
+    if (sh.scratch[4]) {
+      const double qnan = __longlong_as_double(0x7ff8000000000000ll);
+      for (int i = tid; i < t; i += 1024) { J.alpha[i] = J.beta[i] = J.theta[i] = J.P1[i] = J.P2[i] = qnan; }
+      for (int i = tid; i < N; i += 1024) J.sigma[i] = qnan;
+      for (int e = tid; e < t * l1; e += 1024) J.X1t[(int64_t)(e / l1) * J.ldx1 + e % l1] = 0.0;
+      for (int e = tid; e < t * J.l2; e += 1024) J.X2t[(int64_t)(e / J.l2) * J.ldx2 + e % J.l2] = 0.0;
+      for (int e = tid; e < t * N; e += 1024) J.Rcoef[(int64_t)(e / N) * J.ldr + e % N] = 0.0;
+      if (tid == 0) {
+        J.D[0] = J.D[1] = qnan;
+        S->rank = -1; S->nc = 0; S->done = 1;
+        if (J.info) { J.info[5] = 0; J.info[6] = 0; atomicOr(J.info + 4, FLAG_NONFINITE); }
+      }
+      return;
+    }
+  } else if (S->rank < 0) {
+    return;
+  }
   if (stage <= 2) {
     // ---- 1. eigen-decomposition of M
     int rank, base = 0;
@@ -1239,14 +1056,13 @@ __global__ __launch_bounds__(256) void k_scale_rows(const SignJob* __restrict__ 
 }
 
 // ---------------------------------------------------------------- launch --
-void launch_chol(const CholJob* j, int nj, int npad_max, double* gscratch, hipStream_t st) {
-  (void)npad_max;
+void launch_chol(const CholJob* j, int nj, hipStream_t st) {
   static bool attr_set = false;
   if (!attr_set) {
     hipFuncSetAttribute((const void*)k_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)CB_LDS_BYTES);
     attr_set = true;
   }
-  hipLaunchKernelGGL(k_chol, dim3(nj), dim3(1024), CB_LDS_BYTES, st, j, nj, gscratch);
+  hipLaunchKernelGGL(k_chol, dim3(nj), dim3(64 * CB_W), CB_LDS_BYTES, st, j, nj);
 }
 
 void launch_small(const SmallJob* j, int nj, hipStream_t st) {

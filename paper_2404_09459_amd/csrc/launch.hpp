@@ -14,7 +14,7 @@ void launch_ab(int prec, int ta, int tb, int td, int ct, int js, const AbJob* j,
 void launch_gram(int tx, const GramJob* j, const int* pre, int nj, int tiles, hipStream_t st);
 void launch_reduce(int ti, int to, bool sym, const RedJob* j, const int* pre, int nj, int tiles,
                    hipStream_t st);
-void launch_chol(const CholJob* j, int nj, int npad_max, double* gscratch, hipStream_t st);
+void launch_chol(const CholJob* j, int nj, hipStream_t st);
 void launch_small(const SmallJob* j, int nj, hipStream_t st);
 void launch_bjinit(const BJJob* j, int nj, int sweep, hipStream_t st);
 void launch_bjround(const BJJob* j, const int* pre, int nj, int tiles, int sweep, int round, hipStream_t st);

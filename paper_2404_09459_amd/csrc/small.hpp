@@ -4,8 +4,6 @@
 
 namespace rg {
 
-constexpr int CHOL_LDS_MAX = 128;   // Gram orders kept in LDS by k_chol
-constexpr int CHOL_MAX = 256;       // largest padded Gram order
 constexpr int SMALL_MAXN = 512;     // largest l1 + l2 of the compressed pair
 constexpr double BETA_ZERO = 1e-14;
 constexpr double CHOL_TRUNC_REL = 1e-10;   // truncated Cholesky: pivot / original diagonal

@@ -73,3 +73,19 @@ def test_run_rejects_bad_pointers_without_gpu():
     assert R.lib().rgsvd_run(h, ctypes.c_void_p(4096), 39, ctypes.c_void_p(8192), 40,
                              ctypes.c_void_p(4096), None, ctypes.byref(out)) == R.EINVAL
     R.lib().rgsvd_destroy(h)
+
+
+def test_batch_plan_requires_one_power_count():
+    """Every grouped launch of a batch serves all pairs at one step of the
+    subspace iteration: pairs with different power counts are refused."""
+    from paper_2404_09459_amd import rgsvd as R
+    d0 = R.make_desc(400, 300, 100, 10, 5, 2, 1, R.F32, "mixed")
+    d1 = R.make_desc(500, 350, 120, 12, 5, 1, 2, R.F32, "mixed")
+    arr = (R.Desc * 2)(d0, d1)
+    h = ctypes.c_void_p()
+    ws = ctypes.c_size_t()
+    assert R.lib().rgsvd_batch_plan(arr, 2, ctypes.byref(h), ctypes.byref(ws)) == R.EUNSUPPORTED
+    d1.power_iters = 2
+    arr = (R.Desc * 2)(d0, d1)
+    assert R.lib().rgsvd_batch_plan(arr, 2, ctypes.byref(h), ctypes.byref(ws)) == 0
+    R.lib().rgsvd_destroy(h)

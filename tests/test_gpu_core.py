@@ -269,6 +269,6 @@ def test_reduced_precision_gate(dev, precision):
     dd = np.max(np.abs(got["D"] - [ref["D1"], ref["D2"]]))
     _say(f"   pinned {len(idx)}/{k} |dtheta|={dth:.2e} (all {np.max(np.abs(got['theta'] - ref['theta'])):.2e})"
          f" |dD|={dd:.2e} info={got['info'].tolist()}")
-    assert len(idx) >= k // 2
+    assert len(idx) == k
     assert dth <= 1e-4 and dd <= 1e-5
     assert np.max(np.abs(got["alpha"] ** 2 + got["beta"] ** 2 - 1)) <= 1e-12
