@@ -62,6 +62,7 @@ extern "C" {
 #define RGSVD_EWORKSPACE (-5)  /* workspace null or misaligned (needs 256-byte base) */
 #define RGSVD_ENOMODEL (-6)    /* learned sizing requested without a sizing model    */
 #define RGSVD_EUNSUPPORTED (-7)/* combination not provided by this build             */
+#define RGSVD_ETOOBIG (-8)     /* workspace exceeds RGSVD_STATIC_SCRATCH_BYTES        */
 
 /* storage type of G */
 #define RGSVD_F64 0
@@ -160,6 +161,23 @@ int rgsvd_plan(const rgsvd_desc* desc, rgsvd_plan_t* plan, size_t* workspace_byt
  * Errors: RGSVD_EINVAL, RGSVD_EWORKSPACE, RGSVD_ENOMODEL, RGSVD_EHIP. */
 int rgsvd_run(rgsvd_plan_t plan, const void* G1, int64_t ld1, const void* G2, int64_t ld2,
               void* workspace, void* stream, const rgsvd_out* out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * run as rgsvd_run, without a workspace argument.  Its workspace is a
+ * device array of RGSVD_STATIC_SCRATCH_BYTES (64 MiB) built into the library,
+ * one per GPU, held until the process ends.  The call allocates nothing:
+ * no hipMalloc, hipFree or pinned host memory (the plan's job tables are
+ * copied into that array with hipMemcpyAsync from the plan's host memory).
+ * Every static run on a GPU shares that GPU's array and leaves its contents
+ * behind; each run clears what it needs.  Static runs that overlap on one
+ * GPU (two streams, two threads) race on the array: serialise them.
+ * Fixed sizing only.  Errors: RGSVD_EINVAL, RGSVD_EUNSUPPORTED (adaptive or
+ * learned plans), RGSVD_ETOOBIG (the plan's workspace, as reported by
+ * rgsvd_plan, is above RGSVD_STATIC_SCRATCH_BYTES), RGSVD_EHIP. */
+#define RGSVD_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+int rgsvd_run_static(rgsvd_plan_t plan, const void* G1, int64_t ld1, const void* G2, int64_t ld2,
+                     void* stream, const rgsvd_out* out);
 
 /* t (number of returned pairs) and l1, l2: the sketch widths of fixed
  * sizing, the largest widths (capacities) of adaptive and learned sizing. */

@@ -18,7 +18,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <atomic>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -100,6 +102,8 @@ struct PairLay {
 
 struct rgsvd_plan_s {
   rgsvd_desc d{};
+  uint64_t id = 0;    // unique per plan (the static scratch remembers which plan's tables it holds)
+  uint64_t gen = 0;   // bumped whenever the job tables are rebuilt
   bool batched = false;
   int prec = 0, gdt = 0, mode = 0;
   int Lmax = 16, npadG = 64;
@@ -1298,6 +1302,31 @@ int autotune_plan(rgsvd_plan_s* P, void* ws, hipStream_t st, int reps, int32_t* 
   return RGSVD_OK;
 }
 
+static uint64_t next_plan_id() {
+  static std::atomic<uint64_t> n{0};
+  return ++n;
+}
+
+// ------------------------------------------------- allocation-free runs --
+// Workspace of rgsvd_run_static: a file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never passes the array's name
+// to a kernel or copy (on the host it is only a stand-in symbol): the first
+// static run on a device looks up that device's address once, with the
+// device current, and every later use goes through it.
+static __device__ __align__(256) unsigned char scratch[RGSVD_STATIC_SCRATCH_BYTES];
+
+struct StaticSlot {
+  void* ptr = nullptr;   // device address of `scratch` on this GPU
+  uint64_t owner = 0;    // plan whose job tables the scratch holds
+  uint64_t gen = 0;      // and their generation
+};
+constexpr int MAX_DEVICES = 64;
+static std::mutex& static_mutex() {
+  static std::mutex m;
+  return m;
+}
+static StaticSlot g_static[MAX_DEVICES];
+
 // ===================================================================== ABI ==
 extern "C" {
 
@@ -1311,6 +1340,7 @@ const char* rgsvd_strerror(int code) {
     case RGSVD_EWORKSPACE: return "workspace null or not 256-byte aligned";
     case RGSVD_ENOMODEL: return "learned sizing needs a sizing model";
     case RGSVD_EUNSUPPORTED: return "unsupported combination";
+    case RGSVD_ETOOBIG: return "workspace larger than the static scratch (RGSVD_STATIC_SCRATCH_BYTES)";
     default: return "unknown error";
   }
 }
@@ -1323,6 +1353,7 @@ int rgsvd_plan(const rgsvd_desc* desc, rgsvd_plan_t* plan, size_t* workspace_byt
   rgsvd_plan_s* P = new (std::nothrow) rgsvd_plan_s();
   if (!P) return RGSVD_ENOMEM;
   P->d = *desc;
+  P->id = next_plan_id();
   P->prec = desc->precision == RGSVD_PREC_FP64 ? P64 : (desc->precision == RGSVD_PREC_FP32 ? P32 : PBF);
   P->gdt = desc->in_dtype;
   P->mode = desc->mode;
@@ -1388,6 +1419,56 @@ int rgsvd_run(rgsvd_plan_t P, const void* G1, int64_t ld1, const void* G2, int64
   return enqueue(P, workspace, st);
 }
 
+int rgsvd_run_static(rgsvd_plan_t P, const void* G1, int64_t ld1, const void* G2, int64_t ld2, void* stream,
+                     const rgsvd_out* out) {
+  if (!P || P->batched || !G1 || !G2 || !out) return RGSVD_EINVAL;
+  if (P->adaptive || P->learned) return RGSVD_EUNSUPPORTED;
+  if (P->ws > RGSVD_STATIC_SCRATCH_BYTES) return RGSVD_ETOOBIG;
+  PairLay& pr = P->pairs[0];
+  if (ld1 < pr.n || ld2 < pr.n) return RGSVD_EINVAL;
+  if ((out->U && out->ldu < pr.m) || (out->V && out->ldv < pr.p) || (out->R && out->ldr < pr.n))
+    return RGSVD_EINVAL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return RGSVD_EHIP;
+  hipStream_t st = (hipStream_t)stream;
+  std::lock_guard<std::mutex> lock(static_mutex());
+  StaticSlot& sl = g_static[dev];
+  if (!sl.ptr) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return RGSVD_EHIP;
+    sl.ptr = ptr;
+  }
+  void* ws = sl.ptr;
+  const bool same = P->bound && P->lastG1 == G1 && P->lastG2 == G2 && P->lastws == ws && P->lastld1 == ld1 &&
+                    P->lastld2 == ld2 && out_eq(P->lastout, *out);
+  if (!same) {
+    pr.out = *out;
+    P->sides[0].G = G1; P->sides[0].ldg = ld1;
+    P->sides[1].G = G2; P->sides[1].ldg = ld2;
+    P->bound = false;
+    const int rc = build(P, ws);
+    if (rc) return rc;
+    ++P->gen;
+    P->bound = true;
+    P->lastG1 = G1; P->lastG2 = G2; P->lastws = ws; P->lastld1 = ld1; P->lastld2 = ld2;
+    P->lastout = *out;
+  }
+  // the job tables live in the scratch too: copied in again whenever another
+  // plan or another binding of this one ran there last (ordered on `stream`)
+  if (sl.owner != P->id || sl.gen != P->gen) {
+    if (hipMemcpyAsync((char*)ws + P->off_jobs, P->host.data(), P->host.size(), hipMemcpyHostToDevice, st) !=
+        hipSuccess)
+      return RGSVD_EHIP;
+    sl.owner = P->id;
+    sl.gen = P->gen;
+  }
+  const bool prof = P->prof;
+  P->prof = false;   // per-stage events are not created here
+  const int rc = enqueue(P, ws, st);
+  P->prof = prof;
+  return rc;
+}
+
 void rgsvd_destroy(rgsvd_plan_t P) {
   if (!P) return;
   if (P->ev_pending) hipEventSynchronize(P->ev);
@@ -1439,6 +1520,7 @@ int rgsvd_batch_plan(const rgsvd_desc* shapes, int32_t npairs, rgsvd_plan_t* pla
   rgsvd_plan_s* P = new (std::nothrow) rgsvd_plan_s();
   if (!P) return RGSVD_ENOMEM;
   P->d = shapes[0];
+  P->id = next_plan_id();
   P->batched = true;
   P->prec = shapes[0].precision == RGSVD_PREC_FP64 ? P64 : (shapes[0].precision == RGSVD_PREC_FP32 ? P32 : PBF);
   P->gdt = shapes[0].in_dtype;

@@ -10,7 +10,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "librgsvd.so")
 
-OK, EINVAL, ENOTGMP, EHIP, ENOMEM, EWORKSPACE, ENOMODEL, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6, -7
+OK, EINVAL, ENOTGMP, EHIP, ENOMEM, EWORKSPACE, ENOMODEL, EUNSUPPORTED, ETOOBIG = 0, -1, -2, -3, -4, -5, -6, -7, -8
+STATIC_SCRATCH_BYTES = 64 << 20
 F64, F32 = 0, 1
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
 SIZING = {"fixed": 0, "adaptive": 1, "learned": 2}
@@ -62,6 +63,8 @@ EXPORTS = {
                                   ctypes.POINTER(ctypes.c_size_t)]),
     "rgsvd_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                  ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Out)]),
+    "rgsvd_run_static": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                        ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(Out)]),
     "rgsvd_plan_sizes": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64),
                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "rgsvd_destroy": (None, [ctypes.c_void_p]),
@@ -208,6 +211,18 @@ def run(plan, G1, G2, o):
     out = out_struct(o, m, p, n)
     check(lib().rgsvd_run(plan.h, _ptr(G1), G1.stride(0), _ptr(G2), G2.stride(0), plan.ws_ptr,
                           _stream(G1.device), ctypes.byref(out)), "rgsvd_run")
+    return o
+
+
+def run_static(plan, G1, G2, o):
+    """Enqueue one run of `plan` in the library's static device scratch (no
+    workspace, nothing allocated by the call); returns o."""
+    m, n = G1.shape
+    p = G2.shape[0]
+    assert G1.stride(1) == 1 and G2.stride(1) == 1, "rows of G must be contiguous"
+    out = out_struct(o, m, p, n)
+    check(lib().rgsvd_run_static(plan.h, _ptr(G1), G1.stride(0), _ptr(G2), G2.stride(0), _stream(G1.device),
+                                 ctypes.byref(out)), "rgsvd_run_static")
     return o
 
 

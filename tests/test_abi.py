@@ -89,3 +89,20 @@ def test_batch_plan_requires_one_power_count():
     arr = (R.Desc * 2)(d0, d1)
     assert R.lib().rgsvd_batch_plan(arr, 2, ctypes.byref(h), ctypes.byref(ws)) == 0
     R.lib().rgsvd_destroy(h)
+
+
+def test_static_run_refuses_plans_above_the_scratch():
+    """rgsvd_run_static checks the plan's workspace against the static
+    scratch before touching the device."""
+    from paper_2404_09459_amd import rgsvd as R
+    desc = R.make_desc(20000, 15000, 5000, 100, 10, 2, 2, R.F32, "mixed")
+    h = ctypes.c_void_p()
+    ws = ctypes.c_size_t()
+    assert R.lib().rgsvd_plan(ctypes.byref(desc), ctypes.byref(h), ctypes.byref(ws)) == 0
+    assert ws.value > R.STATIC_SCRATCH_BYTES
+    out = R.Out()
+    rc = R.lib().rgsvd_run_static(h, ctypes.c_void_p(4096), 5000, ctypes.c_void_p(8192), 5000, None,
+                                  ctypes.byref(out))
+    assert rc == R.ETOOBIG
+    assert "static scratch" in R.lib().rgsvd_strerror(R.ETOOBIG).decode()
+    R.lib().rgsvd_destroy(h)
