@@ -38,6 +38,53 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Factor of one 16 x 16 diagonal block A = R^T R, run by one wave.  On entry
+// lane j < 16 holds column j of the block's upper part (d[i] = A[i][j] for
+// i <= j, zero elsewhere; lanes 16..63 zeros); on exit d holds column j of R
+// and x column j of R^{-1}.  d0(k) is the original diagonal entry of the
+// block's row k, for the pivot tests.  trunc: a pivot below CHOL_TRUNC_REL of
+// it gives a zero row k of R and of R^{-1} (the row eliminates nothing).
+// Returns whether a pivot failed (not finite, or not above both rel d0(k) and
+// floor), which cannot happen for a dropped row.
+template <typename D0>
+__device__ __forceinline__ bool factor_diag16(double (&d)[16], double (&x)[16], bool trunc, double rel, double floor,
+                                              D0 d0) {
+  const int j = threadIdx.x & 63;
+  double myinv = 0.0;    // 1 / R_jj of this lane's column (0 for a dropped row)
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const double piv = readlane_f64(d[k], k);
+    const double dk0 = d0(k);
+    if (trunc && isfinite(piv) && !(piv > CHOL_TRUNC_REL * dk0 && piv > 0.0)) {
+      if (j >= k) d[k] = 0.0;
+      continue;
+    }
+    if (!(piv > rel * dk0) || !(piv > floor) || !(piv > 0.0) || !isfinite(piv)) bad = true;
+    const double r = sqrt(piv), ri = 1.0 / r;
+    if (j == k) myinv = ri;
+    if (j >= k) d[k] = (j == k) ? r : d[k] * ri;
+#pragma unroll
+    for (int i = k + 1; i < 16; ++i) {
+      const double rki = readlane_f64(d[k], i);
+      if (j >= i) d[i] -= rki * d[k];
+    }
+  }
+  // column j of R^{-1}: x_j = 1 / R_jj, x_i = -(sum_{m=i+1..j} R_im x_m) / R_ii,
+  // R_im and 1 / R_ii read from the lanes that hold them (LDS loads inside this
+  // dependent chain cost twice as much)
+#pragma unroll
+  for (int i = 15; i >= 0; --i) {
+    double acc = 0.0;
+#pragma unroll
+    for (int m = i + 1; m < 16; ++m)
+      if (m <= j) acc += readlane_f64(d[i], m) * x[m];
+    const double rinv = readlane_f64(myinv, i);
+    x[i] = (i < j) ? -acc * rinv : (i == j ? rinv : 0.0);
+  }
+  return bad;
+}
+
 // Cholesky A = R^T R of an N x N Gram (N <= CB_MAXN) and X = R^{-T}, the
 // inverse of the lower factor L = R^T, right-looking in 16 x 16 blocks.
 //
@@ -134,41 +181,10 @@ __global__ __launch_bounds__(64 * CB_W) void k_chol(const CholJob* __restrict__ 
       if (wave == 0) {
         // lane j < 16 holds column j of the block's upper part
         const int j = ln;
-        double d[16];
-        double myinv = 0.0;    // 1 / R_jj of this lane's column (0 for a dropped row)
+        double d[16], x[16];
 #pragma unroll
         for (int i = 0; i < 16; ++i) d[i] = (j < 16 && i <= j) ? Dk[i * 16 + j] : 0.0;
-        bool bad = false;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-          const double piv = readlane_f64(d[k], k);
-          const double dk0 = d0[o + k];
-          if (J.trunc && isfinite(piv) && !(piv > CHOL_TRUNC_REL * dk0 && piv > 0.0)) {
-            if (j >= k) d[k] = 0.0;          // zero row k: it eliminates nothing
-            continue;
-          }
-          if (!(piv > 1e-15 * dk0) || !(piv > 0.0) || !isfinite(piv)) bad = true;
-          const double r = sqrt(piv), ri = 1.0 / r;
-          if (j == k) myinv = ri;
-          if (j >= k) d[k] = (j == k) ? r : d[k] * ri;
-#pragma unroll
-          for (int i = k + 1; i < 16; ++i) {
-            const double rki = readlane_f64(d[k], i);
-            if (j >= i) d[i] -= rki * d[k];
-          }
-        }
-        // column j of R_kk^{-1}: x_j = 1 / R_jj, x_i = -(sum_{m=i+1..j} R_im x_m) / R_ii,
-        // R_im and 1 / R_ii read from the lanes that hold them
-        double x[16];
-#pragma unroll
-        for (int i = 15; i >= 0; --i) {
-          double acc = 0.0;
-#pragma unroll
-          for (int m = i + 1; m < 16; ++m)
-            if (m <= j) acc += readlane_f64(d[i], m) * x[m];
-          const double rinv = readlane_f64(myinv, i);
-          x[i] = (i < j) ? -acc * rinv : (i == j ? rinv : 0.0);
-        }
+        const bool bad = factor_diag16(d, x, J.trunc != 0, 1e-15, 0.0, [&](int k) { return d0[o + k]; });
         // row j of X_kk = R_kk^{-T} is column j of R_kk^{-1}
         if (j < 16) {
 #pragma unroll
@@ -602,6 +618,114 @@ __device__ int pivoted_cholesky(double* S, int64_t ld, int K, double* F, double*
   return rank;
 }
 
+// Unpivoted Cholesky S = R^T R of a K x K SPD matrix in one workgroup,
+// right-looking in 16 x 16 blocks on FP64 MFMA with the matrix left in
+// global memory (L2): S is row-major (ld), both triangles present; the blocks
+// on and above the diagonal are overwritten.  Column k of F (K x K,
+// column-major, ld K) receives row k of R, so F F^T = S.  The order is padded
+// to a multiple of 16 with the identity (virtually: the padding is never
+// stored).  A pivot must exceed CHOL_TRUNC_REL (1e-10) of its row's original
+// diagonal and 1e-12 of the largest diagonal, far above the rounding errors
+// of the Schur complements (a few u max diag): then the multipliers are
+// accurate and no entry of R can grow.  Otherwise (S singular or nearly so,
+// where rounding can leave small positive pivots that amplify errors) it
+// restores S from its lower triangle and d0 and returns false, and the
+// caller falls back to the pivoted form, which stops at the numerical rank.  *trace gets
+// the trace of S.  Scratch: d0 (16 ceil(K/16) doubles), panel (16 x ldp,
+// ldp >= 16 ceil(K/16)), Xk (256 doubles), all shared; bad_s shared.
+__device__ __noinline__ bool chol_unpivoted(double* S, int64_t ld, int K, double* F, double* d0, double* panel, int ldp,
+                               double* Xk, int* bad_s, double* trace) {
+  const int tid = threadIdx.x, wave = tid >> 6, ln = tid & 63, g = ln >> 4, c16 = ln & 15;
+  constexpr int NW = 16;
+  const int nb = (K + 15) >> 4;
+  auto at = [&](int r, int c) -> double {   // S with the identity padding
+    return (r < K && c < K) ? S[(int64_t)r * ld + c] : (r == c ? 1.0 : 0.0);
+  };
+  for (int e = tid; e < K * K; e += 64 * NW) F[e] = 0.0;
+  for (int i = tid; i < 16 * nb; i += 64 * NW) d0[i] = at(i, i);
+  if (tid == 0) *bad_s = 0;
+  __syncthreads();
+  __shared__ double dmax_s;
+  if (tid < 64) {
+    double tr = 0.0, mx = 0.0;
+    for (int i = tid; i < K; i += 64) { tr += d0[i]; mx = fmax(mx, d0[i]); }
+    tr = wave_sum(tr);
+    for (int o2 = 32; o2 > 0; o2 >>= 1) mx = fmax(mx, __shfl_xor(mx, o2, 64));
+    if (tid == 0) { *trace = tr; dmax_s = mx; }
+  }
+  __syncthreads();
+  const double floor = 1e-12 * dmax_s;
+  for (int kb = 0; kb < nb; ++kb) {
+    const int o = 16 * kb;
+    if (wave == 0) {
+      const int j = ln;
+      double d[16], x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) d[i] = (j < 16 && i <= j) ? at(o + i, o + j) : 0.0;
+      const bool bad = factor_diag16(d, x, false, CHOL_TRUNC_REL, floor, [&](int k) { return d0[o + k]; });
+      if (j < 16) {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          Xk[j * 16 + i] = i <= j ? x[i] : 0.0;          // X_kk = R_kk^{-T}, row j
+          if (i <= j) {
+            panel[i * ldp + o + j] = d[i];                 // R[o + i][o + j]
+            if (o + j < K) F[(int64_t)(o + i) * K + o + j] = d[i];
+          }
+        }
+      }
+      if (bad && ln == 0) *bad_s = 1;
+    }
+    __syncthreads();
+    if (*bad_s) {
+      for (int e = tid; e < K * K; e += 64 * NW) {
+        const int r = e / K, c = e - r * K;
+        if (c > r) S[(int64_t)r * ld + c] = S[(int64_t)c * ld + r];
+        else if (c == r) S[(int64_t)r * ld + c] = d0[r];
+      }
+      __syncthreads();
+      return false;
+    }
+    // panel row kb of R: R[kb][jb] = X_kk A[kb][jb]
+    for (int jb = kb + 1 + wave; jb < nb; jb += NW) {
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) acc = mma64(Xk[c16 * 16 + 4 * kk + g], at(o + 4 * kk + g, 16 * jb + c16), acc);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 4 * q + g, c = 16 * jb + c16;
+        panel[r * ldp + c] = acc[q];
+        if (o + r < K && c < K) F[(int64_t)(o + r) * K + c] = acc[q];
+      }
+    }
+    __syncthreads();
+    // trailing update A[ib][jb] -= R[kb][ib]^T R[kb][jb], kb < ib <= jb
+    const int rem = nb - kb - 1;
+    for (int tb = wave; tb < rem * (rem + 1) / 2; tb += NW) {
+      int ib = 0, tt = tb;
+      while (tt >= rem - ib) { tt -= rem - ib; ++ib; }
+      const int jb = kb + 1 + ib + tt;
+      ib += kb + 1;
+      d4 acc;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = at(16 * ib + 4 * q + g, 16 * jb + c16);
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int m = 4 * kk + g;
+        acc = mma64(-panel[m * ldp + 16 * ib + c16], panel[m * ldp + 16 * jb + c16], acc);
+      }
+      // (the strictly lower triangle, diagonal blocks included, keeps the
+      // original S for the restore)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = 16 * ib + 4 * q + g, c = 16 * jb + c16;
+        if (r < K && c < K && r <= c) S[(int64_t)r * ld + c] = acc[q];
+      }
+    }
+    __syncthreads();
+  }
+  return true;
+}
+
 struct SmallShared {
   double keys[SMALL_MAXN];
   double diag[SMALL_MAXN];
@@ -709,7 +833,14 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
     double trM;
     bool more = true;
     if (stage <= 1) {
-      rank = pivoted_cholesky(J.M, J.ldm, N, F, sh.diag, sh.act, lds, &sh.piv_j, &sh.piv_d, 0.0, &sh.trace);
+      // unpivoted blocked Cholesky (the factor's Jacobi needs as many sweeps
+      // as on the greedily pivoted one); the pivoted form, which stops at the
+      // numerical rank, when a pivot fails
+      const int ldp = 16 * ((N + 15) / 16) + 4;
+      if (chol_unpivoted(J.M, J.ldm, N, F, sh.diag, lds, ldp, lds + 16 * ldp, &sh.scratch[5], &sh.trace))
+        rank = N;
+      else
+        rank = pivoted_cholesky(J.M, J.ldm, N, F, sh.diag, sh.act, lds, &sh.piv_j, &sh.piv_d, 0.0, &sh.trace);
       trM = sh.trace;
       if (stage == 1) {
         if (tid == 0) { S->rank = rank; S->trM = trM; bj_start(S, rank, N, t < rank ? t : rank); }
@@ -758,7 +889,17 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
       Hg[(int64_t)j * t + i] = v;
     });
     __syncthreads();
-    rh = pivoted_cholesky(Hg, t, t, FH, sh.diag, sh.act, lds, &sh.piv_j, &sh.piv_d, 1e-12, &sh.trace);
+    // H + 1e-12 I (the shift leaves the eigenvectors and keeps the factor
+    // positive definite when L1 has fewer rows than t or some alpha is 0)
+    for (int i = tid; i < t; i += 1024) Hg[(int64_t)i * t + i] += 1e-12;
+    __syncthreads();
+    {
+      const int ldp = 16 * ((t + 15) / 16) + 4;
+      if (chol_unpivoted(Hg, t, t, FH, sh.diag, lds, ldp, lds + 16 * ldp, &sh.scratch[5], &sh.trace))
+        rh = t;
+      else
+        rh = pivoted_cholesky(Hg, t, t, FH, sh.diag, sh.act, lds, &sh.piv_j, &sh.piv_d, 0.0, &sh.trace);
+    }
     if (J.bjh) {
       if (tid == 0) { S->sw1 = sw1; bj_start(S, rh, t, 0); }
       return;
