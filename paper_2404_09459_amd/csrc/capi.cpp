@@ -47,8 +47,8 @@ inline int ct_of(int L) {
   return 16;
 }
 
-enum Kind { K_ZERO, K_COPY, K_GEN, K_NN, K_AB, K_GRAM, K_RED, K_CHOL, K_SMALL, K_SIGN, K_SCALE, K_GW, K_GTQ,
-            K_PACK, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP, K_BJINIT, K_BJROUND, K_GW4, K_ZEROG };
+enum Kind { K_ZERO, K_COPY, K_GEN, K_AB, K_GRAM, K_RED, K_CHOL, K_SMALL, K_SIGN, K_SCALE, K_GW, K_GTQ,
+            K_PACK, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP, K_BJINIT, K_BJROUND, K_GW4, K_ZEROG, K_NN };
 
 enum Tag { T_ZERO, T_COPY, T_GEN, T_NN, T_TN, T_RED, T_GRAM, T_CHOL, T_SX, T_SMALL, T_RECOVER, T_SIGN,
            T_MGRAM, T_BJAC, T_NTAGS };
@@ -60,13 +60,13 @@ struct Stage {
   int nj = 0, tiles = 0;
   int prec = 0, gdt = 0, rt = 1, ct = 1, js = 1;
   int ta = 0, tb = 0, td = 0;
-  bool sym = false, f64 = false;
+  bool sym = false, f64 = false, split = false;
   size_t zoff = 0, zbytes = 0;  // K_ZERO: workspace range
   int sweep = 0, round = 0;     // K_BJINIT, K_BJROUND
 };
 
 struct CopyJob { const uint32_t* src; uint32_t* dst; int64_t nwords; };
-struct PackJobH { const float* src; void* dst; int64_t ld; int32_t L, nst, bf16, pad; };
+struct PackJobH { const float* src; void* dst; int64_t ld; int32_t L, nst, bf16, pieces; };
 
 struct SideLay {
   int m = 0, n = 0, l = 0, L = 0, which = 0, pair = 0;
@@ -215,8 +215,9 @@ int layout(rgsvd_plan_s* P) {
       s.Yt = take((size_t)s.L * s.ldy * wsz);
       s.Wt = take((size_t)s.L * s.ldw * wsz);
       if (prec == PBF) {
-        s.Yt16 = take((size_t)s.L * s.ldy * 2);
-        s.Wt16 = take((size_t)s.L * s.ldw * 2);
+        // three BF16 pieces each: the FP32-accurate split passes use them all
+        s.Yt16 = take((size_t)3 * s.L * s.ldy * 2);
+        s.Wt16 = take((size_t)3 * s.L * s.ldw * 2);
       }
       if (prec != P64) {
         s.Yp32 = take((size_t)s.L * s.ldy * 4);
@@ -457,7 +458,7 @@ int build(rgsvd_plan_s* P, void* ws) {
   auto pack_dst = [&](const SideLay& s, bool ymat, int p) -> size_t {
     return p == PBF ? (ymat ? s.Yt16 : s.Wt16) : (ymat ? s.Yp32 : s.Wp32);
   };
-  auto add_pack = [&](bool ymat, int p) {
+  auto add_pack = [&](bool ymat, int p, int pieces = 1) {
     std::vector<PackJobH> j; std::vector<int> tl;
     const int ks = p == PBF ? 32 : 16;
     for (auto& s : S) {
@@ -466,6 +467,7 @@ int build(rgsvd_plan_s* P, void* ws) {
       c.src = (const float*)WS(ws, ymat ? s.Yt : s.Wt);
       c.dst = WS(ws, pack_dst(s, ymat, p));
       c.ld = ymat ? s.ldy : s.ldw; c.L = s.L; c.nst = (len + ks - 1) / ks; c.bf16 = p == PBF;
+      c.pieces = pieces;
       j.push_back(c);
       tl.push_back((int)(((int64_t)c.nst * (s.L / 16) * 64 + 255) / 256));
     }
@@ -473,6 +475,28 @@ int build(rgsvd_plan_s* P, void* ws) {
   };
 
   auto add_nn = [&](int p) {
+    if (mixed && gt == 1) {
+      // mixed path over FP32 G: 8-wave workgroups sharing the packed W in
+      // LDS; the BF16 passes round G and W to BF16, the last power pass
+      // (FP32 in the method) runs the FP32-accurate three-piece split
+      const bool split = p == P32;
+      add_pack(false, PBF, split ? 3 : 1);
+      // two 16-row tiles per wave reuse each W fragment twice; the split
+      // pass with 16 column tiles keeps one (its registers are full)
+      const int rt = (split && ctL >= 16) ? 1 : 2;
+      const int wrows = 16 * rt * 8;
+      std::vector<NnJob> j; std::vector<int> tl;
+      for (auto& s : S) {
+        NnJob x{};
+        x.G = s.G; x.Wt = WS(ws, s.Wt16); x.Yt = WS(ws, s.Yt);
+        x.ldg = s.ldg; x.ldw = s.ldw; x.ldy = s.ldy; x.m = s.m; x.n = s.n; x.L = s.L;
+        j.push_back(x);
+        tl.push_back((s.m + wrows - 1) / wrows);
+      }
+      Stage& st = B.add(K_NN, j, tl);
+      st.split = split; st.rt = rt; st.ct = ctL; st.tag = T_NN;
+      return;
+    }
     if (p != P64) add_pack(false, p);
     if (p == P32 && gt == 1) {
       // FP32 pass over FP32 G (MFMA-bound): 4-wave workgroups of 64 rows
@@ -1030,6 +1054,7 @@ int enqueue(rgsvd_plan_s* P, void* ws, hipStream_t st) {
       case K_SCALE: launch_scale((const SignJob*)j, pre, s.nj, s.tiles, st); break;
       case K_GW: launch_gw(s.prec, s.gdt, s.rt, s.ct, (const NnJob*)j, pre, s.nj, s.tiles, st); break;
       case K_GW4: launch_gw4(s.prec, s.ct, (const NnJob*)j, pre, s.nj, s.tiles, st); break;
+      case K_NN: launch_nn(s.split, s.rt, s.ct, (const NnJob*)j, pre, s.nj, s.tiles, st); break;
       case K_GTQ: launch_gtq(s.prec, s.gdt, s.ct, s.js, (const AbJob*)j, pre, s.nj, s.tiles, st); break;
       case K_PACK: launch_pack(j, pre, s.nj, s.tiles, st); break;
       case K_SUMSQ: hipLaunchKernelGGL(k_sumsq, dim3(s.tiles), dim3(256), 0, st, (const SumsqJob*)j, pre, s.nj); break;
@@ -1059,6 +1084,34 @@ int upload(rgsvd_plan_s* P, void* ws, hipStream_t st) {
     return RGSVD_EHIP;
   if (hipEventRecord(P->ev, st) != hipSuccess) return RGSVD_EHIP;
   P->ev_pending = true;
+  return RGSVD_OK;
+}
+
+// Single-pair runs replay their launch sequence as a HIP graph once a
+// binding has run eagerly (a few hundred short launches, mostly the block
+// Jacobi rounds, otherwise wait on the host's launch rate).  The graph holds
+// the bound pointers, so every rebuild of the job tables drops it.
+void drop_graph(rgsvd_plan_s* P) {
+  if (P->gexec) { hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
+}
+
+int capture_graph(rgsvd_plan_s* P, void* ws) {
+  drop_graph(P);
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return RGSVD_EHIP;
+  hipGraph_t g = nullptr;
+  const bool prof = P->prof;
+  P->prof = false;
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    const int rc = enqueue(P, ws, cs);
+    ok = hipStreamEndCapture(cs, &g) == hipSuccess && g && rc == RGSVD_OK;
+  }
+  P->prof = prof;
+  if (ok) ok = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0) == hipSuccess;
+  if (g) hipGraphDestroy(g);
+  hipStreamDestroy(cs);
+  if (!ok) { P->gexec = nullptr; return RGSVD_EHIP; }
   return RGSVD_OK;
 }
 
@@ -1297,6 +1350,7 @@ int autotune_plan(rgsvd_plan_s* P, void* ws, hipStream_t st, int reps, int32_t* 
   P->tune_rt = best.rt; P->tune_js = best.js; P->tune_chunk = best.chunk;
   tune_cache()[shape_key(P)] = best;
   P->bound = false;
+  if (!P->batched) drop_graph(P);
   if (choice) { choice[0] = best.rt; choice[1] = best.js; choice[2] = best.chunk; }
   if (best_ms) *best_ms = best.ms;
   return RGSVD_OK;
@@ -1405,6 +1459,7 @@ int rgsvd_run(rgsvd_plan_t P, const void* G1, int64_t ld1, const void* G2, int64
   bool same = P->bound && P->lastG1 == G1 && P->lastG2 == G2 && P->lastws == workspace &&
               P->lastld1 == ld1 && P->lastld2 == ld2 && out_eq(P->lastout, *out);
   if (!same) {
+    drop_graph(P);
     pr.out = *out;
     P->sides[0].G = G1; P->sides[0].ldg = ld1;
     P->sides[1].G = G2; P->sides[1].ldg = ld2;
@@ -1415,8 +1470,15 @@ int rgsvd_run(rgsvd_plan_t P, const void* G1, int64_t ld1, const void* G2, int64
     P->bound = true;
     P->lastG1 = G1; P->lastG2 = G2; P->lastws = workspace; P->lastld1 = ld1; P->lastld2 = ld2;
     P->lastout = *out;
+    return enqueue(P, workspace, st);   // the first run of a binding is eager
   }
-  return enqueue(P, workspace, st);
+  // per-stage profiling needs its events between launches: eager
+  if (P->prof) return enqueue(P, workspace, st);
+  if (!P->gexec) {
+    const int rc = capture_graph(P, workspace);
+    if (rc) return rc;
+  }
+  return hipGraphLaunch(P->gexec, st) == hipSuccess ? RGSVD_OK : RGSVD_EHIP;
 }
 
 int rgsvd_run_static(rgsvd_plan_t P, const void* G1, int64_t ld1, const void* G2, int64_t ld2, void* stream,
@@ -1442,6 +1504,7 @@ int rgsvd_run_static(rgsvd_plan_t P, const void* G1, int64_t ld1, const void* G2
   const bool same = P->bound && P->lastG1 == G1 && P->lastG2 == G2 && P->lastws == ws && P->lastld1 == ld1 &&
                     P->lastld2 == ld2 && out_eq(P->lastout, *out);
   if (!same) {
+    drop_graph(P);
     pr.out = *out;
     P->sides[0].G = G1; P->sides[0].ldg = ld1;
     P->sides[1].G = G2; P->sides[1].ldg = ld2;

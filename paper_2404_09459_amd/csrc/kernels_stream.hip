@@ -330,6 +330,165 @@ __global__ __launch_bounds__(256) void k_gw4(const NnJob* __restrict__ jobs, con
   }
 }
 
+// ------------------------------------------------------------------ k_nn --
+// Y = G W for FP32 G on BF16 MFMA, with the packed W shared by a workgroup
+// through LDS.  NW waves; wave w streams the 16 RT rows row0 + 16 RT w ...
+// of G through an NB-deep register pipeline, and the packed W of a k-step
+// (NPW pieces x ctn tiles x 64 lanes x 16 bytes) is staged once per
+// workgroup into LDS (two buffers, one barrier per step), where every wave
+// reads the fragments of its RT row tiles.  W then crosses L2 once per
+// 16 RT NW rows of G instead of once per wave tile.
+//
+// SPLIT = false: G is rounded to BF16 (RNE) and W is one BF16 piece.
+// SPLIT = true: an FP32-accurate product.  G and W are each split into three
+// BF16 pieces, x = x1 + x2 + x3 with x1 = bf16(x), x2 = bf16(x - x1),
+// x3 = bf16(x - x1 - x2) (both differences exact in FP32), and the six
+// products g_i w_j with i + j <= 4 are accumulated in FP32; the three
+// dropped ones are below 2^-24 of the product.
+constexpr int NN_NW = 8;
+
+template <bool SPLIT> __device__ __forceinline__ void split_bf16(const float (&x)[8], bf8 (&p)[SPLIT ? 3 : 1]) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 h = (__bf16)x[e];
+    p[0][e] = h;
+    if constexpr (SPLIT) {
+      const float r1 = x[e] - (float)h;
+      const __bf16 m = (__bf16)r1;
+      p[1][e] = m;
+      p[2][e] = (__bf16)(r1 - (float)m);
+    }
+  }
+}
+
+template <bool SPLIT, int CT, int RT>
+__global__ __launch_bounds__(64 * NN_NW) void k_nn(const NnJob* __restrict__ jobs, const int* __restrict__ pre,
+                                                   int nj) {
+  constexpr int NPW = SPLIT ? 3 : 1;         // BF16 pieces of W (and of G)
+  constexpr int KL = 8, KS = 32, NB = 3;
+  constexpr int STR = NPW * CT * 64;          // 16-byte chunks per LDS buffer
+  constexpr int NT = 64 * NN_NW;
+  constexpr int CH = (STR + NT - 1) / NT;     // chunks a thread stages per step
+  extern __shared__ u4v wl[];                 // 2 x STR
+  const int jb = find_side(pre, nj, blockIdx.x);
+  const NnJob J = jobs[jb];
+  const int tile = blockIdx.x - pre[jb];
+  const int tid = threadIdx.x, wave = tid >> 6, ln = tid & 63, g = ln >> 4, li = ln & 15;
+  const int row0 = tile * (16 * RT * NN_NW) + wave * 16 * RT;
+  const int ctn = J.L >> 4;
+  const int nchw = ctn * 64;                  // chunks of one piece per step
+  const int nsteps = (J.n + KS - 1) / KS;
+  const __amdgpu_buffer_rsrc_t rs =
+      make_rsrc((const char*)J.G + (int64_t)row0 * J.ldg * 4, (int64_t)(J.m - row0) * J.ldg * 4);
+  int roff[RT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a) roff[a] = (a * 16 + li) * (int)J.ldg * 4;
+  const u4v* wsrc = (const u4v*)J.Wt;         // piece p, step st: chunks (p nsteps + st) nchw ...
+
+  f4 acc[RT][CT];
+#pragma unroll
+  for (int a = 0; a < RT; ++a)
+#pragma unroll
+    for (int b = 0; b < CT; ++b) acc[a][b] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  float ga[NB][RT][KL];
+  u4v wt[CH];
+  auto gl = [&](int buf, int st) {
+#pragma unroll
+    for (int a = 0; a < RT; ++a) gload<float, float, KL>(ga[buf][a], rs, roff[a] + (st * KS + g * KL) * 4);
+  };
+  auto wfetch = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int c = tid + NT * i;
+      if (c < NPW * nchw) {
+        const int pc = c / nchw, w = c - pc * nchw;
+        wt[i] = *(gptr<u4v>)(wsrc + ((int64_t)pc * nsteps + st) * nchw + w);
+      }
+    }
+  };
+  auto wstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int c = tid + NT * i;
+      if (c < NPW * nchw) {
+        const int pc = c / nchw, w = c - pc * nchw;
+        wl[buf * STR + pc * CT * 64 + w] = wt[i];
+      }
+    }
+  };
+#pragma unroll
+  for (int b = 0; b < NB - 1; ++b)
+    if (b < nsteps) gl(b, b);
+  // column tiles past ctn read zeros, so the MFMAs below need no branch and
+  // independent tiles interleave
+  for (int c = tid; c < 2 * STR; c += NT)
+    if ((c % (CT * 64)) >= nchw) wl[c] = u4v{0, 0, 0, 0};
+  if (nsteps > 0) { wfetch(0); wstore(0); }
+  if (nsteps > 1) wfetch(1);
+  __syncthreads();
+#pragma unroll 1
+  for (int st0 = 0; st0 < nsteps; st0 += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int st = st0 + u;
+      if (st >= nsteps) break;
+      if (st + NB - 1 < nsteps) gl((u + NB - 1) % NB, st + NB - 1);
+      const int k = st * KS + g * KL;
+      const bool last = (st + 1) * KS > J.n;      // wave-uniform
+      bf8 gp[RT][NPW];
+#pragma unroll
+      for (int a = 0; a < RT; ++a) {
+        float v[KL];
+#pragma unroll
+        for (int e = 0; e < KL; ++e) v[e] = (last && k + e >= J.n) ? 0.0f : ga[u][a][e];   // padding between rows
+        split_bf16<SPLIT>(v, gp[a]);
+      }
+      const u4v* wb = wl + (st & 1) * STR;
+      // no branch over the tiles (those past ctn read zeros), so the
+      // dependent products of one tile interleave with the next tile's
+#pragma unroll
+      for (int b = 0; b < CT; ++b) {
+        bf8 wp[NPW];
+#pragma unroll
+        for (int pc = 0; pc < NPW; ++pc) wp[pc] = __builtin_bit_cast(bf8, wb[pc * CT * 64 + b * 64 + ln]);
+#pragma unroll
+        for (int a = 0; a < RT; ++a) {
+          if constexpr (SPLIT) {
+            // smallest terms first
+            acc[a][b] = mmabf(gp[a][2], wp[0], acc[a][b]);
+            acc[a][b] = mmabf(gp[a][1], wp[1], acc[a][b]);
+            acc[a][b] = mmabf(gp[a][0], wp[2], acc[a][b]);
+            acc[a][b] = mmabf(gp[a][1], wp[0], acc[a][b]);
+            acc[a][b] = mmabf(gp[a][0], wp[1], acc[a][b]);
+          }
+          acc[a][b] = mmabf(gp[a][0], wp[0], acc[a][b]);
+        }
+      }
+      if (st + 1 < nsteps) wstore((st + 1) & 1);   // W(st + 1), fetched one step ago
+      if (st + 2 < nsteps) wfetch(st + 2);
+      __syncthreads();
+    }
+  }
+  // lane holds Y[row0 + 16 a + 4 g + ii][16 b + li]: four consecutive rows
+  float* Yt = (float*)J.Yt;
+#pragma unroll
+  for (int b = 0; b < CT; ++b) {
+    if (b >= ctn) continue;
+    float* dst = Yt + (int64_t)(b * 16 + li) * J.ldy;
+#pragma unroll
+    for (int a = 0; a < RT; ++a) {
+      const int r = row0 + a * 16 + 4 * g;
+      if (r + 3 < J.m) {
+        *(f4*)(dst + r) = acc[a][b];
+      } else {
+#pragma unroll
+        for (int ii = 0; ii < 4; ++ii) if (r + ii < J.m) dst[r + ii] = acc[a][b][ii];
+      }
+    }
+  }
+}
+
 // ----------------------------------------------------------------- k_gtq --
 // Job (AbJob): D (rows x J, partial, ldd) = A (rows x K) B (K x J): A = Q^T
 // columns of this row chunk in the compute type (lda, zero beyond m), B = the
@@ -433,7 +592,7 @@ __global__ __launch_bounds__(64) void k_gtq(const AbJob* __restrict__ jobs, cons
 // FP32 (KL = 4) for nst k-steps of KS = 4 KL columns; nst * KS <= ld.  One
 // thread per fragment piece (KL elements); consecutive threads write
 // consecutive pieces.
-struct PackJob { const float* src; void* dst; int64_t ld; int32_t L, nst, bf16, pad; };
+struct PackJob { const float* src; void* dst; int64_t ld; int32_t L, nst, bf16, pieces; };
 
 __global__ __launch_bounds__(256) void k_pack(const PackJob* __restrict__ jobs, const int* __restrict__ pre,
                                               int nj) {
@@ -451,10 +610,18 @@ __global__ __launch_bounds__(256) void k_pack(const PackJob* __restrict__ jobs, 
   const float* src = J.src + (int64_t)c * J.ld + k;
   if (J.bf16) {
     const f4 v0 = *(const f4*)src, v1 = *(const f4*)(src + 4);
-    __bf16 o[8];
+    float x[8];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) { o[e] = (__bf16)v0[e]; o[4 + e] = (__bf16)v1[e]; }
-    __builtin_memcpy((__bf16*)J.dst + piece * 8, o, 16);
+    for (int e = 0; e < 4; ++e) { x[e] = v0[e]; x[4 + e] = v1[e]; }
+    // BF16 pieces x1, x2 = bf16(x - x1), x3 = bf16(x - x1 - x2); piece p of
+    // the operand follows piece p - 1 (nst ctn 64 fragments apart)
+    const int64_t pstride = (int64_t)J.nst * ctn * 64 * 8;
+    for (int p = 0; p < (J.pieces > 1 ? J.pieces : 1); ++p) {
+      __bf16 o[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) { o[e] = (__bf16)x[e]; x[e] -= (float)o[e]; }
+      __builtin_memcpy((__bf16*)J.dst + p * pstride + piece * 8, o, 16);
+    }
   } else {
     *(f4*)((float*)J.dst + piece * 4) = *(const f4*)src;
   }
@@ -480,6 +647,37 @@ static void gw4_ct(int ct, const NnJob* j, const int* pre, int nj, int tiles, hi
     case 4: hipLaunchKernelGGL((k_gw4<P, 4, NB>), dim3(tiles), dim3(256), 0, st, j, pre, nj); break;
     case 8: hipLaunchKernelGGL((k_gw4<P, 8, NB>), dim3(tiles), dim3(256), 0, st, j, pre, nj); break;
     default: hipLaunchKernelGGL((k_gw4<P, 16, NB>), dim3(tiles), dim3(256), 0, st, j, pre, nj); break;
+  }
+}
+
+template <bool SPLIT, int RT>
+static void nn_ct(int ct, const NnJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  const size_t lds = (size_t)2 * (SPLIT ? 3 : 1) * (ct <= 8 ? ct : 16) * 64 * 16;
+  auto go = [&](auto kern) {
+    static bool attr_set = false;   // one flag per instantiation
+    if (!attr_set) {
+      hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(kern, dim3(tiles), dim3(64 * NN_NW), lds, st, j, pre, nj);
+  };
+  switch (ct) {
+    case 1: go(k_nn<SPLIT, 1, RT>); break;
+    case 2: go(k_nn<SPLIT, 2, RT>); break;
+    case 4: go(k_nn<SPLIT, 4, RT>); break;
+    case 8: go(k_nn<SPLIT, 8, RT>); break;
+    default: go(k_nn<SPLIT, 16, RT>); break;
+  }
+}
+
+// rt: 16-row tiles per wave, 2 except for the split pass over 16 column
+// tiles (1: its registers are full)
+void launch_nn(bool split, int rt, int ct, const NnJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  if (split) {
+    if (rt == 2) nn_ct<true, 2>(ct, j, pre, nj, tiles, st);
+    else nn_ct<true, 1>(ct, j, pre, nj, tiles, st);
+  } else {
+    nn_ct<false, 2>(ct, j, pre, nj, tiles, st);
   }
 }
 

@@ -28,6 +28,7 @@ void launch_gw(int prec, int gdt, int rt, int ct, const NnJob* j, const int* pre
                hipStream_t st);
 // FP32 G, FP32 pass, packed W: 4-wave workgroups of 64 rows
 void launch_gw4(int prec, int ct, const NnJob* j, const int* pre, int nj, int tiles, hipStream_t st);
+void launch_nn(bool split, int rt, int ct, const NnJob* j, const int* pre, int nj, int tiles, hipStream_t st);
 void launch_gtq(int prec, int gdt, int ct, int js, const AbJob* j, const int* pre, int nj, int tiles,
                 hipStream_t st);
 void launch_pack(const void* j, const int* pre, int nj, int tiles, hipStream_t st);
