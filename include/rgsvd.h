@@ -99,6 +99,8 @@ extern "C" {
 #define RGSVD_FLAG_BETA_ZERO 0x20  /* some beta < 1e-14: that V column is set to zero */
 #define RGSVD_FLAG_ALPHA_ZERO 0x40 /* sum of alpha^2 is zero                          */
 #define RGSVD_FLAG_NONFINITE 0x80  /* non-finite values reached a Gram matrix         */
+#define RGSVD_FLAG_FALLBACK 0x100  /* learned sizing: the residual judge rejected the
+                                      network's sketch and Algorithm 1 ran instead    */
 
 typedef struct rgsvd_plan_s* rgsvd_plan_t;
 
@@ -115,8 +117,9 @@ typedef struct {
   int32_t mode;             /* RGSVD_TRUNCATED | RGSVD_FULL                            */
   int32_t reserved0;
   uint64_t seed;            /* Omega seed                                              */
-  double tol;               /* adaptive: eps of Algorithm 1 (absolute Frobenius)       */
-  int64_t block;            /* adaptive: b of Algorithm 1 (0 -> 100)                   */
+  double tol;               /* adaptive: eps of Algorithm 1 (absolute Frobenius);
+                               learned: the judge's eps (0: no judge)                   */
+  int64_t block;            /* adaptive, learned fallback: b of Algorithm 1 (0 -> 100) */
   int64_t lmax;             /* adaptive/learned: cap on l_i (0 -> min(m_i, n, 224))    */
 } rgsvd_desc;
 
@@ -153,11 +156,20 @@ int rgsvd_plan(const rgsvd_desc* desc, rgsvd_plan_t* plan, size_t* workspace_byt
  * is compared with tol^2 on the host, so the call synchronises `stream`
  * once after the norms of G and once per block (FP64 precision, truncated
  * mode; blocks rows numerically inside the span of the basis become zero
- * basis vectors).  Learned sizing synchronises once: it evaluates the
- * attached network on the probe features and runs the fixed path at the
- * chosen l (one of k+4, k+8, k+16, k+32, 2k, capped) and q (0..3).  For
- * both, info[1], info[2], info[3] report the l1, l2, q used and sigma_B
- * needs room for the capacities l1 + l2 of rgsvd_plan_sizes.
+ * basis vectors).  Learned sizing sketches at the widest width the network
+ * can pick (min(2k, capacity)); the first 16 columns of that sketch are the
+ * probe (Omega's columns are global, so they are the 16-column sketch), its
+ * features go through the attached network, and the call synchronises once
+ * to read the choice of l (one of k+4, k+8, k+16, k+32, 2k, capped) and q
+ * (0..3); the run then continues on the sketch's first l columns.  The job
+ * tables of every grid point are built and uploaded once per binding of
+ * pointers.  With tol > 0 a residual judge follows: if
+ * ||G_i||_F^2 - ||Q_i^T G_i||_F^2 > tol^2 for either matrix, the pair is
+ * redone by Algorithm 1 (FP64, blocks of `block` columns, tolerance tol;
+ * the plan's buffers are laid out for it) and RGSVD_FLAG_FALLBACK is set;
+ * the judge synchronises once more.  For adaptive and learned sizing
+ * info[1], info[2], info[3] report the l1, l2, q used and sigma_B needs
+ * room for the capacities l1 + l2 of rgsvd_plan_sizes.
  * Errors: RGSVD_EINVAL, RGSVD_EWORKSPACE, RGSVD_ENOMODEL, RGSVD_EHIP. */
 int rgsvd_run(rgsvd_plan_t plan, const void* G1, int64_t ld1, const void* G2, int64_t ld2,
               void* workspace, void* stream, const rgsvd_out* out);
@@ -270,8 +282,11 @@ int rgsvd_set_sizing_model(rgsvd_plan_t plan, const float* params, void* stream)
 /* Probe features of a pair for the sizing network (enqueued on `stream`):
  * the 32 features above, each log10(s_i / s_1) floored at -8 (the FP64 Gram
  * of the probe resolves s_i / s_1 down to about 1e-8), into feat (device,
- * 32 floats).  Uses the plan's shapes, storage type and seed and its
- * workspace (any sizing mode; single-pair plans). */
+ * 32 floats).  The probe is the 16-column sketch in the plan's own sketch
+ * arithmetic (BF16 for mixed plans), the same numbers a learned run of that
+ * precision takes from its sketch's first 16 columns.  Uses the plan's
+ * shapes, storage type and seed and its workspace (any sizing mode;
+ * single-pair plans). */
 int rgsvd_probe_features(rgsvd_plan_t plan, const void* G1, int64_t ld1, const void* G2, int64_t ld2,
                          void* workspace, float* feat, void* stream);
 

@@ -111,8 +111,26 @@ struct rgsvd_plan_s {
   std::vector<SideLay> sides;
   size_t off_jobs = 0, jobs_cap = 0, ws = 0;
   // adaptive sizing: which part build() emits, and the block size
-  enum Part { FIXED, A_INIT, A_BLOCK, TAIL, PROBE } part = FIXED;
+  // FIXED: a whole fixed-size run.  A_INIT, A_BLOCK, TAIL: the steps of
+  // Algorithm 1 (adaptive runs).  L_HEAD: the sketch of a learned run at its
+  // widest grid width, whose first 16 columns give the probe features, and
+  // the network on them (with `probe_only`, the features alone).  L_TAIL: the
+  // rest of a learned run at one grid point (l, q).
+  enum Part { FIXED, A_INIT, A_BLOCK, TAIL, L_HEAD, L_TAIL } part = FIXED;
   bool adaptive = false, learned = false;
+  bool judge = false;        // learned run with tol > 0: residual test, adaptive fallback
+  bool probe_only = false;
+  bool append = false;       // build() adds to the job tables already in `host`
+  int extra_flags = 0;       // ORed into the info template's flag word
+  // learned runs: the head and one tail per grid point, built and uploaded
+  // once per binding
+  std::vector<Stage> lhead;
+  std::vector<std::vector<Stage>> ltails;
+  std::vector<std::pair<int, int>> lgrid;   // (l, q) of each tail
+  int lmaxw = 16;                           // widest grid width
+  bool lbound = false;
+  hipGraphExec_t lhead_exec = nullptr;      // graphs of the head and of the tails
+  std::vector<hipGraphExec_t> ltail_exec;   // (captured when first run)
   size_t off_feat = 0;      // probe features (32 floats), network output (2), activations (128)
   int block = 100;
   double* hscal = nullptr;   // pinned host copy of the per-side scalars
@@ -140,6 +158,7 @@ struct rgsvd_plan_s {
   bool prof = false;
   std::vector<hipEvent_t> pev;
   int prof_count = 0;
+  const std::vector<Stage>* prof_list = nullptr;   // the stage list the events bracket
 };
 
 namespace {
@@ -149,13 +168,16 @@ bool out_eq(const rgsvd_out& a, const rgsvd_out& b) { return std::memcmp(&a, &b,
 // --------------------------------------------------------------- layout --
 int layout(rgsvd_plan_s* P) {
   const int prec = P->prec;
-  const size_t wsz = (prec == P64) ? 8 : 4;   // working element size
-  const size_t psz = wsz;                      // partial element size
+  // a learned run with a judge may fall back to Algorithm 1 in FP64 on the
+  // same buffers: they are laid out for FP64 and the adaptive steps
+  const bool fb = P->adaptive || P->judge;
+  const size_t wsz = (prec == P64 || fb) ? 8 : 4;   // working element size
+  const size_t psz = wsz;                            // partial element size
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off = up(off + bytes, ALIGN); return o; };
   // adaptive runs grow Q by blocks written 16-row aligned at offset l: one
   // spare 16-row group past the capacity
-  const int spare = P->adaptive ? 16 : 0;
+  const int spare = fb ? 16 : 0;
   P->Lmax = 16;
   for (auto& pr : P->pairs) P->Lmax = std::max(P->Lmax, (int)upi(std::max(pr.l1, pr.l2), 16) + spare);
   P->npadG = (int)upi(P->Lmax, 64);
@@ -228,7 +250,7 @@ int layout(rgsvd_plan_s* P) {
       s.gpart = take((size_t)gch * P->npadG * P->npadG * 8);
       s.gram = take((size_t)P->npadG * P->npadG * 8);
       s.sinv = take((size_t)P->npadG * P->npadG * 8);
-      if (P->adaptive) {
+      if (fb) {
         const int lb = (int)upi(std::min(P->block, s.cap), 16);
         s.Ot = take((size_t)lb * s.ldw * wsz);
         s.scal = take(8 * 8);
@@ -264,6 +286,7 @@ int layout(rgsvd_plan_s* P) {
   // job area: generous bound
   size_t per_side = 64 * 1024 + (size_t)(P->sides.empty() ? 0 : P->sides[0].nchunk_max) * 256;
   P->jobs_cap = up(per_side * nsides + 256 * 1024, ALIGN);
+  if (P->learned) P->jobs_cap *= 24;   // the head and up to 20 tails (one per grid point)
   P->off_jobs = take(P->jobs_cap);
   P->ws = off;
   return RGSVD_OK;
@@ -300,7 +323,7 @@ struct Builder {
 inline char* WS(void* ws, size_t off) { return (char*)ws + off; }
 
 int build(rgsvd_plan_s* P, void* ws) {
-  P->host.clear();
+  if (!P->append) P->host.clear();
   P->stages.clear();
   Builder B(P);
   const int prec = P->prec;
@@ -320,8 +343,10 @@ int build(rgsvd_plan_s* P, void* ws) {
   }
 
   const auto part = P->part;
-  const bool head = (part == rgsvd_plan_s::FIXED || part == rgsvd_plan_s::A_INIT);
-  const bool tail = (part == rgsvd_plan_s::FIXED || part == rgsvd_plan_s::TAIL);
+  const bool head = (part == rgsvd_plan_s::FIXED || part == rgsvd_plan_s::A_INIT ||
+                     part == rgsvd_plan_s::L_HEAD);
+  const bool tail = (part == rgsvd_plan_s::FIXED || part == rgsvd_plan_s::TAIL ||
+                     part == rgsvd_plan_s::L_TAIL);
   // 0. zero the W buffers (their padding rows must read as zero) and copy
   //    the info templates
   if (head) {
@@ -337,9 +362,9 @@ int build(rgsvd_plan_s* P, void* ws) {
     }
     B.add(K_ZEROG, zj, zt).tag = T_ZERO;
   }
-  if (head || part == rgsvd_plan_s::TAIL) {
-    // the tail of an adaptive run rewrites the words with the final sizes
-    // (flags raised by the block steps are kept)
+  if ((head && !P->probe_only) || part == rgsvd_plan_s::TAIL || part == rgsvd_plan_s::L_TAIL) {
+    // the tails of adaptive and learned runs rewrite the words with the
+    // final sizes (flags raised before are kept)
     const int nw = head ? RGSVD_INFO_WORDS : 4;
     std::vector<uint32_t> tmpl;
     std::vector<CopyJob> cj;
@@ -347,6 +372,7 @@ int build(rgsvd_plan_s* P, void* ws) {
     for (auto& pr : P->pairs) {
       uint32_t w[RGSVD_INFO_WORDS] = {0};
       w[1] = pr.l1; w[2] = pr.l2; w[3] = P->adaptive ? 0 : pr.q;
+      w[RGSVD_INFO_FLAGS] = (uint32_t)P->extra_flags;
       for (int i = 0; i < RGSVD_INFO_WORDS; ++i) tmpl.push_back(w[i]);
     }
     size_t toff = B.put(tmpl);
@@ -364,82 +390,8 @@ int build(rgsvd_plan_s* P, void* ws) {
     return pr.out.info ? pr.out.info : (int32_t*)WS(ws, pr.info);
   };
 
-  // probe features of the pair and the sizing network's output (learned
-  // sizing): Omega[:, :16], Y = G Omega16, its 16 x 16 Gram in FP64, the
-  // features from the Gram's eigenvalues, and the network on them
-  if (part == rgsvd_plan_s::PROBE) {
-    const int pw = (prec == P64) ? P64 : P32;
-    const size_t wsz = (pw == P64) ? 8 : 4;
-    for (auto& s : S) {
-      Stage z; z.kind = K_ZERO; z.tag = T_ZERO; z.zoff = s.Yt; z.zbytes = (size_t)16 * s.ldy * wsz;
-      P->stages.push_back(z);
-    }
-    {
-      std::vector<GenJob> j; std::vector<int> tl;
-      for (auto& s : S) {
-        GenJob g{};
-        g.Wt = WS(ws, s.Wt); g.ldw = s.ldw; g.seed = s.seed; g.n = s.n; g.col0 = 0;
-        g.ncols = 16; g.L = 16; g.stream = s.stream;
-        j.push_back(g);
-        tl.push_back(((s.n + 255) / 256) * 4);
-      }
-      Stage& st = B.add(K_GEN, j, tl); st.f64 = (pw == P64); st.tag = T_GEN;
-    }
-    if (pw != P64) {
-      // the 16 probe columns in FP32 fragment order
-      std::vector<PackJobH> j; std::vector<int> tl;
-      for (auto& s : S) {
-        PackJobH c{};
-        c.src = (const float*)WS(ws, s.Wt); c.dst = WS(ws, s.Wp32);
-        c.ld = s.ldw; c.L = 16; c.nst = (s.n + 15) / 16; c.bf16 = 0;
-        j.push_back(c);
-        tl.push_back((int)(((int64_t)c.nst * 64 + 255) / 256));
-      }
-      B.add(K_PACK, j, tl).tag = T_ZERO;
-    }
-    {
-      std::vector<NnJob> j; std::vector<int> tl;
-      for (auto& s : S) {
-        NnJob x{};
-        x.G = s.G; x.Wt = WS(ws, pw == P64 ? s.Wt : s.Wp32); x.Yt = WS(ws, s.Yt);
-        x.ldg = s.ldg; x.ldw = s.ldw; x.ldy = s.ldy; x.m = s.m; x.n = s.n; x.L = 16;
-        j.push_back(x);
-        tl.push_back((s.m + 15) / 16);
-      }
-      Stage& st = B.add(K_GW, j, tl);
-      st.prec = pw; st.gdt = gt; st.rt = 1; st.ct = 1; st.tag = T_NN;
-    }
-    {
-      std::vector<GramJob> gj; std::vector<int> gtl;
-      std::vector<RedJob> rj; std::vector<int> rtl;
-      std::vector<FeatJob> fj; std::vector<int> ftl;
-      for (size_t i = 0; i < S.size(); ++i) {
-        auto& s = S[i];
-        GramJob g{};
-        g.X1 = WS(ws, s.Yt); g.X2 = nullptr; g.out = (double*)WS(ws, s.gpart);
-        g.ld1 = s.ldy; g.ld2 = 0; g.r1 = 16; g.r2 = 0; g.k0 = 0; g.k1 = s.m; g.npad = 64; g.clen = s.gcl_m;
-        gj.push_back(g); gtl.push_back(gram_strips(16) * s.gch_m);
-        RedJob r{};
-        r.in = WS(ws, s.gpart); r.out = WS(ws, s.gram); r.sq = nullptr;
-        r.stride = 64 * 64; r.count = r.stride;
-        r.nparts = s.gch_m; r.rows = 64; r.cols = 64; r.ldo = 64; r.ldi = 64; r.nz = 16;
-        rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
-        fj.push_back(FeatJob{(const double*)WS(ws, s.gram), (float*)WS(ws, P->off_feat) + 16 * i, 64, 0});
-        ftl.push_back(1);
-      }
-      Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = (pw == P64) ? 0 : 1; gs.tag = T_GRAM;
-      Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.ta = 0; r.td = 0; r.tag = T_RED;
-      B.add(K_FEAT, fj, ftl).tag = T_SMALL;
-    }
-    if (P->mlp) {
-      Stage m; m.kind = K_MLP; m.tag = T_SMALL; P->stages.push_back(m);
-    }
-    if (P->host.size() > P->jobs_cap) return RGSVD_ENOMEM;
-    return RGSVD_OK;
-  }
-
   // 1. Omega
-  if (part == rgsvd_plan_s::FIXED) {
+  if (part == rgsvd_plan_s::FIXED || part == rgsvd_plan_s::L_HEAD) {
     std::vector<GenJob> j; std::vector<int> tl;
     for (auto& s : S) {
       GenJob g{};
@@ -611,10 +563,71 @@ int build(rgsvd_plan_s* P, void* ws) {
     r.sym = false; r.ta = wt; r.td = wt; r.tag = T_RED;
   };
 
-  if (part == rgsvd_plan_s::FIXED) {
+  // sums of squares (adaptive runs and the residual judge of learned runs):
+  // jobs and their finishing sums
+  auto add_sumsq = [&](std::vector<SumsqJob>& j, std::vector<int>& tl, std::vector<SumsqFin>& f) {
+    Stage& a = B.add(K_SUMSQ, j, tl); a.tag = T_RED;
+    std::vector<int> ftl(f.size(), 1);
+    B.add(K_SUMFIN, f, ftl).tag = T_RED;
+  };
+  // ||G_i||_F^2 into scal[0] (FP64 partials over 64-row slabs, summed in order)
+  auto add_gnorm = [&]() {
+    std::vector<SumsqJob> j; std::vector<int> tl; std::vector<SumsqFin> f;
+    for (auto& s : S) {
+      j.push_back(SumsqJob{s.G, s.ldg, s.m, s.n, gt == 0 ? 1 : 0, 64, (double*)WS(ws, s.spart)});
+      tl.push_back(s.gtiles);
+      f.push_back(SumsqFin{(const double*)WS(ws, s.spart), (double*)WS(ws, s.scal), s.gtiles, 0});
+    }
+    add_sumsq(j, tl, f);
+  };
+
+  if (part == rgsvd_plan_s::FIXED || part == rgsvd_plan_s::L_HEAD)
+    add_nn(mixed ? PBF : prec);   // sketch
+  if (part == rgsvd_plan_s::L_HEAD) {
+    // probe features from the sketch's first 16 columns (Omega's global
+    // columns make them the 16-column sketch): their FP64 Gram, its
+    // eigenvalues, log10 of the normalised singular values; then the network
+    std::vector<GramJob> gj; std::vector<int> gtl;
+    std::vector<RedJob> rj; std::vector<int> rtl;
+    std::vector<FeatJob> fj; std::vector<int> ftl;
+    for (size_t i = 0; i < S.size(); ++i) {
+      auto& s = S[i];
+      GramJob g{};
+      g.X1 = WS(ws, s.Yt); g.X2 = nullptr; g.out = (double*)WS(ws, s.gpart);
+      g.ld1 = s.ldy; g.ld2 = 0; g.r1 = 16; g.r2 = 0; g.k0 = 0; g.k1 = s.m; g.npad = 64; g.clen = s.gcl_m;
+      gj.push_back(g); gtl.push_back(gram_strips(16) * s.gch_m);
+      RedJob r{};
+      r.in = WS(ws, s.gpart); r.out = WS(ws, s.gram); r.sq = nullptr;
+      r.stride = 64 * 64; r.count = r.stride;
+      r.nparts = s.gch_m; r.rows = 64; r.cols = 64; r.ldo = 64; r.ldi = 64; r.nz = 16;
+      rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
+      fj.push_back(FeatJob{(const double*)WS(ws, s.gram), (float*)WS(ws, P->off_feat) + 16 * i, 64, 0});
+      ftl.push_back(1);
+    }
+    Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = wt; gs.tag = T_GRAM;
+    Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.ta = 0; r.td = 0; r.tag = T_RED;
+    B.add(K_FEAT, fj, ftl).tag = T_SMALL;
+    if (!P->probe_only) {
+      if (P->mlp) { Stage m; m.kind = K_MLP; m.tag = T_SMALL; P->stages.push_back(m); }
+      if (P->judge) add_gnorm();
+    }
+    if (P->host.size() > P->jobs_cap) return RGSVD_ENOMEM;
+    return RGSVD_OK;
+  }
+  if (part == rgsvd_plan_s::L_TAIL) {
+    // the chosen width l <= the head's: the sketch rows [l, L) are cleared
+    std::vector<ZeroJob> zj; std::vector<int> zt;
+    const size_t esz = prec == P64 ? 8 : 4;
+    for (auto& s : S) {
+      const size_t bytes = (size_t)(upi(P->lmaxw, 16) - s.l) * s.ldy * esz;
+      if (bytes == 0) continue;
+      zj.push_back(ZeroJob{(uint32_t*)(WS(ws, s.Yt) + (size_t)s.l * s.ldy * esz), (int64_t)(bytes / 4)});
+      zt.push_back((int)((bytes / 4 + 4095) / 4096));
+    }
+    if (!zj.empty()) B.add(K_ZEROG, zj, zt).tag = T_ZERO;
+  }
+  if (part == rgsvd_plan_s::FIXED || part == rgsvd_plan_s::L_TAIL) {
     const int qmax = [&] { int q = 0; for (auto& pr : P->pairs) q = std::max(q, pr.q); return q; }();
-    // sketch
-    add_nn(mixed ? PBF : prec);
     add_orth(true, qmax == 0 ? 2 : 1);
     for (int it = 1; it <= qmax; ++it) {
       int p = mixed ? (it < qmax ? PBF : P32) : prec;
@@ -625,24 +638,20 @@ int build(rgsvd_plan_s* P, void* ws) {
     }
     // projection B_i = Q_i^T G_i
     add_tn(mixed ? P32 : prec);
-  }
-
-  // sums of squares (adaptive): jobs and their finishing sums
-  auto add_sumsq = [&](std::vector<SumsqJob>& j, std::vector<int>& tl, std::vector<SumsqFin>& f) {
-    Stage& a = B.add(K_SUMSQ, j, tl); a.tag = T_RED;
-    std::vector<int> ftl(f.size(), 1);
-    B.add(K_SUMFIN, f, ftl).tag = T_RED;
-  };
-  if (part == rgsvd_plan_s::A_INIT) {
-    // ||G_i||_F^2 (FP64 partials over 64-row slabs, summed in order)
-    std::vector<SumsqJob> j; std::vector<int> tl; std::vector<SumsqFin> f;
-    for (auto& s : S) {
-      j.push_back(SumsqJob{s.G, s.ldg, s.m, s.n, gt == 0 ? 1 : 0, 64, (double*)WS(ws, s.spart)});
-      tl.push_back(s.gtiles);
-      f.push_back(SumsqFin{(const double*)WS(ws, s.spart), (double*)WS(ws, s.scal), s.gtiles, 0});
+    if (part == rgsvd_plan_s::L_TAIL && P->judge) {
+      // ||B_i||_F^2 into scal[1]: with ||G_i||_F^2 the residual
+      // ||(I - Q_i Q_i^T) G_i||_F^2 = ||G_i||_F^2 - ||B_i||_F^2 of the judge
+      std::vector<SumsqJob> j; std::vector<int> tl; std::vector<SumsqFin> f;
+      for (auto& s : S) {
+        const int nt = (s.l + 15) / 16;
+        j.push_back(SumsqJob{WS(ws, s.Wt), s.ldw, s.l, s.n, prec == P64 ? 1 : 0, 16, (double*)WS(ws, s.spart)});
+        tl.push_back(nt);
+        f.push_back(SumsqFin{(const double*)WS(ws, s.spart), (double*)WS(ws, s.scal) + 1, nt, 0});
+      }
+      add_sumsq(j, tl, f);
     }
-    add_sumsq(j, tl, f);
   }
+  if (part == rgsvd_plan_s::A_INIT) add_gnorm();
   if (part == rgsvd_plan_s::A_BLOCK) {
     // one block of Algorithm 1 on every active side: Omega columns
     // [l, l + b) of the side's stream, Y = G Omega into Q's rows [l, l + b),
@@ -980,40 +989,74 @@ __global__ void k_sumfin(const SumsqFin* j, int nj) {
   J.out[0] = s;
 }
 
-// Probe features: eigenvalues of the 16 x 16 probe Gram by cyclic Jacobi
-// (one thread, FP64), sigma_j = sqrt(lambda_j) in descending order, then
+// Probe features: eigenvalues of the 16 x 16 probe Gram by two-sided
+// Jacobi in one wave, sigma_j = sqrt(lambda_j) in descending order, then
 // log10(sigma_j / sigma_1) floored at -8 (the Gram resolves sigma_j / sigma_1
-// down to about sqrt(eps)).
-__global__ void k_feat(const FeatJob* j, int nj) {
+// down to about sqrt(eps)).  Parallel ordering: each of the 15 rounds of a
+// sweep turns 8 disjoint pairs (round-robin over the 16 indices), lanes 0..7
+// forming the rotations, then all 64 lanes applying them to the columns and
+// then to the rows of the matrix (held in LDS).  Sweeps end when the
+// off-diagonal mass is below 1e-32 of the diagonal's, at most 40.
+__global__ __launch_bounds__(64) void k_feat(const FeatJob* j, int nj) {
   const FeatJob J = j[blockIdx.x];
-  __shared__ double a[16][16];
-  for (int e = threadIdx.x; e < 256; e += blockDim.x) a[e >> 4][e & 15] = J.gram[(int64_t)(e >> 4) * J.ldg + (e & 15)];
+  __shared__ double a[16][17];
+  __shared__ double cs[8][2];
+  __shared__ int pq[8][2];
+  const int ln = threadIdx.x;
+  for (int e = ln; e < 256; e += 64) {
+    const int r = e >> 4, c = e & 15;
+    // the reduction filled the upper triangle
+    a[r][c] = (c >= r) ? J.gram[(int64_t)r * J.ldg + c] : J.gram[(int64_t)c * J.ldg + r];
+  }
   __syncthreads();
-  if (threadIdx.x != 0) return;
-  for (int r = 0; r < 16; ++r)
-    for (int c = 0; c < r; ++c) a[r][c] = a[c][r];   // the reduction filled the upper triangle
   for (int sweep = 0; sweep < 40; ++sweep) {
     double off = 0.0, dia = 0.0;
-    for (int r = 0; r < 16; ++r)
-      for (int c = 0; c < 16; ++c) { if (r != c) off += a[r][c] * a[r][c]; else dia += a[r][c] * a[r][c]; }
+    for (int e = ln; e < 256; e += 64) {
+      const int r = e >> 4, c = e & 15;
+      const double v = a[r][c];
+      if (r != c) off += v * v; else dia += v * v;
+    }
+    off = wave_sum(off);
+    dia = wave_sum(dia);
     if (!(off > 1e-32 * dia)) break;
-    for (int p = 0; p < 15; ++p)
-      for (int q = p + 1; q < 16; ++q) {
+    for (int round = 0; round < 15; ++round) {
+      if (ln < 8) {
+        int u = 0, v;
+        if (ln > 0) { u = ln - 1 + round; if (u >= 15) u -= 15; u += 1; }
+        v = 15 - ln - 1 + round; if (v >= 15) v -= 15; v += 1;
+        const int p = u < v ? u : v, q = u < v ? v : u;
         const double apq = a[p][q];
-        if (apq == 0.0) continue;
-        const double th = (a[q][q] - a[p][p]) / (2.0 * apq);
-        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
-        const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
-        for (int r = 0; r < 16; ++r) {
-          const double x = a[r][p], y = a[r][q];
-          a[r][p] = c * x - s * y; a[r][q] = s * x + c * y;
+        double c = 1.0, sn = 0.0;
+        if (apq != 0.0) {
+          const double th = (a[q][q] - a[p][p]) / (2.0 * apq);
+          const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(1.0 + th * th));
+          c = 1.0 / sqrt(1.0 + t * t);
+          sn = t * c;
         }
-        for (int r = 0; r < 16; ++r) {
-          const double x = a[p][r], y = a[q][r];
-          a[p][r] = c * x - s * y; a[q][r] = s * x + c * y;
-        }
+        cs[ln][0] = c; cs[ln][1] = sn; pq[ln][0] = p; pq[ln][1] = q;
       }
+      __syncthreads();
+      // columns p, q of every row: 8 pairs x 16 rows, two per lane
+      for (int e = ln; e < 128; e += 64) {
+        const int pi = e >> 4, r = e & 15;
+        const int p = pq[pi][0], q = pq[pi][1];
+        const double c = cs[pi][0], sn = cs[pi][1];
+        const double x = a[r][p], y = a[r][q];
+        a[r][p] = c * x - sn * y; a[r][q] = sn * x + c * y;
+      }
+      __syncthreads();
+      // rows p, q
+      for (int e = ln; e < 128; e += 64) {
+        const int pi = e >> 4, r = e & 15;
+        const int p = pq[pi][0], q = pq[pi][1];
+        const double c = cs[pi][0], sn = cs[pi][1];
+        const double x = a[p][r], y = a[q][r];
+        a[p][r] = c * x - sn * y; a[q][r] = sn * x + c * y;
+      }
+      __syncthreads();
+    }
   }
+  if (ln != 0) return;
   double sv[16];
   for (int i = 0; i < 16; ++i) sv[i] = sqrt(fmax(a[i][i], 0.0));
   for (int i = 1; i < 16; ++i)
@@ -1022,18 +1065,19 @@ __global__ void k_feat(const FeatJob* j, int nj) {
     J.out[i] = (float)((sv[0] > 0.0 && sv[i] > 0.0) ? fmax(log10(sv[i] / sv[0]), -8.0) : -8.0);
 }
 
-int enqueue(rgsvd_plan_s* P, void* ws, hipStream_t st) {
+int enqueue_list(rgsvd_plan_s* P, void* ws, hipStream_t st, const std::vector<Stage>& list) {
   char* jb = (char*)ws + P->off_jobs;
   if (P->prof) {
-    while (P->pev.size() < P->stages.size() + 1) {
+    while (P->pev.size() < list.size() + 1) {
       hipEvent_t e;
       if (hipEventCreate(&e) != hipSuccess) return RGSVD_EHIP;
       P->pev.push_back(e);
     }
-    P->prof_count = (int)P->stages.size();
+    P->prof_count = (int)list.size();
+    P->prof_list = &list;
   }
   int si = 0;
-  for (const Stage& s : P->stages) {
+  for (const Stage& s : list) {
     if (P->prof) hipEventRecord(P->pev[si], st);
     ++si;
     const int* pre = (const int*)(jb + s.poff);
@@ -1073,6 +1117,8 @@ int enqueue(rgsvd_plan_s* P, void* ws, hipStream_t st) {
   return hipGetLastError() == hipSuccess ? RGSVD_OK : RGSVD_EHIP;
 }
 
+int enqueue(rgsvd_plan_s* P, void* ws, hipStream_t st) { return enqueue_list(P, ws, st, P->stages); }
+
 int upload(rgsvd_plan_s* P, void* ws, hipStream_t st) {
   if (!P->pinned) {
     if (hipHostMalloc(&P->pinned, P->jobs_cap, hipHostMallocDefault) != hipSuccess) return RGSVD_EHIP;
@@ -1095,8 +1141,11 @@ void drop_graph(rgsvd_plan_s* P) {
   if (P->gexec) { hipGraphExecDestroy(P->gexec); P->gexec = nullptr; }
 }
 
-int capture_graph(rgsvd_plan_s* P, void* ws) {
-  drop_graph(P);
+int enqueue_list(rgsvd_plan_s* P, void* ws, hipStream_t st, const std::vector<Stage>& list);
+
+// Capture a stage list into an executable graph (on a stream of its own).
+int capture_list(rgsvd_plan_s* P, void* ws, const std::vector<Stage>& list, hipGraphExec_t* exec) {
+  *exec = nullptr;
   hipStream_t cs;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return RGSVD_EHIP;
   hipGraph_t g = nullptr;
@@ -1104,15 +1153,39 @@ int capture_graph(rgsvd_plan_s* P, void* ws) {
   P->prof = false;
   bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) == hipSuccess;
   if (ok) {
-    const int rc = enqueue(P, ws, cs);
+    const int rc = enqueue_list(P, ws, cs, list);
     ok = hipStreamEndCapture(cs, &g) == hipSuccess && g && rc == RGSVD_OK;
   }
   P->prof = prof;
-  if (ok) ok = hipGraphInstantiate(&P->gexec, g, nullptr, nullptr, 0) == hipSuccess;
+  if (ok) ok = hipGraphInstantiate(exec, g, nullptr, nullptr, 0) == hipSuccess;
   if (g) hipGraphDestroy(g);
   hipStreamDestroy(cs);
-  if (!ok) { P->gexec = nullptr; return RGSVD_EHIP; }
+  if (!ok) { *exec = nullptr; return RGSVD_EHIP; }
   return RGSVD_OK;
+}
+
+int capture_graph(rgsvd_plan_s* P, void* ws) {
+  drop_graph(P);
+  return capture_list(P, ws, P->stages, &P->gexec);
+}
+
+// Drop the learned run's graphs (they hold the bound pointers).
+void drop_learned_graphs(rgsvd_plan_s* P) {
+  if (P->lhead_exec) { hipGraphExecDestroy(P->lhead_exec); P->lhead_exec = nullptr; }
+  for (auto& e : P->ltail_exec)
+    if (e) { hipGraphExecDestroy(e); e = nullptr; }
+  P->ltail_exec.clear();
+}
+
+// Launch a stage list: eagerly when profiling (events between stages),
+// otherwise as its graph, captured on first use.
+int run_list(rgsvd_plan_s* P, void* ws, hipStream_t st, const std::vector<Stage>& list, hipGraphExec_t* exec) {
+  if (P->prof) return enqueue_list(P, ws, st, list);
+  if (!*exec) {
+    const int rc = capture_list(P, ws, list, exec);
+    if (rc) return rc;
+  }
+  return hipGraphLaunch(*exec, st) == hipSuccess ? RGSVD_OK : RGSVD_EHIP;
 }
 
 // capacity of an adaptive basis: lmax (0: no cap) clamped to min(rows, n)
@@ -1146,8 +1219,10 @@ int check_desc(const rgsvd_desc* d) {
     if (d->k > adaptive_cap(d->lmax, d->m, d->n) || d->k > adaptive_cap(d->lmax, d->p, d->n))
       return RGSVD_EINVAL;
   } else if (d->sizing == RGSVD_SIZE_LEARNED) {
-    // the network picks l on a grid up to min(2k, capacity) and q <= 3
-    if (d->lmax < 0 || d->mode != RGSVD_TRUNCATED) return d->lmax < 0 ? RGSVD_EINVAL : RGSVD_EUNSUPPORTED;
+    // the network picks l on a grid up to min(2k, capacity) and q <= 3; tol
+    // > 0 turns on the residual judge (fallback: Algorithm 1 with b = block)
+    if (d->lmax < 0 || d->block < 0 || !(d->tol >= 0.0) || !std::isfinite(d->tol)) return RGSVD_EINVAL;
+    if (d->mode != RGSVD_TRUNCATED) return RGSVD_EUNSUPPORTED;
     if (d->k > adaptive_cap(d->lmax, d->m, d->n) || d->k > adaptive_cap(d->lmax, d->p, d->n))
       return RGSVD_EINVAL;
   } else {
@@ -1237,27 +1312,47 @@ int run_adaptive(rgsvd_plan_s* P, void* ws, hipStream_t st) {
   return stage_list(rgsvd_plan_s::TAIL);
 }
 
-// Probe stage list with every side at width 16 (their buffers hold more).
+// Every side at sketch width l (its buffers hold the capacity).
+void set_width(rgsvd_plan_s* P, int l, int q) {
+  for (auto& s : P->sides) { s.l = l; s.L = (int)upi(l, 16); }
+  for (auto& pr : P->pairs) { pr.l1 = pr.l2 = l; pr.q = q; }
+}
+
+// The 16-column sketch and its features alone (rgsvd_probe_features): the
+// head of a learned run at width 16, in the plan's sketch precision, so the
+// features equal those a learned run computes from its own sketch.
 int run_probe(rgsvd_plan_s* P, void* ws, hipStream_t st) {
-  for (auto& s : P->sides) { s.l = 16; s.L = 16; }
-  P->part = rgsvd_plan_s::PROBE;
+  const int keep = P->lmaxw;
+  P->lmaxw = 16;
+  set_width(P, 16, 0);
+  P->part = rgsvd_plan_s::L_HEAD;
+  P->probe_only = true;
   int rc = build(P, ws);
+  P->probe_only = false;
   P->part = rgsvd_plan_s::FIXED;
+  P->lmaxw = keep;
+  P->lbound = false;
+  drop_learned_graphs(P);
   if (!rc) rc = upload(P, ws, st);
   if (!rc) rc = enqueue(P, ws, st);
   return rc;
 }
 
-// Sketch sizes from the network output (log2(l / k), q): the smallest l of
-// the grid {k+4, k+8, k+16, k+32, 2k} (capped) at or above k 2^y0, and q
-// rounded with a bias of 0.4 towards more passes (q >= 1 from y1 = 0.1 on),
-// clamped to [0, 3].
-void decide_sizes(double y0, double y1, int k, int cap, int* l, int* q) {
-  int g[5] = {k + 4, k + 8, k + 16, k + 32, 2 * k};
+// The sketch widths a sizing network can pick: {k+4, k+8, k+16, k+32, 2k},
+// capped at cap, ascending and distinct.
+std::vector<int> l_grid(int k, int cap) {
   std::vector<int> grid;
-  for (int v : g) { v = std::min(v, cap); if (v >= k) grid.push_back(v); }
+  for (int v : {k + 4, k + 8, k + 16, k + 32, 2 * k}) { v = std::min(v, cap); if (v >= k) grid.push_back(v); }
   std::sort(grid.begin(), grid.end());
   grid.erase(std::unique(grid.begin(), grid.end()), grid.end());
+  return grid;
+}
+
+// Sketch sizes from the network output (log2(l / k), q): the smallest l of
+// the grid at or above k 2^y0, and q rounded with a bias of 0.4 towards more
+// passes (q >= 1 from y1 = 0.1 on), clamped to [0, 3].
+void decide_sizes(double y0, double y1, int k, int cap, int* l, int* q) {
+  const std::vector<int> grid = l_grid(k, cap);
   const double want = k * std::exp2(std::isfinite(y0) ? std::min(y0, 8.0) : 8.0);
   *l = grid.back();
   for (int v : grid) if (v >= want) { *l = v; break; }
@@ -1265,14 +1360,64 @@ void decide_sizes(double y0, double y1, int k, int cap, int* l, int* q) {
   *q = (int)std::min(3.0, std::max(0.0, qq));
 }
 
-// Learned sizing: probe features and the network on the device, one read of
-// its two outputs, then the fixed-size run at the chosen (l, q).
-int run_learned(rgsvd_plan_s* P, void* ws, hipStream_t st) {
+// Job tables of a learned run for the bound pointers: the head (sketch at
+// the widest grid width, probe features, network) and one tail per grid
+// point, serialised once into the job area.
+int bind_learned(rgsvd_plan_s* P, void* ws, hipStream_t st) {
+  PairLay& pr = P->pairs[0];
+  const int cap = std::min(pr.l1cap, pr.l2cap);
+  const std::vector<int> grid = l_grid((int)pr.k, cap);
+  P->lmaxw = grid.back();
+  drop_learned_graphs(P);
+  P->host.clear();
+  P->append = true;
+  P->ltails.clear();
+  P->lgrid.clear();
+  set_width(P, P->lmaxw, 0);
+  P->part = rgsvd_plan_s::L_HEAD;
+  int rc = build(P, ws);
+  P->lhead = std::move(P->stages);
+  for (int q = 0; q <= 3 && !rc; ++q)
+    for (int l : grid) {
+      set_width(P, l, q);
+      P->part = rgsvd_plan_s::L_TAIL;
+      rc = build(P, ws);
+      if (rc) break;
+      P->ltails.push_back(std::move(P->stages));
+      P->lgrid.push_back({l, q});
+    }
+  P->append = false;
+  P->part = rgsvd_plan_s::FIXED;
+  P->stages.clear();
+  P->ltail_exec.assign(P->ltails.size(), nullptr);
+  if (!rc) rc = upload(P, ws, st);
+  P->lbound = !rc;
+  return rc;
+}
+
+// Learned sizing: the head (sketch, features, network), one read of the
+// network's two outputs, then the tail at the chosen (l, q).  With a
+// tolerance (the judge), the residual ||G_i||_F^2 - ||Q_i^T G_i||_F^2 of
+// either side above tol^2 sends the pair to Algorithm 1 (adaptive blocks,
+// FP64) instead, and FLAG_FALLBACK marks it.
+int run_learned(rgsvd_plan_s* P, const void* G1, int64_t ld1, const void* G2, int64_t ld2, void* ws,
+                hipStream_t st, const rgsvd_out* out) {
   PairLay& pr = P->pairs[0];
   if (!P->mlp) return RGSVD_ENOMODEL;
   if (!P->hscal && hipHostMalloc((void**)&P->hscal, 64 * sizeof(double), hipHostMallocDefault) != hipSuccess)
     return RGSVD_EHIP;
-  int rc = run_probe(P, ws, st);
+  const bool same = P->lbound && P->lastG1 == G1 && P->lastG2 == G2 && P->lastws == ws && P->lastld1 == ld1 &&
+                    P->lastld2 == ld2 && out_eq(P->lastout, *out);
+  if (!same) {
+    pr.out = *out;
+    P->sides[0].G = G1; P->sides[0].ldg = ld1;
+    P->sides[1].G = G2; P->sides[1].ldg = ld2;
+    const int rc = bind_learned(P, ws, st);
+    if (rc) return rc;
+    P->lastG1 = G1; P->lastG2 = G2; P->lastws = ws; P->lastld1 = ld1; P->lastld2 = ld2;
+    P->lastout = *out;
+  }
+  int rc = run_list(P, ws, st, P->lhead, &P->lhead_exec);
   if (rc) return rc;
   const float* yd = (const float*)((char*)ws + P->off_feat) + RGSVD_MLP_IN;
   if (hipMemcpyAsync(P->hscal, yd, 2 * sizeof(float), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -1281,13 +1426,38 @@ int run_learned(rgsvd_plan_s* P, void* ws, hipStream_t st) {
   const float* y = (const float*)P->hscal;
   int l = 0, q = 0;
   decide_sizes(y[0], y[1], (int)pr.k, std::min(pr.l1cap, pr.l2cap), &l, &q);
-  pr.l1 = pr.l2 = l;
-  pr.q = q;
-  for (auto& s : P->sides) { s.l = l; s.L = (int)upi(l, 16); }
-  P->part = rgsvd_plan_s::FIXED;
-  rc = build(P, ws);
-  if (!rc) rc = upload(P, ws, st);
-  if (!rc) rc = enqueue(P, ws, st);
+  size_t idx = 0;
+  while (idx < P->lgrid.size() && P->lgrid[idx] != std::make_pair(l, q)) ++idx;
+  if (idx == P->lgrid.size()) return RGSVD_EHIP;
+  set_width(P, l, q);
+  rc = run_list(P, ws, st, P->ltails[idx], &P->ltail_exec[idx]);
+  if (rc || !P->judge) return rc;
+  // the judge: a posteriori residual of each side's basis
+  std::vector<SideLay>& S = P->sides;
+  for (size_t i = 0; i < S.size(); ++i)
+    if (hipMemcpyAsync(P->hscal + 2 * i, (char*)ws + S[i].scal, 2 * sizeof(double), hipMemcpyDeviceToHost, st) !=
+        hipSuccess)
+      return RGSVD_EHIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return RGSVD_EHIP;
+  bool accept = true;
+  for (size_t i = 0; i < S.size(); ++i) {
+    const double res = std::sqrt(std::max(0.0, P->hscal[2 * i] - P->hscal[2 * i + 1]));
+    accept &= !(res >= P->d.tol);
+  }
+  if (accept) return RGSVD_OK;
+  // fallback: Algorithm 1 at the plan's capacity, in FP64 (the plan's
+  // working buffers are laid out for it)
+  const int prec = P->prec;
+  P->prec = P64;
+  P->adaptive = true;
+  P->extra_flags = RGSVD_FLAG_FALLBACK;
+  for (auto& s : S) { s.l = s.cap; s.L = (int)upi(s.cap, 16) + 16; }
+  rc = run_adaptive(P, ws, st);
+  P->prec = prec;
+  P->adaptive = false;
+  P->extra_flags = 0;
+  P->lbound = false;   // the adaptive steps replaced the job tables
+  drop_learned_graphs(P);
   return rc;
 }
 
@@ -1413,6 +1583,7 @@ int rgsvd_plan(const rgsvd_desc* desc, rgsvd_plan_t* plan, size_t* workspace_byt
   P->mode = desc->mode;
   P->adaptive = desc->sizing == RGSVD_SIZE_ADAPTIVE;
   P->learned = desc->sizing == RGSVD_SIZE_LEARNED;
+  P->judge = P->learned && desc->tol > 0.0;
   P->block = desc->block > 0 ? (int)desc->block : 100;
   P->pairs.push_back(pair_from(desc));
   P->wave_slots = device_wave_slots();
@@ -1449,13 +1620,7 @@ int rgsvd_run(rgsvd_plan_t P, const void* G1, int64_t ld1, const void* G2, int64
     P->bound = false;
     return run_adaptive(P, workspace, st);
   }
-  if (P->learned) {
-    pr.out = *out;
-    P->sides[0].G = G1; P->sides[0].ldg = ld1;
-    P->sides[1].G = G2; P->sides[1].ldg = ld2;
-    P->bound = false;
-    return run_learned(P, workspace, st);
-  }
+  if (P->learned) return run_learned(P, G1, ld1, G2, ld2, workspace, st, out);
   bool same = P->bound && P->lastG1 == G1 && P->lastG2 == G2 && P->lastws == workspace &&
               P->lastld1 == ld1 && P->lastld2 == ld2 && out_eq(P->lastout, *out);
   if (!same) {
@@ -1538,6 +1703,7 @@ void rgsvd_destroy(rgsvd_plan_t P) {
   if (P->ev) hipEventDestroy(P->ev);
   if (P->pinned) hipHostFree(P->pinned);
   if (P->gexec) hipGraphExecDestroy(P->gexec);
+  drop_learned_graphs(P);
   if (P->mlp) hipFree(P->mlp);
   if (P->hscal) hipHostFree(P->hscal);
   for (auto e : P->pev) hipEventDestroy(e);
@@ -1559,7 +1725,7 @@ int rgsvd_profile_read(rgsvd_plan_t P, int32_t max, float* ms, int32_t* tag, int
     if (hipEventSynchronize(P->pev[i + 1]) != hipSuccess) return RGSVD_EHIP;
     if (hipEventElapsedTime(&t, P->pev[i], P->pev[i + 1]) != hipSuccess) return RGSVD_EHIP;
     if (ms) ms[i] = t;
-    if (tag) tag[i] = P->stages[i].tag;
+    if (tag) tag[i] = (*P->prof_list)[i].tag;
   }
   return RGSVD_OK;
 }
@@ -1694,8 +1860,10 @@ extern "C" int rgsvd_probe_features(rgsvd_plan_t P, const void* G1, int64_t ld1,
   // restore the plan's own widths afterwards (the probe runs at width 16)
   std::vector<std::pair<int, int>> keep;
   for (auto& s : P->sides) keep.push_back({s.l, s.L});
+  const int l1 = pr.l1, l2 = pr.l2, q = pr.q;
   int rc = run_probe(P, workspace, st);
   for (size_t i = 0; i < P->sides.size(); ++i) { P->sides[i].l = keep[i].first; P->sides[i].L = keep[i].second; }
+  pr.l1 = l1; pr.l2 = l2; pr.q = q;
   if (rc) return rc;
   return hipMemcpyAsync(feat, (char*)workspace + P->off_feat, RGSVD_MLP_IN * sizeof(float),
                         hipMemcpyDeviceToDevice, st) == hipSuccess ? RGSVD_OK : RGSVD_EHIP;

@@ -49,6 +49,27 @@ def lowrank_pair(m, p, n, r, s1, s2, seed, noise_entry=None, noise_spectral=None
     return out[0], out[1]
 
 
+def lowrank_pair_device(m, p, n, r, s1, s2, seed, noise_spectral, device, dtype=None):
+    """The recipe of lowrank_pair (spectral noise floor) drawn on a torch
+    device from torch's seeded generator, for pairs too large to build on
+    the host quickly; returns (G1, G2) device tensors (float32 unless dtype
+    is given).  Not the same numbers as lowrank_pair for the same seed."""
+    import torch
+    dtype = torch.float32 if dtype is None else dtype
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = dict(device=device, dtype=torch.float64)
+    Z = torch.linalg.qr(torch.randn(n, r, generator=g, **f64))[0]
+    out = []
+    for rows, s in ((m, s1), (p, s2)):
+        U = torch.linalg.qr(torch.randn(rows, r, generator=g, **f64))[0]
+        G = (U * torch.as_tensor(np.asarray(s, dtype=np.float64), **f64)) @ Z.T
+        G += (noise_spectral / (math.sqrt(rows) + math.sqrt(n))) * torch.randn(rows, n, generator=g, **f64)
+        out.append(G.to(dtype).contiguous())
+        del G, U
+    return out[0], out[1]
+
+
 def planted_gmp(m, p, n, seed, frac=0.6, dtype=np.float64):
     """Paper-style exactly low-rank GMP; returns (G1, G2, alpha*, beta*)."""
     if m < n or p < n:

@@ -21,7 +21,7 @@ MLP_PARAMS = 6402
 
 FLAGS = {
     0x1: "shift_y", 0x2: "shift_w", 0x4: "chol_fail", 0x8: "jacobi_m",
-    0x10: "jacobi_l1", 0x20: "beta_zero", 0x40: "alpha_zero", 0x80: "nonfinite",
+    0x10: "jacobi_l1", 0x20: "beta_zero", 0x40: "alpha_zero", 0x80: "nonfinite", 0x100: "fallback",
 }
 
 

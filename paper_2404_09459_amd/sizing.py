@@ -126,6 +126,13 @@ def pair_specs(npairs, seed, m_range=(500, 3000), n_range=(100, 400), r_range=(5
     return out
 
 
+def make_pair_device(spec, device):
+    """A pair of the spec drawn on the device (large held-out pairs)."""
+    j = np.arange(spec["r"])
+    return I.lowrank_pair_device(spec["m"], spec["p"], spec["n"], spec["r"], spec["d1"] ** j, spec["d2"] ** j,
+                                 spec["seed"], spec["nu"], device)
+
+
 def make_pair(spec):
     j = np.arange(spec["r"])
     return I.lowrank_pair(spec["m"], spec["p"], spec["n"], spec["r"], spec["d1"] ** j, spec["d2"] ** j,
@@ -140,19 +147,35 @@ def _pinned(ref, k, nu):
     return np.where(weak >= 10 * nu)[0]
 
 
-def _run(g1, g2, k, l, q, seed, precision):
-    """One fixed-size run with a plan of its own (freed afterwards)."""
+def _run(g1, g2, k, l, q, seed, precision, timed=False, sizing="fixed", tol=0.0, block=0, lmax=0,
+         model=None):
+    """One run with a plan of its own (freed afterwards).  timed=True also
+    returns the mean wall time (ms) of two more runs, HIP events around each
+    on the device's stream, after the first."""
     torch = _torch()
     m, n = g1.shape
     p = g2.shape[0]
     dt = R.F64 if g1.dtype == torch.float64 else R.F32
-    plan = R.Plan(R.make_desc(m, p, n, k, l - k, q, seed, dt, precision), g1.device)
+    plan = R.Plan(R.make_desc(m, p, n, k, l - k, q, seed, dt, precision, sizing, "truncated", tol, block, lmax),
+                  g1.device)
+    if model is not None:
+        R.check(R.lib().rgsvd_set_sizing_model(plan.h, R._ptr(model), R._stream(g1.device)), "set model")
     o = R.alloc_outputs(plan.t, m, p, n, plan.l1 + plan.l2, g1.device, uvr=(precision == "fp64"))
     R.run(plan, g1, g2, o)
     torch.cuda.synchronize()
+    ms = None
+    if timed:
+        st = torch.cuda.current_stream(g1.device)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(2):
+            R.run(plan, g1, g2, o)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 2
     out = {kk: v.cpu().numpy() for kk, v in o.items() if kk not in ("Ut", "Vt")}
     del plan
-    return out
+    return (out, ms) if timed else out
 
 
 def l_grid(k, cap):
@@ -160,22 +183,27 @@ def l_grid(k, cap):
 
 
 def passes(got, ref, idx, tol=TOL_THETA):
+    """Whether the pinned angular distances are within tol; None when no
+    index is pinned (nothing to judge: such pairs are counted apart)."""
     if len(idx) == 0:
-        return True
+        return None
     return float(np.max(np.abs(got["theta"][idx] - ref["theta"][idx]))) <= tol
 
 
 def label(g1, g2, spec, seed=1, precision="mixed", margin=LABEL_MARGIN):
-    """(l, q, reference) of a device pair: the cheapest grid point whose
-    angular error is within margin * TOL_THETA.  The network regresses onto
-    these points; a label on the pass boundary itself would put about half
-    of the mispredicted pairs on the failing side, so the margin keeps the
-    regression's scatter inside the tolerance."""
+    """(l, q, reference, pinned indices) of a device pair: the cheapest grid
+    point whose angular error is within margin * TOL_THETA.  The network
+    regresses onto these points; a label on the pass boundary itself would
+    put about half of the mispredicted pairs on the failing side, so the
+    margin keeps the regression's scatter inside the tolerance.  A pair with
+    no pinned index has no label (l = q = None)."""
     k, nu = spec["k"], spec["nu"]
     cap = min(spec["m"], spec["p"], spec["n"], 224)
     lref = min(2 * k + 50, cap)
     ref = _run(g1, g2, k, lref, 4, seed, "fp64")
     idx = _pinned(ref, k, nu)
+    if len(idx) == 0:
+        return None, None, ref, idx
     grid = l_grid(k, cap)
     for q in GRID_Q:
         for l in grid:
