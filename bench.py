@@ -9,7 +9,9 @@ Default workload: G1 100000 x 2000, G2 80000 x 2000 FP32, shared rank 200,
 decay 0.97 per index, spectral noise floor 1e-3; k = 200, oversampling 20,
 two power iterations.  The headline `value` is the mixed-precision path
 (BF16 MFMA sketch and first power iteration, FP32 last iteration and
-projection, FP64 small step); the FP32 and FP64 paths are timed beside it.
+projection, FP64 small step); the FP32 and FP64 paths are timed beside it,
+and so is the mixed path with learned sizing (the sizing network trained
+first on small pairs that the method labels on the GPU).
 Every path is checked against the FP64 CPU oracle run on the same pair with
 the same Omega (angular distances within 1e-4 on the gap-separated indices,
 entropies within 1e-5).  The literal workload gives G1 and G2 one decay, so
@@ -263,6 +265,54 @@ def time_path(R, torch, dev, G1, G2, m, p, n, k, o, q, seed, dt, prec, args):
                 info=got["info"].tolist(), tune=tune)
 
 
+def train_sizing_network(dev):
+    """The sizing network trained as the library's gain test trains it: 176
+    pairs of the training recipe (sizing.TRAIN_RANGES, seed 21) labelled on
+    the GPU by the method itself, unpinned pairs left out, 600 full-batch
+    Adam steps of the library's HIP kernels.  Returns (params, training
+    pairs, seconds)."""
+    import torch
+    from paper_2404_09459_amd import sizing as S
+    t0 = time.time()
+    X, T = [], []
+    for s in S.pair_specs(176, seed=21, **S.TRAIN_RANGES):
+        G1, G2 = S.make_pair(s)
+        g1, g2 = torch.from_numpy(G1).to(dev), torch.from_numpy(G2).to(dev)
+        l, q, _, _ = S.label(g1, g2, s)
+        if l is None:
+            continue
+        X.append(S.probe_features(g1, g2, 1, precision="mixed").cpu().numpy())
+        T.append(S.targets(s["k"], l, q))
+    X = torch.tensor(np.array(X), dtype=torch.float32, device=dev)
+    T = torch.tensor(np.array(T), dtype=torch.float32, device=dev)
+    params, _ = S.train(X, T, dev, epochs=600, lr=3e-3, seed=2)
+    torch.cuda.synchronize()
+    return params, len(X), time.time() - t0
+
+
+def time_learned(R, torch, dev, G1, G2, m, p, n, k, seed, dt, params, args):
+    """Warm up and time the mixed-precision learned-sizing path."""
+    plan = R.Plan(R.make_desc(m, p, n, k, 0, 0, seed, dt, "mixed", "learned"), dev)
+    R.check(R.lib().rgsvd_set_sizing_model(plan.h, R._ptr(params), R._stream(dev)), "set model")
+    outs = R.alloc_outputs(plan.t, m, p, n, plan.l1 + plan.l2, dev, uvr=True)
+    for _ in range(max(1, args.warmup)):
+        R.run(plan, G1, G2, outs)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream(dev)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(args.steps):
+        R.run(plan, G1, G2, outs)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    got = {kk: v.cpu().numpy() for kk, v in outs.items()}
+    log(f"[bench] mixed + learned: {ms:.3f} ms/pair ({1000 / ms:.1f} pairs/s); info {got['info'].tolist()}")
+    del plan
+    return dict(ms=ms, got=got, info=got["info"].tolist())
+
+
 def gate_of(e, k):
     """1e-4 on the pinned angular distances; 1e-5 on the entropies when every
     pair is pinned (D sums over all t pairs)."""
@@ -329,6 +379,8 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-single-thread", action="store_true", help="skip the one-thread oracle timing")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile-shape autotuner")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the mixed + learned-sizing leg (it trains the sizing network first)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain elementwise copy of MIB MiB (read + write) for "
                          "calibrating hardware byte counters")
@@ -363,6 +415,15 @@ def main():
 
     precs = [x for x in args.precisions.split(",") if x]
     res = {prec: time_path(R, torch, dev, G1, G2, m, p, n, k, o, q, seed, dt, prec, args) for prec in precs}
+    learned, net = None, None
+    if not args.no_learned and esz == 4:
+        params, ntrain, tsec = train_sizing_network(dev)
+        net = {"training_pairs": ntrain, "training_seconds": round(tsec, 1),
+               "recipe": "176 pairs m, p in [1000, 4000], n in [200, 1000], rank 5..220, last-component magnitude "
+                         "1e-4..0.3, noise floor 1e-6..1e-2, labelled on the GPU "
+                         "by the method, unpinned left out; 600 Adam steps of the HIP MLP kernels"}
+        log(f"[bench] sizing network trained on {ntrain} pairs in {tsec:.1f}s")
+        learned = time_learned(R, torch, dev, G1, G2, m, p, n, k, seed, dt, params, args)
 
     if args.calib_copy > 0:
         nel = args.calib_copy * (1 << 20) // 4
@@ -389,6 +450,19 @@ def main():
             t1, _ = time_oracle(G1d, G2d, k, o, q, seed, 1, threads=1)
             cpu["single_thread"] = {"value": 1.0 / t1, "unit": "pairs/s", "cores": 1,
                                     "sample": f"1 full pair ({t1:.2f}s), BLAS/LAPACK limited to one thread"}
+        if learned is not None:
+            # the learned sizing picks its own (l, q): it is judged as its
+            # labels are, against a converged run of the method (the oracle
+            # at l = min(2k + 50, 224), q = 4) on the components above the
+            # noise floor, and the default sizing beside it on the same footing
+            lc = min(2 * k + 50, m, p, n, 224)
+            refc = O_rgsvd(G1d, G2d, k, lc - k, 4, seed)
+            idc = pinned(refc, k, nu)
+            el = errors(learned["got"], refc, idc)
+            ed0 = errors(res["mixed"]["got"], refc, idc) if "mixed" in res else None
+            learned["converged"] = {"reference": f"oracle FP64, l={lc}, q=4", "errors_learned": el,
+                                    "errors_mixed_default_sizing": ed0, "gate_passed": gate_of(el, k)}
+            log(f"[bench] learned vs converged: {el}")
         del G1d, G2d
         # the same shapes with distinct decays: the mixed path against the
         # full-size oracle on spread-out GSVs
@@ -416,6 +490,12 @@ def main():
                        "errors_vs_oracle": e, "gate_passed": gate_of(e, k) if e else None,
                        "info": r["info"], "autotune": r["tune"],
                        "stage_ms": {kk: round(v[0], 4) for kk, v in r["stages"].items()}}
+    if learned is not None:
+        e = errors(learned["got"], ref, pinned(ref, k, nu)) if ref is not None else None
+        paths["mixed_learned"] = {"pairs_per_s": 1000.0 / learned["ms"], "ms_per_pair": learned["ms"],
+                                  "errors_vs_oracle": e, "gate_passed": gate_of(e, k) if e else None,
+                                  "info": learned["info"], "l_q_chosen": [learned["info"][1], learned["info"][3]],
+                                  "vs_converged": learned.get("converged"), "sizing_network": net}
     # dominant kernel of the headline path: each stage's event time carries
     # the cost of an empty launch between events (the smallest stage time),
     # so stages are ranked by their time above it
@@ -446,6 +526,8 @@ def main():
         "accuracy_gate_passed": gate,
         "sketch_tflops": paths[flag]["sketch_tflops"],
         "mixed_vs_fp64_speedup": (res["fp64"]["ms"] / res["mixed"]["ms"]) if {"mixed", "fp64"} <= set(res) else None,
+        "mixed_learned_vs_fp64_speedup": (res["fp64"]["ms"] / learned["ms"])
+        if (learned is not None and "fp64" in res) else None,
         "roofline": roof,
         "roofline_sketch": roof_sketch,
         "cpu_baseline": cpu,

@@ -852,7 +852,15 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
       base = bj_sweeps(S, J.tol, more);
     }
     const int tt = t < rank ? t : rank;
-    sw1 = base + (more ? jacobi_any(F, N, N, rank, J.tol, J.maxsweep - base, tt, sh, lds, cap) : 0);
+    // the block sweeps are the whole budget of a factor that needed the
+    // block Jacobi: one that has not settled after them has no gap at t (the
+    // dominant subspace is not determined) and keeps FLAG_JACOBI_M, rather
+    // than running single-workgroup sweeps of tens of ms each
+    if (stage == 2 && more) {
+      sw1 = J.maxsweep + 1;
+    } else {
+      sw1 = base + (more ? jacobi_any(F, N, N, rank, J.tol, J.maxsweep - base, tt, sh, lds, cap) : 0);
+    }
     // column norms of F: one wave per column, lanes striding its rows (one
     // thread walking a whole column serialises its loads)
     for (int c = tid >> 6; c < N; c += 16) {

@@ -22,6 +22,14 @@ from . import rgsvd as R
 GRID_Q = (0, 1, 2, 3)
 TOL_THETA = 1e-4
 LABEL_MARGIN = 0.1
+# training pairs: the learned-sizing workload's ranks (up to 220 shared
+# components, n up to 1000) on fewer rows (m, p <= 4000), so that labelling
+# stays a few seconds of GPU time while the probe spectra cover the
+# workload's (a 16-column probe of a rank-200 pair is nearly flat).  The
+# decays follow from the magnitude of the last shared component, so that
+# about half of the pairs keep all r components above the noise floor
+# (those are the pairs with a gap at k, the ones the labels can judge)
+TRAIN_RANGES = dict(m_range=(1000, 4000), n_range=(200, 1000), r_range=(5, 220), tail_range=(1e-4, 0.3))
 
 
 def _torch():
@@ -105,19 +113,25 @@ def train(X, T, device, epochs=400, lr=3e-3, seed=0):
 
 # --------------------------------------------------------------- pairs ---
 def pair_specs(npairs, seed, m_range=(500, 3000), n_range=(100, 400), r_range=(5, 40),
-               d_range=(0.5, 0.99), nu_range=(1e-6, 1e-2)):
+               d_range=(0.5, 0.99), nu_range=(1e-6, 1e-2), tail_range=None):
     """Training / held-out pairs shaped like the learned-sizing workload
     (scaled down): shared rank r, decays d1, d2, spectral noise floor nu
-    (log-uniform); k = the number of shared components above 10 nu (>= 2)."""
+    (log-uniform); k = the number of shared components above 10 nu (>= 2).
+    With tail_range the decays are d_i = tau_i^(1/(r-1)) for tail magnitudes
+    tau_i drawn log-uniform from it, else uniform from d_range."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(npairs):
         m = int(rng.integers(m_range[0], m_range[1] + 1))
         p = int(rng.integers(m_range[0], m_range[1] + 1))
         n = int(rng.integers(n_range[0], n_range[1] + 1))
-        r = int(rng.integers(r_range[0], min(r_range[1], n // 4) + 1))
-        d1 = float(rng.uniform(*d_range))
-        d2 = float(rng.uniform(*d_range))
+        r = int(rng.integers(r_range[0], max(r_range[0], min(r_range[1], n // 4)) + 1))
+        if tail_range is None:
+            d1 = float(rng.uniform(*d_range))
+            d2 = float(rng.uniform(*d_range))
+        else:
+            lo, hi = np.log(tail_range[0]), np.log(tail_range[1])
+            d1, d2 = (float(np.exp(rng.uniform(lo, hi)) ** (1.0 / max(1, r - 1))) for _ in range(2))
         nu = float(np.exp(rng.uniform(np.log(nu_range[0]), np.log(nu_range[1]))))
         j = np.arange(r)
         mag = np.minimum(d1 ** j, d2 ** j)
