@@ -38,12 +38,13 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TF = {"fp64": 78.6, "fp32": 157.3, "mixed": 2516.6}
 # 256 CUs x 4 SIMDs x 16 FP64 FMA lanes x 2 flops x 2.4 GHz
 FP64_VEC_PEAK_TF = 78.6
-# HBM bytes per launch on the 20000/15000 x 5000 workload, from FETCH_SIZE and
-# WRITE_SIZE scaled by a copy kernel of known size (profiles/hbm_counters_*.md):
-# the sketch kernel, k_small (mean of its two launches), k_bjround
-TRAFFIC_SKETCH = 755.5e6
-TRAFFIC_SMALL = 1.42e6
-TRAFFIC_BJROUND = 0.56e6
+# HBM bytes per launch from FETCH_SIZE and WRITE_SIZE, each scaled by what it
+# reads for a copy kernel of known size (profiles/hbm_counters_*.md), keyed by
+# workload: the mixed sketch pass (k_nn, BF16) and the block Jacobi launches
+# (k_bjinit + k_bjround, averaged over the launches of a run).  Kernels changed
+# since their counters were taken have no entry (traffic null).
+TRAFFIC = {"large": {"sketch": 1.659e9, "bjacobi": 1.956e6},
+           "medium": {"bjacobi": 0.56e6}}
 
 
 def log(*a):
@@ -324,7 +325,6 @@ def roofline_of(dom_tag, dom_ms, dom_cnt, info, m, p, n, k, l, esz, flag, worklo
     avg_ms = dom_ms / dom_cnt
     gbytes = (m + p) * n * esz
     N = 2 * l
-    medium = workload_name == "medium"
     if dom_tag == "bjacobi":
         # block one-sided Jacobi on the factor of M (order N): a sweep visits
         # the N (N - 1) / 2 column pairs, each with three length-N inner
@@ -333,7 +333,7 @@ def roofline_of(dom_tag, dom_ms, dom_cnt, info, m, p, n, k, l, esz, flag, worklo
         sw1 = int(info[5])
         flops = sw1 * 6.0 * N * N * (N - 1)
         roof = {"bound": "alu", "achieved": flops / (dom_ms * 1e-3) / 1e12, "peak": FP64_VEC_PEAK_TF,
-                "unit": "TFLOP/s", "traffic": TRAFFIC_BJROUND if medium else None}
+                "unit": "TFLOP/s", "traffic": TRAFFIC.get(workload_name, {}).get("bjacobi")}
     elif dom_tag == "small":
         # k_small (its launches summed): pivoted Cholesky of M (N^3 / 3),
         # H = L1^T L1 (l t (t + 1)), pivoted Cholesky of H (t^3 / 3), the
@@ -343,7 +343,7 @@ def roofline_of(dom_tag, dom_ms, dom_cnt, info, m, p, n, k, l, esz, flag, worklo
         sw2 = int(info[6])
         flops = N ** 3 / 3.0 + l * t * (t + 1.0) + t ** 3 / 3.0 + sw2 * 6.0 * t * t * (t - 1) + 2.0 * N * t * t
         roof = {"bound": "alu", "achieved": flops / (dom_ms * 1e-3) / 1e12, "peak": FP64_VEC_PEAK_TF,
-                "unit": "TFLOP/s", "traffic": TRAFFIC_SMALL if medium else None}
+                "unit": "TFLOP/s", "traffic": None}
     elif dom_tag == "chol":
         # Cholesky and inverse of the l x l Gram of both sides per launch:
         # l^3 / 3 + l^3 / 3 flops each
@@ -506,9 +506,10 @@ def main():
     # the streaming sketch kernel beside it: one read of G1 and G2 per launch
     gbytes = (m + p) * n * esz
     sk_ms = res[flag]["sketch_ms"]
-    roof_sketch = {"bound": "hbm", "kernel": "k_gw", "achieved": gbytes / (sk_ms * 1e-3) / 1e9,
+    roof_sketch = {"bound": "hbm", "kernel": "k_nn" if flag == "mixed" else "k_gw",
+                   "achieved": gbytes / (sk_ms * 1e-3) / 1e9,
                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": gbytes / (sk_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                   "traffic": TRAFFIC_SKETCH if args.workload == "medium" else None,
+                   "traffic": TRAFFIC.get(args.workload, {}).get("sketch") if flag == "mixed" else None,
                    "tflops": sk_flops / (sk_ms * 1e-3) / 1e12,
                    "bf16_mfma_frac": sk_flops / (sk_ms * 1e-3) / 1e12 / MFMA_PEAK_TF["mixed"]}
     gate = None
