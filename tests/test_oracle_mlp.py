@@ -58,24 +58,52 @@ def test_training_reduces_loss():
 
 # ------------------------------------------------------- sizing features ---
 def test_probe_features_scale_invariant_and_rank_revealing():
-    """log10(sigma_j / sigma_1) of the probe sketch: unchanged by scaling G,
-    first entry 0, non-increasing, and a rank-r matrix (r < 16) shows a drop
-    to the floor region after r values (the probe sketch has rank r)."""
+    """Both halves are log10 ratios: unchanged by scaling G.  The probe half
+    (s_2, s_4, ..., s_16 over s_1) is non-increasing; a rank-r matrix
+    (r < 16) shows a drop to the floor after its r-th singular value in the
+    probe and after its r-th sketch column in the profile (the sketch has
+    rank r, so later columns lie in the span of the first r)."""
     from oracle.sizing import features
     rng = np.random.default_rng(3)
     m, n, r = 300, 120, 6
     G1 = rng.standard_normal((m, r)) @ rng.standard_normal((r, n))
     G2 = rng.standard_normal((250, n))
-    f = features(G1, G2, 9)
-    f2 = features(7.5 * G1, 0.01 * G2, 9)
+    k, cap = 8, 120                      # grid {12, 16, 24, 40}: L = 40, profile at 2, 4, 6, 8, 12, 16, 24, 40
+    f = features(G1, G2, 9, k, cap)
+    f2 = features(7.5 * G1, 0.01 * G2, 9, k, cap)
     assert f.shape == (32,)
     live = f > -8                        # entries above the floor
     assert np.array_equal(live, f2 > -8)
     assert np.allclose(f[live], f2[live], atol=1e-12)
-    assert f[0] == 0.0 and f[16] == 0.0
-    assert np.all(np.diff(f[:16]) <= 1e-12) and np.all(np.diff(f[16:]) <= 1e-12)
-    assert f[r - 1] > -3 and np.all(f[r:16] == -8.0)    # rank 6: the rest is at the floor
-    assert np.all(f[16:] > -3)                           # full-rank Gaussian G2
+    assert np.all(np.diff(f[:8]) <= 1e-12) and np.all(np.diff(f[16:24]) <= 1e-12)
+    assert np.all(f[:3] > -3) and np.all(f[3:8] == -8.0)        # probe: s_2, s_4, s_6 live, s_8.. floor
+    assert np.all(f[8:11] > -3) and np.all(f[11:16] == -8.0)    # profile: columns 2, 4, 6 live, 8.. floor
+    assert np.all(f[16:] > -3)                                   # full-rank Gaussian G2
+
+
+def test_sketch_profile_is_distance_to_previous_columns():
+    """rho_j is the distance of sketch column j from the span of columns
+    1..j-1: brute force by least squares on each prefix."""
+    from oracle.philox import gaussian_matrix
+    from oracle.sizing import sketch_profile
+    rng = np.random.default_rng(5)
+    G = rng.standard_normal((90, 40)) * (0.8 ** np.arange(40))[None, :]
+    L = 12
+    rho = sketch_profile(G, 6, 2, L)
+    S = G @ gaussian_matrix(6, 2, 40, 0, L)
+    ref = [np.linalg.norm(S[:, 0])]
+    for j in range(1, L):
+        c, *_ = np.linalg.lstsq(S[:, :j], S[:, j], rcond=None)
+        ref.append(np.linalg.norm(S[:, j] - S[:, :j] @ c))
+    assert np.allclose(rho, ref, rtol=1e-10)
+
+
+def test_profile_positions():
+    from oracle.sizing import profile_positions
+    assert profile_positions(20, 52) == [5, 10, 15, 20, 24, 28, 36, 52]
+    assert profile_positions(200, 224) == [50, 100, 150, 200, 204, 208, 216, 224]
+    assert profile_positions(3, 6) == [1, 2, 3, 3, 6, 6, 6, 6]
+    assert profile_positions(1, 2) == [1, 1, 1, 1, 2, 2, 2, 2]
 
 
 def test_probe_spectrum_of_orthonormal_rows_is_gaussian_block():
