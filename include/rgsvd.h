@@ -255,10 +255,14 @@ int rgsvd_batch_autotune(rgsvd_plan_t plan, const rgsvd_pair_io* io, void* works
 /* ---------------------------------------------------- sizing network ---- */
 /* 32-64-64-2 ReLU MLP in FP32.  Parameter layout: W1 (64x32), b1 (64),
  * W2 (64x64), b2 (64), W3 (2x64), b3 (2), row-major W[out][in],
- * concatenated (RGSVD_MLP_PARAMS floats).  Features (32): log10(s_i/s_1)
- * of the 16 singular values of the probe sketches G1 Omega[:, :16] and
- * G2 Omega[:, :16].  Outputs: regression targets (log2(l / k), q) of the
- * sketch width l and the power count q. */
+ * concatenated (RGSVD_MLP_PARAMS floats).  Features (32, G1's 16 then
+ * G2's, each a log10 ratio floored at -8): log10(s_j / s_1) for
+ * j = 2, 4, ..., 16 of the singular values of the probe sketch
+ * G Omega[:, :16], then log10(rho_j / rho_1) at the columns ceil(k/4),
+ * ceil(k/2), ceil(3k/4), k, k+4, k+8, k+16 and L (clamped to [1, L]) of the
+ * sketch G Omega[:, :L] at the widest grid width L, rho_j the j-th diagonal
+ * entry of its CholeskyQR factor R.  Outputs: regression targets
+ * (log2(l / k), q) of the sketch width l and the power count q. */
 #define RGSVD_MLP_PARAMS 6402
 #define RGSVD_MLP_IN 32
 #define RGSVD_MLP_OUT 2
@@ -280,13 +284,16 @@ int rgsvd_mlp_adam(float* params, const float* grad, float* m, float* v, int32_t
  * own device buffer on `stream`). */
 int rgsvd_set_sizing_model(rgsvd_plan_t plan, const float* params, void* stream);
 /* Probe features of a pair for the sizing network (enqueued on `stream`):
- * the 32 features above, each log10(s_i / s_1) floored at -8 (the FP64 Gram
- * of the probe resolves s_i / s_1 down to about 1e-8), into feat (device,
- * 32 floats).  The probe is the 16-column sketch in the plan's own sketch
- * arithmetic (BF16 for mixed plans), the same numbers a learned run of that
- * precision takes from its sketch's first 16 columns.  Uses the plan's
- * shapes, storage type and seed and its workspace (any sizing mode;
- * single-pair plans). */
+ * the 32 features above (the floor at -8 is what an FP64 Gram of a sketch
+ * resolves), into feat (device, 32 floats).  Runs the head of a learned
+ * run: the sketch at the widest grid width L of the plan's k and capacity,
+ * in the plan's own sketch arithmetic (BF16 for mixed plans), its first 16
+ * columns as the probe, and the first CholeskyQR pass over all L columns
+ * for the profile, so a learned plan of the same shapes, precision, k and
+ * seed gets the same numbers in its own runs.  Uses the plan's shapes,
+ * storage type and seed and its workspace (any sizing mode; single-pair
+ * plans); the grid width follows the plan's capacity, so features for a
+ * learned plan are taken with a learned plan. */
 int rgsvd_probe_features(rgsvd_plan_t plan, const void* G1, int64_t ld1, const void* G2, int64_t ld2,
                          void* workspace, float* feat, void* stream);
 

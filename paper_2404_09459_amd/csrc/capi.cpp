@@ -48,7 +48,7 @@ inline int ct_of(int L) {
 }
 
 enum Kind { K_ZERO, K_COPY, K_GEN, K_AB, K_GRAM, K_RED, K_CHOL, K_SMALL, K_SIGN, K_SCALE, K_GW, K_GTQ,
-            K_PACK, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP, K_BJINIT, K_BJROUND, K_GW4, K_ZEROG, K_NN };
+            K_PACK, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP, K_BJINIT, K_BJROUND, K_GW4, K_ZEROG, K_NN, K_PROF };
 
 enum Tag { T_ZERO, T_COPY, T_GEN, T_NN, T_TN, T_RED, T_GRAM, T_CHOL, T_SX, T_SMALL, T_RECOVER, T_SIGN,
            T_MGRAM, T_BJAC, T_NTAGS };
@@ -584,9 +584,12 @@ int build(rgsvd_plan_s* P, void* ws) {
   if (part == rgsvd_plan_s::FIXED || part == rgsvd_plan_s::L_HEAD)
     add_nn(mixed ? PBF : prec);   // sketch
   if (part == rgsvd_plan_s::L_HEAD) {
-    // probe features from the sketch's first 16 columns (Omega's global
-    // columns make them the 16-column sketch): their FP64 Gram, its
-    // eigenvalues, log10 of the normalised singular values; then the network
+    // features: the probe (the sketch's first 16 columns, which Omega's
+    // global columns make the 16-column sketch): their FP64 Gram, its
+    // eigenvalues, log10 of the normalised singular values; then the first
+    // CholeskyQR pass over the whole sketch, whose factor's diagonal is the
+    // profile (its Q stays in Yt: every tail starts from its prefix); then
+    // the network
     std::vector<GramJob> gj; std::vector<int> gtl;
     std::vector<RedJob> rj; std::vector<int> rtl;
     std::vector<FeatJob> fj; std::vector<int> ftl;
@@ -607,6 +610,13 @@ int build(rgsvd_plan_s* P, void* ws) {
     Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = wt; gs.tag = T_GRAM;
     Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.ta = 0; r.td = 0; r.tag = T_RED;
     B.add(K_FEAT, fj, ftl).tag = T_SMALL;
+    add_orth(true, 1);
+    std::vector<ProfJob> pj; std::vector<int> ptl;
+    for (size_t i = 0; i < S.size(); ++i)
+      pj.push_back(ProfJob{(const double*)WS(ws, S[i].sinv), (float*)WS(ws, P->off_feat) + 16 * i + 8, P->npadG,
+                           S[i].l, (int)P->pairs[S[i].pair].k, 0});
+    ptl.assign(pj.size(), 1);
+    B.add(K_PROF, pj, ptl).tag = T_SMALL;
     if (!P->probe_only) {
       if (P->mlp) { Stage m; m.kind = K_MLP; m.tag = T_SMALL; P->stages.push_back(m); }
       if (P->judge) add_gnorm();
@@ -628,7 +638,10 @@ int build(rgsvd_plan_s* P, void* ws) {
   }
   if (part == rgsvd_plan_s::FIXED || part == rgsvd_plan_s::L_TAIL) {
     const int qmax = [&] { int q = 0; for (auto& pr : P->pairs) q = std::max(q, pr.q); return q; }();
-    add_orth(true, qmax == 0 ? 2 : 1);
+    // a learned tail starts after the head's first pass at the widest width
+    // (the prefix of its Q is the first pass at width l)
+    const int first = (qmax == 0 ? 2 : 1) - (part == rgsvd_plan_s::L_TAIL ? 1 : 0);
+    if (first > 0) add_orth(true, first);
     for (int it = 1; it <= qmax; ++it) {
       int p = mixed ? (it < qmax ? PBF : P32) : prec;
       add_tn(p);
@@ -991,8 +1004,8 @@ __global__ void k_sumfin(const SumsqFin* j, int nj) {
 
 // Probe features: eigenvalues of the 16 x 16 probe Gram by two-sided
 // Jacobi in one wave, sigma_j = sqrt(lambda_j) in descending order, then
-// log10(sigma_j / sigma_1) floored at -8 (the Gram resolves sigma_j / sigma_1
-// down to about sqrt(eps)).  Parallel ordering: each of the 15 rounds of a
+// log10(sigma_j / sigma_1) for j = 2, 4, ..., 16, floored at -8 (the Gram
+// resolves sigma_j / sigma_1 down to about sqrt(eps)).  Parallel ordering: each of the 15 rounds of a
 // sweep turns 8 disjoint pairs (round-robin over the 16 indices), lanes 0..7
 // forming the rotations, then all 64 lanes applying them to the columns and
 // then to the rows of the matrix (held in LDS).  Sweeps end when the
@@ -1061,8 +1074,29 @@ __global__ __launch_bounds__(64) void k_feat(const FeatJob* j, int nj) {
   for (int i = 0; i < 16; ++i) sv[i] = sqrt(fmax(a[i][i], 0.0));
   for (int i = 1; i < 16; ++i)
     for (int k = i; k > 0 && sv[k] > sv[k - 1]; --k) { const double t = sv[k]; sv[k] = sv[k - 1]; sv[k - 1] = t; }
-  for (int i = 0; i < 16; ++i)
-    J.out[i] = (float)((sv[0] > 0.0 && sv[i] > 0.0) ? fmax(log10(sv[i] / sv[0]), -8.0) : -8.0);
+  // s_2, s_4, ..., s_16 over s_1
+  for (int i = 0; i < 8; ++i) {
+    const double v = sv[2 * i + 1];
+    J.out[i] = (float)((sv[0] > 0.0 && v > 0.0) ? fmax(log10(v / sv[0]), -8.0) : -8.0);
+  }
+}
+
+// Sketch profile: rho_j = R_jj of the Cholesky factor of the widest
+// sketch's Gram (the distance of sketch column j from the span of the ones
+// before it) is 1 / X_jj of X = R^{-T}; log10(rho_j / rho_1) floored at -8
+// at the columns ceil(k/4), ceil(k/2), ceil(3k/4), k, k+4, k+8, k+16, L
+// (1-based, clamped to [1, L]).  A dropped or failed pivot (X_jj not a
+// positive finite number) reads as the floor.
+__global__ __launch_bounds__(64) void k_prof(const ProfJob* j, int nj) {
+  const ProfJob J = j[blockIdx.x];
+  const int i = threadIdx.x;
+  if (i >= 8) return;
+  const int k = J.k, L = J.L;
+  const int raw[8] = {(k + 3) / 4, (k + 1) / 2, (3 * k + 3) / 4, k, k + 4, k + 8, k + 16, L};
+  const int pos = min(max(raw[i], 1), L);
+  const double x1 = J.sinv[0], xj = J.sinv[(int64_t)(pos - 1) * (J.ld + 1)];
+  const bool ok = isfinite(x1) && isfinite(xj) && x1 > 0.0 && xj > 0.0;
+  J.out[i] = (float)(ok ? fmax(log10(x1 / xj), -8.0) : -8.0);
 }
 
 int enqueue_list(rgsvd_plan_s* P, void* ws, hipStream_t st, const std::vector<Stage>& list) {
@@ -1106,6 +1140,7 @@ int enqueue_list(rgsvd_plan_s* P, void* ws, hipStream_t st, const std::vector<St
         hipLaunchKernelGGL(k_sumfin, dim3((s.nj + 63) / 64), dim3(64), 0, st, (const SumsqFin*)j, s.nj);
         break;
       case K_FEAT: hipLaunchKernelGGL(k_feat, dim3(s.nj), dim3(64), 0, st, (const FeatJob*)j, s.nj); break;
+      case K_PROF: hipLaunchKernelGGL(k_prof, dim3(s.nj), dim3(64), 0, st, (const ProfJob*)j, s.nj); break;
       case K_MLP: {
         float* f = (float*)((char*)ws + P->off_feat);
         rgsvd_mlp_forward(P->mlp, f, 1, f + RGSVD_MLP_IN, f + RGSVD_MLP_IN + RGSVD_MLP_OUT, st);
@@ -1318,13 +1353,26 @@ void set_width(rgsvd_plan_s* P, int l, int q) {
   for (auto& pr : P->pairs) { pr.l1 = pr.l2 = l; pr.q = q; }
 }
 
-// The 16-column sketch and its features alone (rgsvd_probe_features): the
-// head of a learned run at width 16, in the plan's sketch precision, so the
-// features equal those a learned run computes from its own sketch.
+// The sketch widths a sizing network can pick: {k+4, k+8, k+16, k+32, 2k},
+// capped at cap, ascending and distinct.
+std::vector<int> l_grid(int k, int cap) {
+  std::vector<int> grid;
+  for (int v : {k + 4, k + 8, k + 16, k + 32, 2 * k}) { v = std::min(v, cap); if (v >= k) grid.push_back(v); }
+  std::sort(grid.begin(), grid.end());
+  grid.erase(std::unique(grid.begin(), grid.end()), grid.end());
+  return grid;
+}
+
+// The features alone (rgsvd_probe_features): the head of a learned run
+// (the sketch at the widest grid width of the plan's k and capacity, the
+// probe, the first CholeskyQR pass and the profile) in the plan's sketch
+// precision, so the features equal those a learned run computes from its
+// own sketch.
 int run_probe(rgsvd_plan_s* P, void* ws, hipStream_t st) {
   const int keep = P->lmaxw;
-  P->lmaxw = 16;
-  set_width(P, 16, 0);
+  const PairLay& pr = P->pairs[0];
+  P->lmaxw = l_grid((int)pr.k, std::min(pr.l1cap, pr.l2cap)).back();
+  set_width(P, P->lmaxw, 0);
   P->part = rgsvd_plan_s::L_HEAD;
   P->probe_only = true;
   int rc = build(P, ws);
@@ -1336,16 +1384,6 @@ int run_probe(rgsvd_plan_s* P, void* ws, hipStream_t st) {
   if (!rc) rc = upload(P, ws, st);
   if (!rc) rc = enqueue(P, ws, st);
   return rc;
-}
-
-// The sketch widths a sizing network can pick: {k+4, k+8, k+16, k+32, 2k},
-// capped at cap, ascending and distinct.
-std::vector<int> l_grid(int k, int cap) {
-  std::vector<int> grid;
-  for (int v : {k + 4, k + 8, k + 16, k + 32, 2 * k}) { v = std::min(v, cap); if (v >= k) grid.push_back(v); }
-  std::sort(grid.begin(), grid.end());
-  grid.erase(std::unique(grid.begin(), grid.end()), grid.end());
-  return grid;
 }
 
 // Sketch sizes from the network output (log2(l / k), q): the smallest l of
@@ -1857,7 +1895,7 @@ extern "C" int rgsvd_probe_features(rgsvd_plan_t P, const void* G1, int64_t ld1,
   P->sides[0].G = G1; P->sides[0].ldg = ld1;
   P->sides[1].G = G2; P->sides[1].ldg = ld2;
   P->bound = false;
-  // restore the plan's own widths afterwards (the probe runs at width 16)
+  // restore the plan's own widths afterwards (the probe runs at the widest grid width)
   std::vector<std::pair<int, int>> keep;
   for (auto& s : P->sides) keep.push_back({s.l, s.L});
   const int l1 = pr.l1, l2 = pr.l2, q = pr.q;

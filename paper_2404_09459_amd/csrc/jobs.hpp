@@ -101,4 +101,11 @@ struct FeatJob {
   int32_t ldg, pad;
 };
 
+// Sketch profile: the diagonal of X = R^{-T} from the CholeskyQR Cholesky of
+// the widest sketch (ld x ld, order L); k the target rank.
+struct ProfJob {
+  const double* sinv; float* out;
+  int32_t ld, L, k, pad;
+};
+
 }  // namespace rg

@@ -1,8 +1,10 @@
 """Learned sketch sizing: probe features, labels from the method itself, and
 training of the 32-64-64-2 network with the library's own HIP kernels.
 
-The network reads the 32 probe features of a pair (log10 of the normalised
-singular values of G_i Omega[:, :16], i = 1, 2) and regresses
+The network reads the 32 features of a pair (per matrix: eight normalised
+singular values of the 16-column probe G_i Omega[:, :16] and eight entries of
+the R-diagonal profile of the widest sketch at columns placed relative to k,
+as log10 ratios) and regresses
 (log2(l / k), q): the sketch width relative to the target rank and the power
 count.  A pair's label is the cheapest point of the grid
 l in {k+4, k+8, k+16, k+32, 2k} x q in {0..3} (fewest passes over G, then the
@@ -28,8 +30,19 @@ LABEL_MARGIN = 0.1
 # workload's (a 16-column probe of a rank-200 pair is nearly flat).  The
 # decays follow from the magnitude of the last shared component, so that
 # about half of the pairs keep all r components above the noise floor
-# (those are the pairs with a gap at k, the ones the labels can judge)
-TRAIN_RANGES = dict(m_range=(1000, 4000), n_range=(200, 1000), r_range=(5, 220), tail_range=(1e-4, 0.3))
+# (those are the pairs with a gap at k, the ones the labels can judge), and
+# k counts the components above twice the floor, so that tails a few times
+# the noise (where more passes pay) are among them.  The two decays are
+# drawn apart: with one decay for both matrices every GSV sits near
+# 1/sqrt(2) and theta is set by how the noise splits between G1 and G2,
+# which no sketch size makes more exact
+TRAIN_RANGES = dict(m_range=(1000, 4000), n_range=(200, 1000), r_range=(5, 220), tail_range=(1e-4, 0.3),
+                    k_floor=2.0)
+# a few training pairs at the workload's own scale (drawn on the device):
+# the noise a sketch takes in grows with the rows and n, and with it the
+# passes a tail near the floor needs
+TRAIN_LARGE = dict(m_range=(20000, 100000), n_range=(1000, 2000), r_range=(50, 220), tail_range=(1e-4, 0.3),
+                   k_floor=2.0)
 
 
 def _torch():
@@ -38,13 +51,15 @@ def _torch():
 
 
 # ------------------------------------------------------------ features ---
-def probe_features(G1, G2, seed, precision="fp64"):
-    """32 probe features of a device pair (float32 device tensor)."""
+def probe_features(G1, G2, seed, k, precision="fp64"):
+    """The 32 sizing features of a device pair for target rank k (float32
+    device tensor), from a learned plan of the pair's shapes, as a learned
+    run of that precision computes them."""
     torch = _torch()
     m, n = G1.shape
     p = G2.shape[0]
     dt = R.F64 if G1.dtype == torch.float64 else R.F32
-    plan = R.Plan(R.make_desc(m, p, n, 1, 0, 0, seed, dt, precision), G1.device)
+    plan = R.Plan(R.make_desc(m, p, n, k, 0, 0, seed, dt, precision, "learned"), G1.device)
     feat = torch.empty(32, dtype=torch.float32, device=G1.device)
     R.check(R.lib().rgsvd_probe_features(plan.h, R._ptr(G1), G1.stride(0), R._ptr(G2), G2.stride(0),
                                          plan.ws_ptr, R._ptr(feat), R._stream(G1.device)), "probe_features")
@@ -113,12 +128,14 @@ def train(X, T, device, epochs=400, lr=3e-3, seed=0):
 
 # --------------------------------------------------------------- pairs ---
 def pair_specs(npairs, seed, m_range=(500, 3000), n_range=(100, 400), r_range=(5, 40),
-               d_range=(0.5, 0.99), nu_range=(1e-6, 1e-2), tail_range=None):
+               d_range=(0.5, 0.99), nu_range=(1e-6, 1e-2), tail_range=None, k_floor=10.0, p_same=0.0):
     """Training / held-out pairs shaped like the learned-sizing workload
     (scaled down): shared rank r, decays d1, d2, spectral noise floor nu
-    (log-uniform); k = the number of shared components above 10 nu (>= 2).
+    (log-uniform); k = the number of shared components above k_floor nu
+    (at least 2).
     With tail_range the decays are d_i = tau_i^(1/(r-1)) for tail magnitudes
-    tau_i drawn log-uniform from it, else uniform from d_range."""
+    tau_i drawn log-uniform from it, else uniform from d_range; with
+    probability p_same both matrices take d1."""
     rng = np.random.default_rng(seed)
     out = []
     for i in range(npairs):
@@ -133,9 +150,11 @@ def pair_specs(npairs, seed, m_range=(500, 3000), n_range=(100, 400), r_range=(5
             lo, hi = np.log(tail_range[0]), np.log(tail_range[1])
             d1, d2 = (float(np.exp(rng.uniform(lo, hi)) ** (1.0 / max(1, r - 1))) for _ in range(2))
         nu = float(np.exp(rng.uniform(np.log(nu_range[0]), np.log(nu_range[1]))))
+        if p_same > 0.0 and rng.uniform() < p_same:
+            d2 = d1
         j = np.arange(r)
         mag = np.minimum(d1 ** j, d2 ** j)
-        k = int(max(2, min(r, np.sum(mag >= 10 * nu))))
+        k = int(max(2, min(r, np.sum(mag >= k_floor * nu))))
         out.append(dict(m=m, p=p, n=n, r=r, d1=d1, d2=d2, nu=nu, k=k, seed=seed * 7919 + i))
     return out
 
@@ -224,6 +243,22 @@ def label(g1, g2, spec, seed=1, precision="mixed", margin=LABEL_MARGIN):
             if passes(_run(g1, g2, k, l, q, seed, precision), ref, idx, margin * TOL_THETA):
                 return l, q, ref, idx
     return grid[-1], GRID_Q[-1], ref, idx
+
+
+def label_set(dev, specs, make, seed=1, precision="mixed"):
+    """Features and targets of the pinned pairs among specs (make(spec) gives
+    the device pair); returns (X, T, number of unpinned pairs left out)."""
+    X, T, skipped = [], [], 0
+    for s in specs:
+        g1, g2 = make(s)
+        l, q, _, _ = label(g1, g2, s, seed=seed, precision=precision)
+        if l is None:
+            skipped += 1
+        else:
+            X.append(probe_features(g1, g2, seed, s["k"], precision=precision).cpu().numpy())
+            T.append(targets(s["k"], l, q))
+        del g1, g2
+    return X, T, skipped
 
 
 def cost(spec, l, q):
