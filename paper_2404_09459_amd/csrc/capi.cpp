@@ -48,7 +48,7 @@ inline int ct_of(int L) {
 }
 
 enum Kind { K_ZERO, K_COPY, K_GEN, K_AB, K_GRAM, K_RED, K_CHOL, K_SMALL, K_SIGN, K_SCALE, K_GW, K_GTQ,
-            K_PACK, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP, K_BJINIT, K_BJROUND, K_GW4, K_ZEROG, K_NN, K_PROF };
+            K_PACK, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP, K_BJINIT, K_BJROUND, K_GW4, K_ZEROG, K_NN, K_PROF, K_TN };
 
 enum Tag { T_ZERO, T_COPY, T_GEN, T_NN, T_TN, T_RED, T_GRAM, T_CHOL, T_SX, T_SMALL, T_RECOVER, T_SIGN,
            T_MGRAM, T_BJAC, T_NTAGS };
@@ -84,6 +84,7 @@ struct SideLay {
   int cap = 0, lcur = 0, bcur = 0, gtiles = 0;
   bool active = false;
   int nchunk0 = 1, nchunk_max = 1;   // heuristic and largest row-chunk counts of G^T Q
+  int tn_nchunk = 1, tn_mchunk = 0;  // row chunks of the mixed path's 8-wave G^T Q (k_tn)
 };
 
 struct PairLay {
@@ -223,6 +224,18 @@ int layout(rgsvd_plan_s* P) {
       s.nchunk = nch; s.mchunk = mch;
       s.nchunk0 = nch;
       s.nchunk_max = std::max(1, std::min(2 * nch, (s.m + 31) / 32));
+      if (prec == PBF && P->gdt != RGSVD_F64) {
+        // k_tn: about two 8-wave workgroups per CU over all sides, chunks
+        // in proportion to the rows, at least 256 rows each
+        int64_t rows_all = 0;
+        for (auto& q : P->pairs) rows_all += q.m + q.p;
+        const int64_t wpc = ((s.n + 31) / 32 + TN_WAVES - 1) / TN_WAVES;
+        int64_t tn = 2 * (int64_t)(P->wave_slots / 4) * s.m / std::max<int64_t>(1, rows_all * wpc);
+        tn = std::max<int64_t>(1, std::min<int64_t>(tn, (s.m + 255) / 256));
+        s.tn_mchunk = (int)upi((s.m + tn - 1) / tn, 32);
+        s.tn_nchunk = (s.m + s.tn_mchunk - 1) / s.tn_mchunk;
+        s.nchunk_max = std::max(s.nchunk_max, s.tn_nchunk);
+      }
       // Gram chunks over m and over n
       int nb = P->npadG / 64, nblk = nb * (nb + 1) / 2;
       // (about 512 tiles in all, but no chunk longer than 1024 rows: a batch of
@@ -529,6 +542,41 @@ int build(rgsvd_plan_s* P, void* ws) {
 
   // G^T Q (or Q^T G) into the Wt buffers: split over row chunks then reduced
   auto add_tn = [&](int p) {
+    if (mixed && gt == 1) {
+      // mixed path over FP32 G: 8-wave workgroups sharing the packed Q^T in
+      // LDS; the BF16 pass rounds both operands, the FP32 passes of the
+      // method run the three-piece split
+      const bool split = p == P32;
+      add_pack(true, PBF, split ? 3 : 1);
+      // row tiles: the largest side's count, rounded up to even
+      const int ctn = [&] { int t = 1; for (auto& s : S) t = std::max(t, s.L / 16); return t; }();
+      const int tct = ctn == 1 ? 1 : std::min(16, (ctn + 1) & ~1);
+      std::vector<AbJob> aj; std::vector<int> atl;
+      std::vector<RedJob> rj; std::vector<int> rtl;
+      for (auto& s : S) {
+        const int64_t pstride = (int64_t)((s.m + 31) / 32) * s.L * 32;   // elements between BF16 pieces
+        for (int c = 0; c < s.tn_nchunk; ++c) {
+          const int r0 = c * s.tn_mchunk;
+          AbJob a{};
+          a.A = (const char*)WS(ws, s.Yt16) + (size_t)r0 * s.L * 2; a.lda = pstride;
+          a.B = (const char*)s.G + (size_t)r0 * s.ldg * 4; a.ldb = s.ldg;
+          a.D = WS(ws, s.part) + (size_t)c * s.L * s.ldw * 4; a.ldd = s.ldw;
+          a.rows = s.L; a.K = std::min(s.tn_mchunk, s.m - r0); a.J = s.n; a.accumulate = 0; a.colscale = nullptr;
+          aj.push_back(a);
+          atl.push_back(tn_tiles_per_chunk(split, tct, s.n));
+        }
+        RedJob r{};
+        r.in = WS(ws, s.part); r.out = WS(ws, s.Wt); r.sq = nullptr;
+        r.stride = (int64_t)s.L * s.ldw; r.count = (int64_t)s.L * s.n;
+        r.nparts = s.tn_nchunk; r.rows = s.L; r.cols = s.n; r.ldo = s.ldw; r.ldi = s.ldw;
+        rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
+      }
+      Stage& a = B.add(K_TN, aj, atl);
+      a.split = split; a.ct = tct; a.tag = T_TN;
+      Stage& r = B.add(K_RED, rj, rtl);
+      r.sym = false; r.ta = wt; r.td = wt; r.tag = T_RED;
+      return;
+    }
     if (p != P64) add_pack(true, p);
     std::vector<AbJob> aj; std::vector<int> atl;
     std::vector<RedJob> rj; std::vector<int> rtl;
@@ -1134,6 +1182,7 @@ int enqueue_list(rgsvd_plan_s* P, void* ws, hipStream_t st, const std::vector<St
       case K_GW4: launch_gw4(s.prec, s.ct, (const NnJob*)j, pre, s.nj, s.tiles, st); break;
       case K_NN: launch_nn(s.split, s.rt, s.ct, (const NnJob*)j, pre, s.nj, s.tiles, st); break;
       case K_GTQ: launch_gtq(s.prec, s.gdt, s.ct, s.js, (const AbJob*)j, pre, s.nj, s.tiles, st); break;
+      case K_TN: launch_tn(s.split, s.ct, (const AbJob*)j, pre, s.nj, s.tiles, st); break;
       case K_PACK: launch_pack(j, pre, s.nj, s.tiles, st); break;
       case K_SUMSQ: hipLaunchKernelGGL(k_sumsq, dim3(s.tiles), dim3(256), 0, st, (const SumsqJob*)j, pre, s.nj); break;
       case K_SUMFIN:

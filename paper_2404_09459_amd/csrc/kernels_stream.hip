@@ -445,25 +445,26 @@ __global__ __launch_bounds__(64 * NN_NW) void k_nn(const NnJob* __restrict__ job
         split_bf16<SPLIT>(v, gp[a]);
       }
       const u4v* wb = wl + (st & 1) * STR;
-      // no branch over the tiles (those past ctn read zeros), so the
-      // dependent products of one tile interleave with the next tile's
+      // no branch over the tiles (those past ctn read zeros); the column
+      // tiles go in groups, product-major within a group, so that four
+      // independent accumulators sit between dependent MFMAs
+      constexpr int TG = RT == 1 ? (CT < 4 ? CT : 4) : (CT < 2 ? CT : 2);
+      constexpr int PG[6] = {2, 1, 0, 1, 0, 0}, PW[6] = {0, 1, 2, 0, 1, 0};   // smallest terms first
 #pragma unroll
-      for (int b = 0; b < CT; ++b) {
-        bf8 wp[NPW];
+      for (int b0 = 0; b0 < CT; b0 += TG) {
+        bf8 wp[TG][NPW];
 #pragma unroll
-        for (int pc = 0; pc < NPW; ++pc) wp[pc] = __builtin_bit_cast(bf8, wb[pc * CT * 64 + b * 64 + ln]);
+        for (int bb = 0; bb < TG; ++bb)
 #pragma unroll
-        for (int a = 0; a < RT; ++a) {
-          if constexpr (SPLIT) {
-            // smallest terms first
-            acc[a][b] = mmabf(gp[a][2], wp[0], acc[a][b]);
-            acc[a][b] = mmabf(gp[a][1], wp[1], acc[a][b]);
-            acc[a][b] = mmabf(gp[a][0], wp[2], acc[a][b]);
-            acc[a][b] = mmabf(gp[a][1], wp[0], acc[a][b]);
-            acc[a][b] = mmabf(gp[a][0], wp[1], acc[a][b]);
-          }
-          acc[a][b] = mmabf(gp[a][0], wp[0], acc[a][b]);
-        }
+          for (int pc = 0; pc < NPW; ++pc)
+            wp[bb][pc] = __builtin_bit_cast(bf8, wb[pc * CT * 64 + (b0 + bb) * 64 + ln]);
+#pragma unroll
+        for (int t = SPLIT ? 0 : 5; t < 6; ++t)
+#pragma unroll
+          for (int bb = 0; bb < TG; ++bb)
+#pragma unroll
+            for (int a = 0; a < RT; ++a)
+              acc[a][b0 + bb] = mmabf(gp[a][PG[t]], wp[bb][PW[t]], acc[a][b0 + bb]);
       }
       if (st + 1 < nsteps) wstore((st + 1) & 1);   // W(st + 1), fetched one step ago
       if (st + 2 < nsteps) wfetch(st + 2);
@@ -583,6 +584,166 @@ __global__ __launch_bounds__(64) void k_gtq(const AbJob* __restrict__ jobs, cons
             if (col0 + q < J.J) dst[col0 + q] = (dT)acc[b][q][ii];
         }
       }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ k_tn --
+// The mixed path's G^T Q passes over FP32 G.  Job (AbJob) as for k_gtq:
+// D (rows x J, partial, ldd) = A (rows x K) B (K x J), A = Q^T of the row
+// chunk packed in BF16 fragment order (piece p at lda elements after piece
+// 0, the chunk's first k-step first), B = the chunk of G (K rows, ldb).
+// Workgroup: TN_NW waves over TN_NW / RH consecutive 32-column tiles of one
+// chunk (lane li owns two adjacent columns, one per MFMA sub-tile); the RH
+// waves of a column tile share its CT = RH CTW row tiles of D, CTW each (RH
+// = 2 halves the accumulators of the split pass over many row tiles; the
+// second wave's loads of the same G rows hit the cache).  The packed A of a k-step is staged in LDS once for all the
+// waves (double-buffered, written one step ahead, one barrier per step);
+// G streams from HBM into registers NB - 1 steps ahead.
+// SPLIT = false: G rounded to BF16, A one BF16 piece.  SPLIT = true: the
+// FP32-accurate product of k_nn's split: three BF16 pieces of both operands,
+// the six products g_i q_j with i + j <= 4, smallest first.
+constexpr int TN_NW = TN_WAVES;
+
+template <bool SPLIT, int CTW, int RH>
+__global__ __launch_bounds__(64 * TN_NW) void k_tn(const AbJob* __restrict__ jobs, const int* __restrict__ pre,
+                                                   int nj, int ntiles) {
+  constexpr int NP = SPLIT ? 3 : 1;
+  constexpr int CT = CTW * RH;                // row tiles staged
+  constexpr int CG = TN_NW / RH;              // column tiles per workgroup
+  // G pipeline depth: three steps, two for a split wave over 6 or more row
+  // tiles (its accumulators and pieces fill the registers)
+  constexpr int KL = 8, KS = 32, NB = (SPLIT && CTW >= 6) ? 2 : 3, JS = 2;
+  constexpr int STR = NP * CT * 64;           // 16-byte chunks per LDS buffer
+  constexpr int NT = 64 * TN_NW;
+  constexpr int CH = (STR + NT - 1) / NT;     // chunks a thread stages per step
+  extern __shared__ u4v al[];                 // 2 x STR
+  const int t = xcd_tile(blockIdx.x, gridDim.x);
+  if (t >= ntiles) return;                    // whole workgroups only
+  const int jb = find_side(pre, nj, t);
+  const AbJob J = jobs[jb];
+  const int wg = t - pre[jb];
+  const int tid = threadIdx.x, wave = tid >> 6, ln = tid & 63, g = ln >> 4, li = ln & 15;
+  const int cw = wave % CG, rh = wave / CG;   // column tile in the workgroup, row half
+  const int col0 = (wg * CG + cw) * 16 * JS + JS * li;
+  const int ctn = (J.rows + 15) >> 4;
+  const int nchw = ctn * 64;                  // chunks of one piece per step
+  const int nsteps = (J.K + KS - 1) / KS;
+  const __amdgpu_buffer_rsrc_t rs = make_rsrc(J.B, (int64_t)J.K * J.ldb * 4);
+  const bool cok0 = col0 < J.J, cok1 = col0 + 1 < J.J;
+  const int coff = (cok0 ? col0 : 0) * 4;
+  const u4v* asrc = (const u4v*)J.A;          // piece pc, step st: chunks pc lda / 8 + st nchw ...
+  const int64_t pst = J.lda / 8;
+
+  f4 acc[CTW][JS];
+#pragma unroll
+  for (int b = 0; b < CTW; ++b)
+#pragma unroll
+    for (int q = 0; q < JS; ++q) acc[b][q] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  float gb[NB][KL][JS];
+  u4v at[CH];
+  // the lane's part of the address in a VGPR, the step's and the row's in
+  // the scalar offset
+  const int voff = g * KL * (int)J.ldb * 4 + coff;
+  const int rstr = (int)J.ldb * 4;
+  auto gl = [&](int buf, int st) {
+#pragma unroll
+    for (int e = 0; e < KL; ++e) {
+      const f2 t = __builtin_bit_cast(f2, __builtin_amdgcn_raw_buffer_load_b64(rs, voff, (st * KS + e) * rstr, 0));
+      gb[buf][e][0] = t[0];
+      gb[buf][e][1] = t[1];
+    }
+  };
+  auto afetch = [&](int st) {
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int c = tid + NT * i;
+      if (c < NP * nchw) {
+        const int pc = c / nchw, w = c - pc * nchw;
+        at[i] = *(gptr<u4v>)(asrc + pc * pst + (int64_t)st * nchw + w);
+      }
+    }
+  };
+  auto astore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < CH; ++i) {
+      const int c = tid + NT * i;
+      if (c < NP * nchw) {
+        const int pc = c / nchw, w = c - pc * nchw;
+        al[buf * STR + pc * CT * 64 + w] = at[i];
+      }
+    }
+  };
+  // row tiles past ctn read zeros, so the MFMAs below need no branch
+  for (int c = tid; c < 2 * STR; c += NT)
+    if ((c % (CT * 64)) >= nchw) al[c] = u4v{0, 0, 0, 0};
+  if (nsteps > 0) { afetch(0); astore(0); }
+#pragma unroll
+  for (int b = 0; b < NB - 1; ++b)
+    if (b < nsteps) gl(b, b);
+  __syncthreads();
+#pragma unroll 1
+  for (int st0 = 0; st0 < nsteps; st0 += NB) {
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int st = st0 + u;
+      if (st >= nsteps) break;
+      // A of the next step (L2-resident) is loaded before this step's G
+      // prefetch and stored once it arrives, so its registers are free
+      // again before the MFMAs; the buffer it fills was last read in the
+      // step before the last barrier
+      if (st + 1 < nsteps) afetch(st + 1);
+      if (st + NB - 1 < nsteps) gl((u + NB - 1) % NB, st + NB - 1);
+      if (st + 1 < nsteps) astore((st + 1) & 1);
+      bf8 bp[JS][NP];
+      {
+        float v0[KL], v1[KL];
+#pragma unroll
+        for (int e = 0; e < KL; ++e) {
+          v0[e] = cok0 ? gb[u][e][0] : 0.0f;
+          v1[e] = cok1 ? gb[u][e][1] : 0.0f;
+        }
+        split_bf16<SPLIT>(v0, bp[0]);
+        split_bf16<SPLIT>(v1, bp[1]);
+      }
+      const u4v* ab = al + (st & 1) * STR + rh * CTW * 64;
+      // row tiles in pairs, product-major within a pair: four independent
+      // accumulators between dependent MFMAs
+#pragma unroll
+      for (int b0 = 0; b0 < CTW; b0 += 2) {
+        constexpr int PA[6] = {0, 1, 2, 0, 1, 0}, PB[6] = {2, 1, 0, 1, 0, 0};   // smallest terms first
+        bf8 ap[2][NP];
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+          if (b0 + bb < CTW)
+#pragma unroll
+            for (int pc = 0; pc < NP; ++pc)
+              ap[bb][pc] = __builtin_bit_cast(bf8, ab[pc * CT * 64 + (b0 + bb) * 64 + ln]);
+#pragma unroll
+        for (int t = SPLIT ? 0 : 5; t < 6; ++t)
+#pragma unroll
+          for (int bb = 0; bb < 2; ++bb)
+            if (b0 + bb < CTW)
+#pragma unroll
+              for (int q = 0; q < JS; ++q)
+                acc[b0 + bb][q] = mmabf(ap[bb][PA[t]], bp[q][PB[t]], acc[b0 + bb][q]);
+      }
+      __syncthreads();
+    }
+  }
+  // lane holds D[16 (rh CTW + b) + 4 g + ii][col0 + q]
+  float* D = (float*)J.D;
+#pragma unroll
+  for (int b = 0; b < CTW; ++b) {
+    if (rh * CTW + b >= ctn) continue;
+#pragma unroll
+    for (int ii = 0; ii < 4; ++ii) {
+      const int c = (rh * CTW + b) * 16 + 4 * g + ii;
+      if (c >= J.rows) continue;
+      float* dst = D + (int64_t)c * J.ldd + col0;
+      if (cok1) *(f2*)dst = f2{acc[b][0][ii], acc[b][1][ii]};
+      else if (cok0) dst[0] = acc[b][0][ii];
     }
   }
 }
@@ -728,6 +889,56 @@ void launch_gtq(int prec, int gdt, int ct, int js, const AbJob* j, const int* pr
     else if (js == 4) gtq_ct<PBF, float, 4>(ct, j, pre, nj, tiles, st);
     else gtq_ct<PBF, float, 2>(ct, j, pre, nj, tiles, st);
   }
+}
+
+// ct: row tiles of D (1, or an even count up to 16); the split pass over 10
+// or more runs two waves per column tile, ct / 2 row tiles each
+template <bool SPLIT>
+static void tn_ct(int ct, const AbJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  const size_t lds = (size_t)2 * (SPLIT ? 3 : 1) * ct * 64 * 16;
+  const dim3 grid(xcd_grid(tiles));
+  auto go = [&](auto kern) {
+    static bool attr_set = false;   // one flag per instantiation
+    if (!attr_set) {
+      hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(kern, grid, dim3(64 * TN_NW), lds, st, j, pre, nj, tiles);
+  };
+  switch (ct) {
+    case 1: go(k_tn<SPLIT, 1, 1>); break;
+    case 2: go(k_tn<SPLIT, 2, 1>); break;
+    case 4: go(k_tn<SPLIT, 4, 1>); break;
+    case 6: go(k_tn<SPLIT, 6, 1>); break;
+    case 8: go(k_tn<SPLIT, 8, 1>); break;
+    default:
+      if constexpr (SPLIT) {
+        switch (ct) {
+          case 10: go(k_tn<true, 5, 2>); break;
+          case 12: go(k_tn<true, 6, 2>); break;
+          case 14: go(k_tn<true, 7, 2>); break;
+          default: go(k_tn<true, 8, 2>); break;
+        }
+      } else {
+        switch (ct) {
+          case 10: go(k_tn<false, 10, 1>); break;
+          case 12: go(k_tn<false, 12, 1>); break;
+          case 14: go(k_tn<false, 14, 1>); break;
+          default: go(k_tn<false, 16, 1>); break;
+        }
+      }
+  }
+}
+
+// workgroups per row chunk of k_tn over n columns
+int tn_tiles_per_chunk(bool split, int ct, int n) {
+  const int cg = (split && ct >= 10) ? TN_NW / 2 : TN_NW;
+  return ((n + 31) / 32 + cg - 1) / cg;
+}
+
+void launch_tn(bool split, int ct, const AbJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
+  if (split) tn_ct<true>(ct, j, pre, nj, tiles, st);
+  else tn_ct<false>(ct, j, pre, nj, tiles, st);
 }
 
 void launch_pack(const void* j, const int* pre, int nj, int tiles, hipStream_t st) {

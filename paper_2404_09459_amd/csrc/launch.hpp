@@ -31,5 +31,9 @@ void launch_gw4(int prec, int ct, const NnJob* j, const int* pre, int nj, int ti
 void launch_nn(bool split, int rt, int ct, const NnJob* j, const int* pre, int nj, int tiles, hipStream_t st);
 void launch_gtq(int prec, int gdt, int ct, int js, const AbJob* j, const int* pre, int nj, int tiles,
                 hipStream_t st);
+// waves per workgroup of k_tn; each wave covers 32 columns of G
+constexpr int TN_WAVES = 8;
+void launch_tn(bool split, int ct, const AbJob* j, const int* pre, int nj, int tiles, hipStream_t st);
+int tn_tiles_per_chunk(bool split, int ct, int n);
 void launch_pack(const void* j, const int* pre, int nj, int tiles, hipStream_t st);
 }  // namespace rg
