@@ -482,15 +482,27 @@ int build(rgsvd_plan_s* P, void* ws) {
     std::vector<NnJob> j; std::vector<int> tl;
     const bool rt4_ok = !(p == P64 || gt == 0 || ctL > 8);
     int rt = P->tune_rt ? (P->tune_rt == 4 && rt4_ok ? 4 : 1) : (rt4_ok ? 4 : 1);
+    // FP64 over more than 8 column tiles: two jobs per side, the first 128
+    // columns of Y and the rest (8 tiles' accumulators and operands fill a
+    // wave's registers; G is read twice)
+    const bool halves = p == P64 && ctL > 8;
     for (auto& s : S) {
-      NnJob x{};
-      x.G = s.G; x.Wt = WS(ws, p == P64 ? s.Wt : pack_dst(s, false, p)); x.Yt = WS(ws, s.Yt);
-      x.ldg = s.ldg; x.ldw = s.ldw; x.ldy = s.ldy; x.m = s.m; x.n = s.n; x.L = s.L;
-      j.push_back(x);
-      tl.push_back((s.m + 16 * rt - 1) / (16 * rt));
+      for (int h = 0; h < (halves ? 2 : 1); ++h) {
+        const int r0 = h * 128;
+        if (r0 >= s.L) break;
+        NnJob x{};
+        const size_t wsz8 = p == P64 ? 8 : 0;
+        x.G = s.G;
+        x.Wt = p == P64 ? (const void*)(WS(ws, s.Wt) + (size_t)r0 * s.ldw * wsz8) : WS(ws, pack_dst(s, false, p));
+        x.Yt = WS(ws, s.Yt) + (size_t)r0 * s.ldy * (p == P64 ? 8 : 4);
+        x.ldg = s.ldg; x.ldw = s.ldw; x.ldy = s.ldy; x.m = s.m; x.n = s.n;
+        x.L = halves ? std::min(128, s.L - r0) : s.L;
+        j.push_back(x);
+        tl.push_back((s.m + 16 * rt - 1) / (16 * rt));
+      }
     }
     Stage& st = B.add(K_GW, j, tl);
-    st.prec = p; st.gdt = gt; st.rt = rt; st.ct = ctL; st.tag = T_NN;
+    st.prec = p; st.gdt = gt; st.rt = rt; st.ct = halves ? 8 : ctL; st.tag = T_NN;
   };
 
   // CholeskyQR passes on the Yt (ymat = true) or Wt buffers
@@ -580,6 +592,9 @@ int build(rgsvd_plan_s* P, void* ws) {
     if (p != P64) add_pack(true, p);
     std::vector<AbJob> aj; std::vector<int> atl;
     std::vector<RedJob> rj; std::vector<int> rtl;
+    // FP64 over more than 8 row tiles: two jobs per chunk, rows [0, 128) of
+    // D and the rest (as in the G W pass)
+    const bool halves = p == P64 && ctL > 8;
     const bool js4_ok = !(p == P64 || gt == 0 || ctL > 8);
     const int js = P->tune_js ? (P->tune_js == 4 && js4_ok ? 4 : 2) : (js4_ok ? 4 : 2);
     const size_t psz = (prec == P64) ? 8 : 4;
@@ -596,6 +611,18 @@ int build(rgsvd_plan_s* P, void* ws) {
         a.B = (const char*)s.G + (size_t)r0 * s.ldg * (gt == 0 ? 8 : 4); a.ldb = s.ldg;
         a.D = WS(ws, s.part) + (size_t)c * s.L * s.ldw * psz; a.ldd = s.ldw;
         a.rows = s.L; a.K = rows; a.J = s.n; a.accumulate = 0; a.colscale = nullptr;
+        if (halves) {
+          // P64 reads Q^T unpacked (row c at c lda): the second job starts at row 128
+          for (int h = 0; h < 2 && h * 128 < s.L; ++h) {
+            AbJob b = a;
+            b.A = (const char*)a.A + (size_t)h * 128 * s.ldy * 8;
+            b.D = (char*)a.D + (size_t)h * 128 * s.ldw * psz;
+            b.rows = std::min(128, s.L - h * 128);
+            aj.push_back(b);
+            atl.push_back((s.n + 16 * js - 1) / (16 * js));
+          }
+          continue;
+        }
         aj.push_back(a);
         atl.push_back((s.n + 16 * js - 1) / (16 * js));
       }
@@ -606,7 +633,7 @@ int build(rgsvd_plan_s* P, void* ws) {
       rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
     }
     Stage& a = B.add(K_GTQ, aj, atl);
-    a.prec = p; a.gdt = gt; a.ct = ctL; a.js = js; a.tag = T_TN;
+    a.prec = p; a.gdt = gt; a.ct = halves ? 8 : ctL; a.js = js; a.tag = T_TN;
     Stage& r = B.add(K_RED, rj, rtl);
     r.sym = false; r.ta = wt; r.td = wt; r.tag = T_RED;
   };
