@@ -246,6 +246,31 @@ def test_determinism_bitwise(dev):
         assert np.array_equal(a[key], b[key]), key
 
 
+@pytest.mark.parametrize("m,p,n,k,o,q", [
+    (4093, 2711, 517, 150, 10, 1),   # 160-wide basis: the split G^T Q pass runs two waves per column tile
+    (3001, 2077, 333, 40, 8, 2),     # 48-wide basis, n = 10 x 32 + 13, ragged row chunks
+])
+def test_mixed_ragged_gate(dev, m, p, n, k, o, q):
+    """The mixed path on ragged shapes (m, p and n off every tile multiple)
+    against the FP64 oracle: 1e-4 on the pinned angular distances, the
+    GSV pairs on the unit circle."""
+    from oracle import rgsvd as O
+    from paper_2404_09459_amd import inputs as I
+    _say(f"mixed ragged gate m={m} p={p} n={n} k={k} o={o} q={q}")
+    j = np.arange(k)
+    G1, G2 = I.lowrank_pair(m, p, n, k, 0.97 ** j, 0.95 ** j, 7 + n, noise_spectral=1e-5, dtype=np.float32)
+    got = _run(dev, G1, G2, k, o, q, 23, precision="mixed")
+    ref = O.rgsvd(G1.astype(np.float64), G2.astype(np.float64), k, o, q, 23)
+    s = ref["sigma_B"]
+    weak = np.minimum(ref["alpha"], ref["beta"]) * np.linalg.norm(ref["R"], axis=1)
+    idx = np.where(weak >= 10 * 1e-5)[0] if s[k - 1] >= 2 * s[k] else np.arange(0)
+    dth = np.max(np.abs(got["theta"][idx] - ref["theta"][idx]))
+    _say(f"   pinned {len(idx)}/{k} |dtheta|={dth:.2e} info={got['info'].tolist()}")
+    assert len(idx) >= k // 2
+    assert dth <= 1e-4
+    assert np.max(np.abs(got["alpha"] ** 2 + got["beta"] ** 2 - 1)) <= 1e-12
+
+
 @pytest.mark.parametrize("precision", ["mixed", "fp32"])
 def test_reduced_precision_gate(dev, precision):
     """BF16/FP32 sketch paths against the FP64 oracle: 1e-4 on the angular
