@@ -314,6 +314,46 @@ def time_learned(R, torch, dev, G1, G2, m, p, n, k, seed, dt, params, args):
     return dict(ms=ms, got=got, info=got["info"].tolist())
 
 
+def time_batch_of_pairs(R, torch, dev, m, p, n, k, o, q, nu, dt, B, args):
+    """B pairs of the workload's shape and spectrum (the recipe drawn on the
+    device, seeds 31..31+B-1) in one batched plan, mixed precision, replayed
+    as one graph: the rounds of the latency-bound small step of all B pairs
+    share their launches.  Pair 0 is also run alone, and its angular
+    distances compared with the batch's."""
+    from paper_2404_09459_amd import inputs as I
+    j = np.arange(k)
+    pairs = [I.lowrank_pair_device(m, p, n, k, 0.97 ** j, 0.97 ** j, 31 + b, nu, dev) for b in range(B)]
+    torch.cuda.synchronize()
+    descs = [R.make_desc(m, p, n, k, o, q, 3, dt, "mixed") for _ in range(B)]
+    plan = R.BatchPlan(descs, dev)
+    outs = plan.bind(pairs)
+    for _ in range(max(1, args.warmup)):
+        plan.run()
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream(dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    steps = max(1, args.steps // 2)
+    e0.record(st)
+    for _ in range(steps):
+        plan.run()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    got0 = outs[0]["theta"].cpu().numpy()
+    info0 = outs[0]["info"].cpu().numpy().tolist()
+    del plan, outs
+    single = R.rgsvd(pairs[0][0], pairs[0][1], k, o, q, 3, precision="mixed")
+    torch.cuda.synchronize()
+    dth = float(np.max(np.abs(got0 - single["theta"].cpu().numpy())))
+    del pairs, single
+    torch.cuda.empty_cache()
+    log(f"[bench] batch of {B} pairs: {ms:.3f} ms per batch ({1000 * B / ms:.1f} pairs/s); "
+        f"pair 0 against its single run |dtheta| {dth:.1e}; info {info0}")
+    return {"pairs": B, "ms_per_batch": ms, "pairs_per_s": 1000.0 * B / ms, "ms_per_pair": ms / B,
+            "theta_vs_single_run": dth, "info_pair0": info0,
+            "recipe": f"{B} pairs of the workload's recipe drawn on the device (torch generator, seeds 31..{30 + B})"}
+
+
 def gate_of(e, k):
     """1e-4 on the pinned angular distances; 1e-5 on the entropies when every
     pair is pinned (D sums over all t pairs)."""
@@ -379,6 +419,9 @@ def main():
     ap.add_argument("--cpu-reps", type=int, default=3)
     ap.add_argument("--no-single-thread", action="store_true", help="skip the one-thread oracle timing")
     ap.add_argument("--no-tune", action="store_true", help="skip the tile-shape autotuner")
+    ap.add_argument("--batch-pairs", type=int, default=4,
+                    help="large workload: also time a batched plan of this many pairs of the same shape "
+                         "(0: skip)")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the mixed + learned-sizing leg (it trains the sizing network first)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
@@ -426,6 +469,10 @@ def main():
                          "method, unpinned left out; 600 Adam steps of the HIP MLP kernels"}
         log(f"[bench] sizing network trained on {ntrain} pairs in {tsec:.1f}s")
         learned = time_learned(R, torch, dev, G1, G2, m, p, n, k, seed, dt, params, args)
+
+    batch = None
+    if args.workload == "large" and args.batch_pairs > 0 and esz == 4 and "mixed" in res:
+        batch = time_batch_of_pairs(R, torch, dev, m, p, n, k, o, q, nu, dt, args.batch_pairs, args)
 
     if args.calib_copy > 0:
         nel = args.calib_copy * (1 << 20) // 4
@@ -549,6 +596,7 @@ def main():
         "roofline_sketch": roof_sketch,
         "cpu_baseline": cpu,
         "paths": paths,
+        "batch_of_pairs": batch,
         "distinct_decay_gate": distinct,
     }
     print(json.dumps(out), flush=True)
