@@ -79,7 +79,9 @@ extern "C" {
 #define RGSVD_SIZE_LEARNED 2   /* sizing network picks l and q from a 16-column probe */
 /* truncation */
 #define RGSVD_TRUNCATED 0      /* t = k GSV pairs                                      */
-#define RGSVD_FULL 1           /* t = n, needs l1 + l2 >= n                            */
+#define RGSVD_FULL 1           /* t = n, needs l1 + l2 >= n (fixed or adaptive sizing;
+                                  adaptive runs return RGSVD_ENOTGMP from rgsvd_run
+                                  when the widths they reach fall short)              */
 
 /* info words (int32, device), filled by a run */
 #define RGSVD_INFO_STATUS 0

@@ -1324,9 +1324,14 @@ int check_desc(const rgsvd_desc* d) {
     if (d->mode == RGSVD_TRUNCATED && d->k > l) return RGSVD_EINVAL;
     if (2 * l > SMALL_MAXN) return RGSVD_EUNSUPPORTED;
   } else if (d->sizing == RGSVD_SIZE_ADAPTIVE) {
-    // Algorithm 1 with an absolute tolerance; FP64 arithmetic, truncated mode
+    // Algorithm 1 with an absolute tolerance; FP64 arithmetic.  Full mode
+    // needs capacities that can reach l1 + l2 >= n (checked again on the
+    // widths the run reaches)
     if (!(d->tol > 0.0) || !std::isfinite(d->tol) || d->block < 0 || d->lmax < 0) return RGSVD_EINVAL;
-    if (d->precision != RGSVD_PREC_FP64 || d->mode != RGSVD_TRUNCATED) return RGSVD_EUNSUPPORTED;
+    if (d->precision != RGSVD_PREC_FP64) return RGSVD_EUNSUPPORTED;
+    if (d->mode == RGSVD_FULL &&
+        adaptive_cap(d->lmax, d->m, d->n) + adaptive_cap(d->lmax, d->p, d->n) < d->n)
+      return RGSVD_ENOTGMP;
     if (d->k > adaptive_cap(d->lmax, d->m, d->n) || d->k > adaptive_cap(d->lmax, d->p, d->n))
       return RGSVD_EINVAL;
   } else if (d->sizing == RGSVD_SIZE_LEARNED) {
@@ -1420,6 +1425,8 @@ int run_adaptive(rgsvd_plan_s* P, void* ws, hipStream_t st) {
   }
   pr.l1 = S[0].lcur;
   pr.l2 = S[1].lcur;
+  // full mode (t = n) is Algorithm 2 on a GMP: the bases must span n together
+  if (pr.t > pr.l1 + pr.l2) return RGSVD_ENOTGMP;
   return stage_list(rgsvd_plan_s::TAIL);
 }
 

@@ -852,11 +852,11 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
       base = bj_sweeps(S, J.tol, more);
     }
     const int tt = t < rank ? t : rank;
-    // the block sweeps are the whole budget of a factor that needed the
-    // block Jacobi: one that has not settled after them has no gap at t (the
-    // dominant subspace is not determined) and keeps FLAG_JACOBI_M, rather
-    // than running single-workgroup sweeps of tens of ms each
-    if (stage == 2 && more) {
+    // above order 256 the block sweeps are the whole budget of the factor:
+    // one that has not settled after them keeps FLAG_JACOBI_M rather than
+    // running single-workgroup sweeps of tens of ms each (20 ms at order
+    // 440); smaller factors finish on the single workgroup
+    if (stage == 2 && more && N > 256) {
       sw1 = J.maxsweep + 1;
     } else {
       sw1 = base + (more ? jacobi_any(F, N, N, rank, J.tol, J.maxsweep - base, tt, sh, lds, cap) : 0);

@@ -70,13 +70,15 @@ def lowrank_pair_device(m, p, n, r, s1, s2, seed, noise_spectral, device, dtype=
     return out[0], out[1]
 
 
-def planted_gmp(m, p, n, seed, frac=0.6, dtype=np.float64):
-    """Paper-style exactly low-rank GMP; returns (G1, G2, alpha*, beta*)."""
+def planted_gmp(m, p, n, seed, frac=0.6, dtype=np.float64, frac2=None):
+    """Paper-style exactly low-rank GMP; returns (G1, G2, alpha*, beta*).
+    Ranks frac min(m, p, n) for G1 and frac2 (default frac) of it for G2."""
     if m < n or p < n:
         raise ValueError("planted_gmp needs m >= n and p >= n")
     rng = np.random.default_rng(seed)
     nn = min(m, p, n)
-    r1 = r2 = max(1, int(round(frac * nn)))
+    r1 = max(1, int(round(frac * nn)))
+    r2 = max(1, int(round((frac if frac2 is None else frac2) * nn)))
     n_one = n - r2            # alpha = 1, beta = 0
     n_zero = n - r1           # alpha = 0, beta = 1
     s = n - n_one - n_zero

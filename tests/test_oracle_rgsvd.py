@@ -9,7 +9,7 @@ import pytest
 from scipy.linalg import cossin, null_space
 
 from oracle import rgsvd as O
-from oracle.philox import STREAM_G1
+from oracle.philox import STREAM_G1, STREAM_G2
 from paper_2404_09459_amd import inputs as I
 
 
@@ -219,6 +219,30 @@ def test_paper_generator_full_mode():
     r = O.rgsvd(G1, G2, k=40, oversample=0, q=1, seed=3, l1=rank, l2=rank, t=40)
     assert np.linalg.norm(np.sort(r["alpha"])[::-1] - a_star) < 1e-10
     assert np.linalg.norm(np.sort(r["beta"]) - np.sort(b_star)) < 1e-10
+
+
+@pytest.mark.parametrize("frac2,b", [(0.6, 100), (0.45, 8)])
+def test_paper_generator_adaptive_full_mode(frac2, b):
+    """The paper's own regime: Algorithm 1 (blocks of b, absolute eps) builds
+    both bases of an exactly low-rank GMP, then Algorithm 2 with t = n.  The
+    widths stop at the first block past each rank (the residual is rounding
+    after it), and the GSVs equal the planted ones and the deterministic GSVD
+    (Algorithm 2 with Q1 = I, Q2 = I) at the paper's 1e-10 level; with unequal
+    ranks l1 > l2, the branch Algorithm 2 takes through L2's SVD."""
+    G1, G2, a_star, b_star = I.planted_gmp(130, 110, 60, seed=13, frac=0.6, frac2=frac2)
+    r1, r2 = int(round(0.6 * 60)), int(round(frac2 * 60))
+    # eps above the cumulative residual's rounding floor (about sqrt(u) ||G||_F)
+    eps = 1e-6 * min(np.linalg.norm(G1), np.linalg.norm(G2))
+    Q1, _ = O.basis_adaptive(G1, eps, b, 4, STREAM_G1)
+    Q2, _ = O.basis_adaptive(G2, eps, b, 4, STREAM_G2)
+    l1, l2 = Q1.shape[1], Q2.shape[1]
+    assert l1 == min(60, -(-r1 // b) * b) and l2 == min(60, -(-r2 // b) * b)
+    assert l1 + l2 >= 60
+    r = O.finish(G1, G2, Q1, Q2, 60)
+    det = O.full_gsvd(G1, G2)
+    assert np.max(np.abs(np.sort(r["alpha"])[::-1] - a_star)) < 1e-10
+    assert np.max(np.abs(np.sort(r["beta"]) - np.sort(b_star))) < 1e-10
+    assert np.max(np.abs(r["alpha"] - det["alpha"])) < 1e-10
 
 
 def test_perturbation_bound_corollary_and_theorem_exp():
