@@ -185,9 +185,7 @@ def test_small_pair_fp64_parity(dev):
     (700, 1290, 95, 30, 18, 1, np.float64),    # l = 48: three tiles
     (2049, 1500, 300, 40, 10, 1, np.float32),  # fp32 storage, fp64 arithmetic
     (129, 65, 64, 1, 1, 1, np.float64),        # k = 1, l = 2
-    pytest.param(900, 700, 300, 60, 10, 1, np.float64, marks=pytest.mark.skip(
-        reason="faulted the GPU with a block-staged LDS Jacobi (since removed) whose cause was "
-               "not found; kept off the GPU")),           # l1 + l2 = 140
+    (900, 700, 300, 60, 10, 1, np.float64),    # l1 + l2 = 140: the block Jacobi, its ninth block partial
 ])
 def test_ragged_fp64_parity(dev, m, p, n, k, o, q, dt):
     from oracle import rgsvd as O
