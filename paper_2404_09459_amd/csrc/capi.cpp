@@ -66,7 +66,7 @@ struct Stage {
 };
 
 struct CopyJob { const uint32_t* src; uint32_t* dst; int64_t nwords; };
-struct PackJobH { const float* src; void* dst; int64_t ld; int32_t L, nst, bf16, pieces; };
+struct PackJobH { const void* src; void* dst; int64_t ld; int32_t L, nst, bf16, pieces, f64src; };
 
 struct SideLay {
   int m = 0, n = 0, l = 0, L = 0, which = 0, pair = 0;
@@ -75,6 +75,7 @@ struct SideLay {
   int gch_m = 1, gcl_m = 0, gch_n = 1, gcl_n = 0;
   size_t Yt = 0, Wt = 0, part = 0, gpart = 0, gram = 0, sinv = 0;
   size_t Yt16 = 0, Wt16 = 0, Yp32 = 0, Wp32 = 0;   // packed BF16 / FP32 operands (fragment order)
+  size_t Xp16 = 0;                                  // R^-T of the CholeskyQR in three BF16 pieces (mixed)
   const void* G = nullptr; int64_t ldg = 0;
   uint64_t seed = 0; int stream = 1;
   // adaptive basis (Algorithm 1): Omega block buffer, rows formed so far,
@@ -253,6 +254,7 @@ int layout(rgsvd_plan_s* P) {
         // three BF16 pieces each: the FP32-accurate split passes use them all
         s.Yt16 = take((size_t)3 * s.L * s.ldy * 2);
         s.Wt16 = take((size_t)3 * s.L * s.ldw * 2);
+        s.Xp16 = take((size_t)3 * P->npadG * P->npadG * 2);
       }
       if (prec != P64) {
         s.Yp32 = take((size_t)s.L * s.ldy * 4);
@@ -546,6 +548,35 @@ int build(rgsvd_plan_s* P, void* ws) {
       Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = wt; gs.tag = T_GRAM;
       Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.ta = 0; r.td = 0; r.tag = T_RED;
       Stage& c = B.add(K_CHOL, cj, ctl); c.tag = T_CHOL;
+      if (mixed) {
+        // the mixed path: R^-T packed in three BF16 pieces, then Q^T = R^-T Y^T
+        // in place on k_tn's three-piece products (one row chunk: K = L)
+        std::vector<PackJobH> pj; std::vector<int> ptl;
+        std::vector<AbJob> tj; std::vector<int> ttl;
+        const int ctn = [&] { int t = 1; for (auto& s : S) t = std::max(t, s.L / 16); return t; }();
+        const int tct = ctn == 1 ? 1 : std::min(16, (ctn + 1) & ~1);
+        for (auto& s : S) {
+          const int len = ymat ? s.m : s.n;
+          const int ld = ymat ? s.ldy : s.ldw;
+          const int nst = (s.L + 31) / 32;
+          PackJobH pk{};
+          pk.src = WS(ws, s.sinv); pk.dst = WS(ws, s.Xp16); pk.ld = P->npadG; pk.L = s.L; pk.nst = nst;
+          pk.bf16 = 1; pk.pieces = 3; pk.f64src = 1;
+          pj.push_back(pk);
+          ptl.push_back((int)(((int64_t)nst * (s.L / 16) * 64 + 255) / 256));
+          AbJob a{};
+          a.A = WS(ws, s.Xp16); a.lda = (int64_t)nst * s.L * 32;   // elements between pieces
+          a.B = WS(ws, ymat ? s.Yt : s.Wt); a.ldb = ld;
+          a.D = WS(ws, ymat ? s.Yt : s.Wt); a.ldd = ld;
+          a.rows = s.L; a.K = s.L; a.J = len; a.accumulate = 0; a.colscale = nullptr;
+          tj.push_back(a);
+          ttl.push_back(tn_tiles_per_chunk(true, tct, len));
+        }
+        B.add(K_PACK, pj, ptl).tag = T_SX;
+        Stage& a = B.add(K_TN, tj, ttl);
+        a.split = true; a.ct = tct; a.tag = T_SX;
+        continue;
+      }
       Stage& a = B.add(K_AB, aj, atl);
       a.prec = sxp; a.ta = 0; a.tb = wt; a.td = wt; a.ct = ctL; a.tag = T_SX;
       a.js = (sxp == P64) ? 2 : 1;

@@ -749,11 +749,12 @@ __global__ __launch_bounds__(64 * TN_NW) void k_tn(const AbJob* __restrict__ job
 }
 
 // ---------------------------------------------------------------- k_pack --
-// FP32 operand (L x ld, Xt layout) -> fragment order in BF16 (KL = 8) or
-// FP32 (KL = 4) for nst k-steps of KS = 4 KL columns; nst * KS <= ld.  One
+// FP32 operand (L x ld, Xt layout; FP64 with f64src, BF16 output only) ->
+// fragment order in BF16 (KL = 8) or FP32 (KL = 4) for nst k-steps of
+// KS = 4 KL columns; nst * KS <= ld.  One
 // thread per fragment piece (KL elements); consecutive threads write
 // consecutive pieces.
-struct PackJob { const float* src; void* dst; int64_t ld; int32_t L, nst, bf16, pieces; };
+struct PackJob { const void* src; void* dst; int64_t ld; int32_t L, nst, bf16, pieces, f64src; };
 
 __global__ __launch_bounds__(256) void k_pack(const PackJob* __restrict__ jobs, const int* __restrict__ pre,
                                               int nj) {
@@ -768,12 +769,20 @@ __global__ __launch_bounds__(256) void k_pack(const PackJob* __restrict__ jobs, 
   const int64_t st = q / ctn;
   const int c = b * 16 + (ln & 15);
   const int64_t k = st * 4 * KL + (ln >> 4) * KL;
-  const float* src = J.src + (int64_t)c * J.ld + k;
+  const int64_t so = (int64_t)c * J.ld + k;
   if (J.bf16) {
-    const f4 v0 = *(const f4*)src, v1 = *(const f4*)(src + 4);
     float x[8];
+    if (J.f64src) {
+      // an FP64 source (the CholeskyQR inverse), rounded to FP32 first
+      const double* sd = (const double*)J.src + so;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) { x[e] = v0[e]; x[4 + e] = v1[e]; }
+      for (int e = 0; e < 8; ++e) x[e] = (float)sd[e];
+    } else {
+      const float* src = (const float*)J.src + so;
+      const f4 v0 = *(const f4*)src, v1 = *(const f4*)(src + 4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) { x[e] = v0[e]; x[4 + e] = v1[e]; }
+    }
     // BF16 pieces x1, x2 = bf16(x - x1), x3 = bf16(x - x1 - x2); piece p of
     // the operand follows piece p - 1 (nst ctn 64 fragments apart)
     const int64_t pstride = (int64_t)J.nst * ctn * 64 * 8;
@@ -784,7 +793,7 @@ __global__ __launch_bounds__(256) void k_pack(const PackJob* __restrict__ jobs, 
       __builtin_memcpy((__bf16*)J.dst + p * pstride + piece * 8, o, 16);
     }
   } else {
-    *(f4*)((float*)J.dst + piece * 4) = *(const f4*)src;
+    *(f4*)((float*)J.dst + piece * 4) = *(const f4*)((const float*)J.src + so);
   }
 }
 
