@@ -230,7 +230,8 @@ def time_path(R, torch, dev, G1, G2, m, p, n, k, o, q, seed, dt, prec, args):
     if not args.no_tune:
         choice, tms = R.autotune(plan, G1, G2, outs, reps=2)
         tune = {"rows_per_tile": choice[0], "cols_per_lane": choice[1],
-                "chunks": ["heuristic", "half", "twice"][choice[2]], "ms": tms}
+                "chunks": ["heuristic", "half", "twice"][choice[2]],
+                "kernels": {0: None, 1: "8-wave k_nn/k_tn", 2: "per-wave k_gw/k_gtq"}[choice[3]], "ms": tms}
         log(f"[bench] {prec}: autotuned tile shapes {tune}")
     for _ in range(args.warmup):
         R.run(plan, G1, G2, outs)

@@ -238,13 +238,17 @@ int rgsvd_batch_run(rgsvd_plan_t plan, void* stream);
 /* Tile shapes of the streaming kernels chosen by measurement on the caller's
  * data:
  * rows per tile of the G W kernel (1 or 4), columns per lane of the G^T Q
- * kernel (2 or 4) and the number of row chunks of its split reduction (the
- * heuristic count, half, twice).  Each valid combination is enqueued
+ * kernel (2 or 4), the number of row chunks of its split reduction (the
+ * heuristic count, half, twice) and, on the mixed path over FP32 storage,
+ * the kernels themselves (1: 8-wave workgroups sharing W or Q^T through LDS,
+ * whose tile shapes are fixed; 2: the per-wave kernels with the three
+ * knobs).  Each valid combination is enqueued
  * reps + 1 times on `stream` (outputs are written, one warm-up) and timed
  * with HIP events; the fastest is kept in the plan and in a per-process cache
  * keyed by the plan's shapes, storage type and precision, which later plans
- * of the same key start from.  choice (3 int32, may be NULL): rt, js, chunk
- * index (0 heuristic, 1 half, 2 twice); best_ms (may be NULL): mean run time
+ * of the same key start from.  choice (4 int32, may be NULL): rt, js, chunk
+ * index (0 heuristic, 1 half, 2 twice), kernel family (0 where there is
+ * no choice); best_ms (may be NULL): mean run time
  * of the choice.  Synchronises `stream`.  Fixed-size plans only.
  * rgsvd_batch_autotune takes the batch's pointers like rgsvd_batch_bind and
  * must be followed by rgsvd_batch_bind (which captures with the choice). */

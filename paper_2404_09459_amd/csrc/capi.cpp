@@ -137,8 +137,10 @@ struct rgsvd_plan_s {
   int block = 100;
   double* hscal = nullptr;   // pinned host copy of the per-side scalars
   // tile-shape knobs of the streaming kernels (0: heuristic); set by the
-  // autotuner or taken from its per-shape cache
-  int tune_rt = 0, tune_js = 0, tune_chunk = 0;
+  // autotuner or taken from its per-shape cache.  tune_wg picks the mixed
+  // path's streaming kernels over FP32 storage: 1 the 8-wave k_nn and k_tn,
+  // 2 the per-wave k_gw, k_gw4 and k_gtq
+  int tune_rt = 0, tune_js = 0, tune_chunk = 0, tune_wg = 0;
   int wave_slots = 2048;   // concurrently resident single-wave workgroups
   // job tables
   std::vector<unsigned char> host;   // serialized job tables
@@ -346,6 +348,10 @@ int build(rgsvd_plan_s* P, void* ws) {
   const int gt = (P->gdt == RGSVD_F64) ? 0 : 1;
   const bool mixed = (prec == PBF);
   const int ctL = ct_of([&] { int L = 16; for (auto& s : P->sides) L = std::max(L, s.L); return L; }());
+  // k_nn and k_tn share each k-step's W or Q^T across 8 waves behind one
+  // barrier; with up to 4 row tiles (L <= 64) a step holds too few MFMAs to
+  // pay for it, and the per-wave kernels are faster (a batch of narrow pairs)
+  const bool wg8 = mixed && gt == 1 && (P->tune_wg ? P->tune_wg == 1 : ctL >= 8);
   std::vector<SideLay>& S = P->sides;
   const int ns = (int)S.size();
   // row chunks of the G^T Q reductions: heuristic, half or twice as many
@@ -442,7 +448,7 @@ int build(rgsvd_plan_s* P, void* ws) {
   };
 
   auto add_nn = [&](int p) {
-    if (mixed && gt == 1) {
+    if (wg8) {
       // mixed path over FP32 G: 8-wave workgroups sharing the packed W in
       // LDS; the BF16 passes round G and W to BF16, the last power pass
       // (FP32 in the method) runs the FP32-accurate three-piece split
@@ -585,7 +591,7 @@ int build(rgsvd_plan_s* P, void* ws) {
 
   // G^T Q (or Q^T G) into the Wt buffers: split over row chunks then reduced
   auto add_tn = [&](int p) {
-    if (mixed && gt == 1) {
+    if (wg8) {
       // mixed path over FP32 G: 8-wave workgroups sharing the packed Q^T in
       // LDS; the BF16 pass rounds both operands, the FP32 passes of the
       // method run the three-piece split
@@ -1620,7 +1626,7 @@ int run_learned(rgsvd_plan_s* P, const void* G1, int64_t ld1, const void* G2, in
 // half of it or twice it).  Every valid combination runs `reps` times after
 // one warm-up with HIP events around the enqueued stages; the fastest total
 // wins and is remembered for the plan's shape key.
-struct TuneChoice { int rt, js, chunk; float ms; };
+struct TuneChoice { int rt, js, chunk, wg; float ms; };
 std::map<std::string, TuneChoice>& tune_cache() {
   static std::map<std::string, TuneChoice> c;
   return c;
@@ -1638,20 +1644,27 @@ void apply_cached_tune(rgsvd_plan_s* P) {
   auto it = tune_cache().find(shape_key(P));
   if (it == tune_cache().end()) return;
   P->tune_rt = it->second.rt; P->tune_js = it->second.js; P->tune_chunk = it->second.chunk;
+  P->tune_wg = it->second.wg;
 }
 
 int autotune_plan(rgsvd_plan_s* P, void* ws, hipStream_t st, int reps, int32_t* choice, float* best_ms) {
   const bool streamy = P->prec != P64 && P->gdt == RGSVD_F32;
+  const bool mixed = P->prec == PBF && P->gdt == RGSVD_F32;
+  // the mixed path's 8-wave kernels (k_nn, k_tn) have none of the three
+  // knobs; its per-wave kernels have all of them
   std::vector<int> rts = streamy ? std::vector<int>{1, 4} : std::vector<int>{1};
   std::vector<int> jss = streamy ? std::vector<int>{2, 4} : std::vector<int>{2};
+  std::vector<int> wgs = mixed ? std::vector<int>{1, 2} : std::vector<int>{0};
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return RGSVD_EHIP;
-  TuneChoice best{0, 0, 0, 1e30f};
+  TuneChoice best{0, 0, 0, 0, 1e30f};
   int rc = RGSVD_OK;
+  for (int wg : wgs)
   for (int rt : rts)
     for (int js : jss)
       for (int ch = 0; ch < 3 && !rc; ++ch) {
-        P->tune_rt = rt; P->tune_js = js; P->tune_chunk = ch;
+        if (wg == 1 && (rt != rts[0] || js != jss[0] || ch != 0)) continue;
+        P->tune_rt = rt; P->tune_js = js; P->tune_chunk = ch; P->tune_wg = wg;
         P->part = rgsvd_plan_s::FIXED;
         rc = build(P, ws);
         if (!rc) rc = upload(P, ws, st);
@@ -1664,16 +1677,16 @@ int autotune_plan(rgsvd_plan_s* P, void* ws, hipStream_t st, int reps, int32_t* 
         float ms = 0.0f;
         hipEventElapsedTime(&ms, e0, e1);
         ms /= (float)std::max(1, reps);
-        if (ms < best.ms) best = TuneChoice{rt, js, ch, ms};
+        if (ms < best.ms) best = TuneChoice{rt, js, ch, wg, ms};
       }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   if (rc) return rc;
-  P->tune_rt = best.rt; P->tune_js = best.js; P->tune_chunk = best.chunk;
+  P->tune_rt = best.rt; P->tune_js = best.js; P->tune_chunk = best.chunk; P->tune_wg = best.wg;
   tune_cache()[shape_key(P)] = best;
   P->bound = false;
   if (!P->batched) drop_graph(P);
-  if (choice) { choice[0] = best.rt; choice[1] = best.js; choice[2] = best.chunk; }
+  if (choice) { choice[0] = best.rt; choice[1] = best.js; choice[2] = best.chunk; choice[3] = best.wg; }
   if (best_ms) *best_ms = best.ms;
   return RGSVD_OK;
 }

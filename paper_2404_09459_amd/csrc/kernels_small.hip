@@ -787,6 +787,9 @@ __device__ inline int bj_sweeps(const BJState* S, double tol, bool& more) {
 //     column norms, never sqrt(1 - alpha^2)), X1, X2, (L Y)^T, quantities.
 // Stages (SmallJob::stage) split the step around the block Jacobi launches
 // on the factors of M and H.
+// largest order factored by the diagonally pivoted Cholesky in every case
+constexpr int PIVOT_MAX = 128;
+
 __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob& J, double* lds, int cap,
                                                              SmallShared& sh) {
   const int l1 = J.l1, N = J.l1 + J.l2, t = J.t;
@@ -833,11 +836,16 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
     double trM;
     bool more = true;
     if (stage <= 1) {
-      // unpivoted blocked Cholesky (the factor's Jacobi needs as many sweeps
-      // as on the greedily pivoted one); the pivoted form, which stops at the
-      // numerical rank, when a pivot fails
+      // up to order PIVOT_MAX the diagonally pivoted Cholesky: where B has
+      // fewer dominant directions than rows (noise columns in the sketch)
+      // its graded factor settles in up to half the Jacobi sweeps of the
+      // unpivoted one.  Above it the blocked unpivoted form, whose factor
+      // needed as many sweeps on the wide sketches measured, and whose cost
+      // does not grow with one barrier per column; the pivoted form, which
+      // stops at the numerical rank, when a pivot fails
       const int ldp = 16 * ((N + 15) / 16) + 4;
-      if (chol_unpivoted(J.M, J.ldm, N, F, sh.diag, lds, ldp, lds + 16 * ldp, &sh.scratch[5], &sh.trace))
+      if (N > PIVOT_MAX &&
+          chol_unpivoted(J.M, J.ldm, N, F, sh.diag, lds, ldp, lds + 16 * ldp, &sh.scratch[5], &sh.trace))
         rank = N;
       else
         rank = pivoted_cholesky(J.M, J.ldm, N, F, sh.diag, sh.act, lds, &sh.piv_j, &sh.piv_d, 0.0, &sh.trace);
@@ -903,7 +911,8 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
     __syncthreads();
     {
       const int ldp = 16 * ((t + 15) / 16) + 4;
-      if (chol_unpivoted(Hg, t, t, FH, sh.diag, lds, ldp, lds + 16 * ldp, &sh.scratch[5], &sh.trace))
+      if (t > PIVOT_MAX &&
+          chol_unpivoted(Hg, t, t, FH, sh.diag, lds, ldp, lds + 16 * ldp, &sh.scratch[5], &sh.trace))
         rh = t;
       else
         rh = pivoted_cholesky(Hg, t, t, FH, sh.diag, sh.act, lds, &sh.piv_j, &sh.piv_d, 0.0, &sh.trace);

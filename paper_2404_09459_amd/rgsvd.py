@@ -228,15 +228,15 @@ def run_static(plan, G1, G2, o):
 
 def autotune(plan, G1, G2, o, reps=2):
     """Pick the streaming kernels' tile shapes for `plan` by timing on these
-    inputs (outputs are written); returns ((rt, js, chunk), ms per run)."""
+    inputs (outputs are written); returns ((rt, js, chunk, kernel family), ms per run)."""
     m, n = G1.shape
     p = G2.shape[0]
     out = out_struct(o, m, p, n)
-    ch = (ctypes.c_int32 * 3)()
+    ch = (ctypes.c_int32 * 4)()
     ms = ctypes.c_float()
     check(lib().rgsvd_autotune(plan.h, _ptr(G1), G1.stride(0), _ptr(G2), G2.stride(0), plan.ws_ptr,
                                _stream(G1.device), ctypes.byref(out), reps, ch, ctypes.byref(ms)), "rgsvd_autotune")
-    return (ch[0], ch[1], ch[2]), ms.value
+    return (ch[0], ch[1], ch[2], ch[3]), ms.value
 
 
 _PLANS = {}
@@ -342,12 +342,12 @@ class BatchPlan:
             io[i].G1 = _ptr(G1); io[i].G2 = _ptr(G2)
             io[i].ld1 = G1.stride(0); io[i].ld2 = G2.stride(0)
             io[i].out = out_struct(o, G1.shape[0], G2.shape[0], G1.shape[1])
-        ch = (ctypes.c_int32 * 3)()
+        ch = (ctypes.c_int32 * 4)()
         ms = ctypes.c_float()
         check(lib().rgsvd_batch_autotune(self.h, io, self.ws_ptr, _stream(self.device), reps, ch,
                                          ctypes.byref(ms)), "rgsvd_batch_autotune")
         check(lib().rgsvd_batch_bind(self.h, io, self.ws_ptr, _stream(self.device)), "rgsvd_batch_bind")
-        return (ch[0], ch[1], ch[2]), ms.value
+        return (ch[0], ch[1], ch[2], ch[3]), ms.value
 
     def __del__(self):
         try:

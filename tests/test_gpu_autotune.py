@@ -53,7 +53,7 @@ def test_autotune_single_pair(dev):
     choice, ms = R.autotune(plan, g1, g2, out, reps=2)
     t_tuned = _time(plan, g1, g2, out)
     dth = np.max(np.abs(out["theta"].cpu().numpy() - base["theta"]))
-    _say(f"autotune {m}/{p}x{n} l={k + o_}: choice (rt, js, chunk) = {choice}, tuner {ms:.3f} ms;"
+    _say(f"autotune {m}/{p}x{n} l={k + o_}: choice (rt, js, chunk, family) = {choice}, tuner {ms:.3f} ms;"
          f" default {t_default:.3f} ms -> tuned {t_tuned:.3f} ms; |dtheta| vs default {dth:.1e}")
     assert t_tuned <= 1.10 * t_default
     assert dth <= 1e-5
