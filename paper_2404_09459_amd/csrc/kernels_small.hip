@@ -38,49 +38,70 @@ __device__ __forceinline__ double readlane_f64(double v, int lane) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Factor of one 16 x 16 diagonal block A = R^T R, run by one wave.  On entry
-// lane j < 16 holds column j of the block's upper part (d[i] = A[i][j] for
-// i <= j, zero elsewhere; lanes 16..63 zeros); on exit d holds column j of R
-// and x column j of R^{-1}.  d0(k) is the original diagonal entry of the
-// block's row k, for the pivot tests.  trunc: a pivot below CHOL_TRUNC_REL of
-// it gives a zero row k of R and of R^{-1} (the row eliminates nothing).
-// Returns whether a pivot failed (not finite, or not above both rel d0(k) and
-// floor), which cannot happen for a dropped row.
-template <typename D0>
-__device__ __forceinline__ bool factor_diag16(double (&d)[16], double (&x)[16], bool trunc, double rel, double floor,
-                                              D0 d0) {
-  const int j = threadIdx.x & 63;
-  double myinv = 0.0;    // 1 / R_jj of this lane's column (0 for a dropped row)
+// Factor of one 16 x 16 diagonal block A = R^T R by one wave, with X = R^{-T}
+// (the inverse of the lower factor L = R^T): elimination on the rows of
+// [A | I].  Lane (i, h) = (lane / 4, lane % 4) holds entries 4h .. 4h + 3 of
+// row i of both halves.  Step k scales row k by 1 / sqrt(pivot) (the hardware
+// estimate and two Newton steps), publishes it in `row` (32 doubles of LDS,
+// read by the same wave in order, so no barrier), and every row below
+// subtracts R_ki times it: the left half becomes R, the right half the
+// forward substitution L^{-1}.  On exit a[e] = R[i][4h + e] (4h + e >= i) and
+// b[e] = X[i][4h + e] (4h + e <= i).  blk(i, c) gives A[i][c] for c >= i;
+// d0(r) is the original diagonal entry of row r, for the pivot tests.
+// trunc: a pivot below CHOL_TRUNC_REL of it gives a zero row k of R and zero
+// row and column k of X (the row eliminates nothing).  Returns whether a
+// pivot failed (not finite, or not above both rel d0(k) and floor), which
+// cannot happen for a dropped row.
+template <typename BLK, typename D0>
+__device__ __forceinline__ bool factor_diag16(BLK blk, D0 d0, double* row, double (&a)[4], double (&b)[4],
+                                              bool trunc, double rel, double floor) {
+  const int ln = threadIdx.x & 63, i = ln >> 2, h = ln & 3;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int c = 4 * h + e;
+    a[e] = c >= i ? blk(i, c) : blk(c, i);
+    b[e] = c == i ? 1.0 : 0.0;
+  }
+  const double d0l = d0(ln & 15);
   bool bad = false;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
-    const double piv = readlane_f64(d[k], k);
-    const double dk0 = d0(k);
+    const double piv = readlane_f64(a[k & 3], 4 * k + (k >> 2));
+    const double dk0 = readlane_f64(d0l, k);
     if (trunc && isfinite(piv) && !(piv > CHOL_TRUNC_REL * dk0 && piv > 0.0)) {
-      if (j >= k) d[k] = 0.0;
+      if (i == k) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) { a[e] = 0.0; b[e] = 0.0; }
+      }
       continue;
     }
     if (!(piv > rel * dk0) || !(piv > floor) || !(piv > 0.0) || !isfinite(piv)) bad = true;
-    const double r = sqrt(piv), ri = 1.0 / r;
-    if (j == k) myinv = ri;
-    if (j >= k) d[k] = (j == k) ? r : d[k] * ri;
+    const double hp = 0.5 * piv;
+    double y = __builtin_amdgcn_rsq(piv);
+    y = y * fma(-hp * y, y, 1.5);
+    y = y * fma(-hp * y, y, 1.5);
+    if (i == k) {
 #pragma unroll
-    for (int i = k + 1; i < 16; ++i) {
-      const double rki = readlane_f64(d[k], i);
-      if (j >= i) d[i] -= rki * d[k];
+      for (int e = 0; e < 4; ++e) {
+        a[e] *= y;
+        b[e] *= y;
+        row[4 * h + e] = a[e];
+        row[16 + 4 * h + e] = b[e];
+      }
     }
-  }
-  // column j of R^{-1}: x_j = 1 / R_jj, x_i = -(sum_{m=i+1..j} R_im x_m) / R_ii,
-  // R_im and 1 / R_ii read from the lanes that hold them (LDS loads inside this
-  // dependent chain cost twice as much)
+    // the row is written before any lane reads it, and read before the next
+    // step writes it (LDS serves a wave in program order; the wave barrier
+    // keeps the compiler from moving the accesses across)
+    __builtin_amdgcn_wave_barrier();
+    if (i > k) {
+      const double rki = row[i];
 #pragma unroll
-  for (int i = 15; i >= 0; --i) {
-    double acc = 0.0;
-#pragma unroll
-    for (int m = i + 1; m < 16; ++m)
-      if (m <= j) acc += readlane_f64(d[i], m) * x[m];
-    const double rinv = readlane_f64(myinv, i);
-    x[i] = (i < j) ? -acc * rinv : (i == j ? rinv : 0.0);
+      for (int e = 0; e < 4; ++e) {
+        a[e] = fma(-rki, row[4 * h + e], a[e]);
+        b[e] = fma(-rki, row[16 + 4 * h + e], b[e]);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
   }
   return bad;
 }
@@ -179,21 +200,18 @@ __global__ __launch_bounds__(64 * CB_W) void k_chol(const CholJob* __restrict__ 
       }
       __syncthreads();
       if (wave == 0) {
-        // lane j < 16 holds column j of the block's upper part
-        const int j = ln;
-        double d[16], x[16];
+        // Dk serves as the factor's row buffer once read
+        double a[4], b[4];
+        const bool bad = factor_diag16([&](int r, int c) { return Dk[r * 16 + c]; },
+                                       [&](int r) { return d0[o + r]; }, Dk, a, b, J.trunc != 0, 1e-15, 0.0);
+        const int i = ln >> 2, h = ln & 3;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) d[i] = (j < 16 && i <= j) ? Dk[i * 16 + j] : 0.0;
-        const bool bad = factor_diag16(d, x, J.trunc != 0, 1e-15, 0.0, [&](int k) { return d0[o + k]; });
-        // row j of X_kk = R_kk^{-T} is column j of R_kk^{-1}
-        if (j < 16) {
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const double v = i <= j ? x[i] : 0.0;
-            Xk[j * 16 + i] = v;
-            xrow[j * CB_LD + o + i] = v;
-            if (i <= j && o + j < N) J.sinv[(int64_t)(o + j) * np + o + i] = v;
-          }
+        for (int e = 0; e < 4; ++e) {
+          const int c = 4 * h + e;
+          const double v = c <= i ? b[e] : 0.0;
+          Xk[i * 16 + c] = v;
+          xrow[i * CB_LD + o + c] = v;
+          if (c <= i && o + i < N) J.sinv[(int64_t)(o + i) * np + o + c] = v;
         }
         if (bad && ln == 0) bad_s = 1;
       }
@@ -658,19 +676,18 @@ __device__ __noinline__ bool chol_unpivoted(double* S, int64_t ld, int K, double
   for (int kb = 0; kb < nb; ++kb) {
     const int o = 16 * kb;
     if (wave == 0) {
-      const int j = ln;
-      double d[16], x[16];
+      // Xk serves as the factor's row buffer until it is written
+      double a[4], b[4];
+      const bool bad = factor_diag16([&](int r, int c) { return at(o + r, o + c); },
+                                     [&](int r) { return d0[o + r]; }, Xk, a, b, false, CHOL_TRUNC_REL, floor);
+      const int i = ln >> 2, h = ln & 3;
 #pragma unroll
-      for (int i = 0; i < 16; ++i) d[i] = (j < 16 && i <= j) ? at(o + i, o + j) : 0.0;
-      const bool bad = factor_diag16(d, x, false, CHOL_TRUNC_REL, floor, [&](int k) { return d0[o + k]; });
-      if (j < 16) {
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          Xk[j * 16 + i] = i <= j ? x[i] : 0.0;          // X_kk = R_kk^{-T}, row j
-          if (i <= j) {
-            panel[i * ldp + o + j] = d[i];                 // R[o + i][o + j]
-            if (o + j < K) F[(int64_t)(o + i) * K + o + j] = d[i];
-          }
+      for (int e = 0; e < 4; ++e) {
+        const int c = 4 * h + e;
+        Xk[i * 16 + c] = c <= i ? b[e] : 0.0;            // X_kk = R_kk^{-T}, row i
+        if (c >= i) {
+          panel[i * ldp + o + c] = a[e];                   // R[o + i][o + c]
+          if (o + c < K) F[(int64_t)(o + i) * K + o + c] = a[e];
         }
       }
       if (bad && ln == 0) *bad_s = 1;
