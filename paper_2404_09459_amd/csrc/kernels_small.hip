@@ -398,6 +398,37 @@ pair_step_padded(double* Lp, double* Lq, int j, bool live, double tol, double th
   return turn;
 }
 
+// The same with column p held in registers (x, EM rows per lane) across
+// steps: only column q passes through LDS.
+template <int G, int EM>
+__device__ __attribute__((always_inline)) inline bool
+pair_step_reg(double (&x)[EM], double* Lq, int j, bool live, double tol, double thr, double& rel2) {
+  double y[EM];
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int e = 0; e < EM; ++e) {
+    y[e] = Lq[j + G * e];
+    al = fma(x[e], x[e], al);
+    be = fma(y[e], y[e], be);
+    ga = fma(x[e], y[e], ga);
+  }
+  al = group_sum<G>(al);
+  be = group_sum<G>(be);
+  ga = group_sum<G>(ga);
+  double c, s;
+  const bool turn = jacobi_turn(al, be, ga, live, tol, thr, c, s);
+  if (turn) {
+    rel2 = fmax(rel2, ga * ga / (al * be));
+#pragma unroll
+    for (int e = 0; e < EM; ++e) {
+      const double xn = c * x[e] - s * y[e];
+      Lq[j + G * e] = s * x[e] + c * y[e];
+      x[e] = xn;
+    }
+  }
+  return turn;
+}
+
 // Round-robin tournament on m1 + 1 players (m1 odd): in round `round`,
 // slot pi (0 <= pi <= m1 / 2) pairs players u and v; slot 0 keeps player 0
 // and the others rotate, so every pair meets once in m1 rounds.
@@ -1148,14 +1179,29 @@ bj_visit(const BJJob& J, BJState* S, int w, int sweep, int round, double* lds, d
       __syncthreads();
     }
   }
-  for (int s2 = 0; s2 < B; ++s2) {
-    const int a = g, b = B + ((g + s2) & (B - 1));
-    any |= pair_step_padded<G, EM>(lds + a * LD, lds + b * LD, j, live(a, b), J.tol, thr, rel2);
+  // cross pairs: group g keeps column g for the B steps (in registers, one
+  // LDS read and write of it per round) and meets the columns of block v in
+  // turn, which pass from group to group through LDS
+  {
+    const int a = g;
+    double x[EM];
+#pragma unroll
+    for (int e = 0; e < EM; ++e) x[e] = lds[a * LD + j + G * e];
+    for (int s2 = 0; s2 < B; ++s2) {
+      const int b = B + ((g + s2) & (B - 1));
+      any |= pair_step_reg<G, EM>(x, lds + b * LD, j, live(a, b), J.tol, thr, rel2);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int e = 0; e < EM; ++e) lds[a * LD + j + G * e] = x[e];
     __syncthreads();
   }
   for (int o = 32; o > 0; o >>= 1) rel2 = fmax(rel2, __shfl_xor(rel2, o, 64));
   if ((tid & 63) == 0 && rel2 > 0.0)
     atomicMax((unsigned long long*)&S->rel[sweep & 1], (unsigned long long)__double_as_longlong(rel2));
+  // rotations seen: one flag per wave, before the write-back (no barrier
+  // after the last step's)
+  if (__any(any) && (tid & 63) == 0) atomicOr(&S->rot[sweep & 1], 1);
   // write back; in the last round of the sweep every column passes through
   // exactly one workgroup, which leaves its squared norm for the next sweep
   double n2 = 0.0;
@@ -1172,7 +1218,6 @@ bj_visit(const BJJob& J, BJState* S, int w, int sweep, int round, double* lds, d
     n2 = group_sum<TPC>(n2);
     if (sc_ok && sc_j == 0) J.nrm2[gcol(sc_c)] = n2;
   }
-  if (__syncthreads_or(any) && tid == 0) atomicOr(&S->rot[sweep & 1], 1);
 }
 
 // One round of one sweep for every job (nblk / 2 workgroups each).
