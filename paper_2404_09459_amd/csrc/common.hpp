@@ -128,17 +128,6 @@ __device__ __forceinline__ double swz16_f64(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// A double from lane ^ 32 (v_permlane32_swap of the value with itself: the
-// low half receives the high half's values and the high half the low's).
-__device__ __forceinline__ double swap32_f64(double v) {
-  const long long b = __double_as_longlong(v);
-  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)b, (unsigned)b, false, false);
-  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)(b >> 32), (unsigned)(b >> 32), false, false);
-  const bool low = (threadIdx.x & 63) < 32;
-  const unsigned plo = low ? lo[1] : lo[0], phi = low ? hi[1] : hi[0];
-  return __longlong_as_double(((long long)phi << 32) | plo);
-}
-
 // Sum over each aligned group of G lanes (G a power of two <= 64), left in
 // every lane of the group.  Each step adds a partner holding the same
 // partial (quad xor 1, xor 2; 8-lane mirror; 16-lane mirror; lane ^ 16;
