@@ -159,6 +159,13 @@ def bench_batch(args):
     torch.cuda.synchronize()
     log(f"[bench] batch: 256 pairs generated on the device in {time.time() - t0:.1f}s")
     plan = R.BatchPlan(descs, dev)
+    tune = None
+    if not args.no_tune:
+        choice, tms = plan.autotune(pairs, reps=2)
+        tune = {"rows_per_tile": choice[0], "cols_per_lane": choice[1],
+                "chunks": ["heuristic", "half", "twice"][choice[2]],
+                "kernels": {0: None, 1: "8-wave k_nn/k_tn", 2: "per-wave k_gw/k_gtq"}[choice[3]], "ms": tms}
+        log(f"[bench] batch: autotuned tile shapes {tune}")
     outs = plan.bind(pairs)
     for _ in range(args.warmup):
         plan.run()
@@ -213,6 +220,7 @@ def bench_batch(args):
                                "10..50, decays 0.6..0.95, noise 1e-5, FP32, BF16 sketches, oversample 10, q=2, "
                                "one captured graph",
                    "pairs": len(specs), "power_iters": q, "path": "mixed"},
+        "autotune": tune,
         "accuracy_gate_passed": gate,
         "roofline": roof,
         "cpu_baseline": cpu,
