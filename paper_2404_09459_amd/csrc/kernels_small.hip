@@ -544,37 +544,56 @@ __device__ inline int rank_desc(const double* key, int n, int i) {
 }
 
 // --------------------------------------------------------------- k_small --
-// C = A B in one workgroup on FP64 MFMA (16 x 16 output tiles, one per
-// wave at a time, k in steps of 4): element (i, k) of A at
+// C = A B in one workgroup on FP64 MFMA: element (i, k) of A at
 // A[i sai + k sak], element (k, j) of B at B[k sbk + j sbj]; I x J output,
-// inner order K.  store(i, j, v) receives every output element once; with
-// SYM (A B symmetric, I == J) only tiles on or above the diagonal are formed
-// and store(i, j, v) is called for i <= j.
+// inner order K.  A wave takes a strip of TW 16 x 16 output tiles along j
+// at a time: per step of 4 in k it loads one A fragment and TW B fragments
+// and runs TW independent MFMA chains (a single tile's chain waits on its
+// loads at every step).  store(i, j, v) receives every output element once;
+// with SYM (A B symmetric, I == J) only strips reaching the diagonal are
+// formed and store(i, j, v) is called for i <= j.
 template <bool SYM, typename Store>
 __device__ __attribute__((always_inline)) inline void
 wg_gemm64(const double* A, int64_t sai, int64_t sak, const double* B, int64_t sbk, int64_t sbj, int I, int J,
           int K, Store store) {
+  constexpr int TW = 4;
   const int wave = threadIdx.x >> 6, ln = threadIdx.x & 63, r16 = ln & 15, g = ln >> 4;
-  const int ti = (I + 15) / 16, tj = (J + 15) / 16;
-  for (int tile = wave; tile < ti * tj; tile += 16) {
-    const int bi = tile / tj, bj = tile - bi * tj;
-    if (SYM && bi > bj) continue;
-    const int ia = bi * 16 + r16, jb = bj * 16 + r16;
-    const bool oka = ia < I, okb = jb < J;
+  const int ti = (I + 15) / 16, tj = (J + 15) / 16, ts = (tj + TW - 1) / TW;
+  for (int strip = wave; strip < ti * ts; strip += 16) {
+    const int bi = strip / ts, bs = strip - bi * ts;
+    if (SYM && TW * bs + TW - 1 < bi) continue;
+    const int ia = bi * 16 + r16;
+    const bool oka = ia < I;
     const double* pa = A + (oka ? ia : 0) * sai;
-    const double* pb = B + (okb ? jb : 0) * sbj;
-    d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 4
+    const double* pb[TW];
+    bool okb[TW];
+#pragma unroll
+    for (int u = 0; u < TW; ++u) {
+      const int jb = (TW * bs + u) * 16 + r16;
+      okb[u] = jb < J;
+      pb[u] = B + (okb[u] ? jb : 0) * sbj;
+    }
+    d4 acc[TW];
+#pragma unroll
+    for (int u = 0; u < TW; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
     for (int k0 = 0; k0 < K; k0 += 4) {
       const int k = k0 + g;
       const double a = (oka && k < K) ? pa[k * sak] : 0.0;
-      const double b = (okb && k < K) ? pb[k * sbk] : 0.0;
-      acc = mma64(a, b, acc);
+#pragma unroll
+      for (int u = 0; u < TW; ++u) {
+        const double b = (okb[u] && k < K) ? pb[u][k * sbk] : 0.0;
+        acc[u] = mma64(a, b, acc[u]);
+      }
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = bi * 16 + out_row<0>(g, q);
-      if (i < I && jb < J && (!SYM || i <= jb)) store(i, jb, acc[q]);
+    for (int u = 0; u < TW; ++u) {
+      const int jb = (TW * bs + u) * 16 + r16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = bi * 16 + out_row<0>(g, q);
+        if (i < I && jb < J && (!SYM || i <= jb)) store(i, jb, acc[u][q]);
+      }
     }
   }
 }
