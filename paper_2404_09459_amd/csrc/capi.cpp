@@ -958,6 +958,7 @@ int build(rgsvd_plan_s* P, void* ws) {
       x.X2t = (double*)WS(ws, pr.X2t); x.ldx2 = pr.l2;
       x.Rcoef = (double*)WS(ws, pr.Rcoef); x.ldr = pr.N;
       x.info = info_of((int)pi);
+      x.ycs = (double*)WS(ws, pr.bjn);   // free once H's block Jacobi is done
       return x;
     };
     auto add_small = [&](int stage) {
@@ -965,7 +966,7 @@ int build(rgsvd_plan_s* P, void* ws) {
       for (size_t pi = 0; pi < P->pairs.size(); ++pi) {
         const auto& pr = P->pairs[pi];
         const int st = stage == 1 ? (bjm(pr) ? 1 : 0) : stage;
-        if ((stage == 2 && !bjm(pr)) || (stage == 3 && !bjh(pr))) continue;
+        if ((stage == 2 && !bjm(pr)) || (stage >= 3 && !bjh(pr))) continue;
         sj.push_back(small_job(pi, st)); tl.push_back(1);
       }
       if (!sj.empty()) B.add(K_SMALL, sj, tl).tag = T_SMALL;
@@ -1006,7 +1007,33 @@ int build(rgsvd_plan_s* P, void* ws) {
     for (auto& pr : P->pairs) { any_m |= bjm(pr); any_h |= bjh(pr); }
     add_small(1);
     if (any_m) { add_bj(false); add_small(2); }
-    if (any_h) { add_bj(true); add_small(3); }
+    if (any_h) {
+      add_bj(true);
+      add_small(3);
+      // Rcoef = (L Y)^T = diag(ycs) (H's factor)^T L^T on FP64 MFMA over 64-column
+      // tiles of L^T (one workgroup held it as 16 waves before), then stage 4
+      std::vector<AbJob> aj; std::vector<int> atl;
+      int tmax = 1;
+      for (size_t pi = 0; pi < P->pairs.size(); ++pi) {
+        auto& pr = P->pairs[pi];
+        if (!bjh(pr)) continue;
+        const int N = pr.l1 + pr.l2, t = pr.t;
+        double* Lg = (double*)WS(ws, pr.work);
+        AbJob a{};
+        a.A = Lg + (size_t)N * t + (size_t)t * t; a.lda = t;   // factor of H, column-major: its transpose
+        a.B = Lg; a.ldb = N;                                    // L (N x t, column-major): L^T
+        a.D = WS(ws, pr.Rcoef); a.ldd = pr.N;
+        a.rows = t; a.K = t; a.J = N; a.accumulate = 0;
+        a.colscale = (const double*)WS(ws, pr.bjn);
+        aj.push_back(a);
+        atl.push_back((N + 63) / 64);
+        tmax = std::max(tmax, t);
+      }
+      Stage& a = B.add(K_AB, aj, atl);
+      a.prec = P64; a.ta = 0; a.tb = 0; a.td = 0; a.ct = ct_of(tmax); a.js = 1;
+      a.tag = T_SMALL;
+      add_small(4);
+    }
   }
   // recovery: R (needed for the sign convention), then U, V
   const int ctT = ct_of([&] { int t = 1; for (auto& pr : P->pairs) t = std::max(t, pr.t); return t; }());

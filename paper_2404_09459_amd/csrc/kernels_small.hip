@@ -989,32 +989,46 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
       return;
     }
   }
-  {
-    // Jacobi on the factor of H (after the block sweeps in stage 3)
-    int base = 0;
-    bool more = true;
-    if (stage == 3) {
-      sw1 = S->sw1;
-      rh = S->nc;
-      base = bj_sweeps(S, J.tol, more);
+  if (stage == 4) {
+    sw1 = S->sw1;
+    sw2 = S->sw2;
+  } else {
+    {
+      // Jacobi on the factor of H (after the block sweeps in stage 3)
+      int base = 0;
+      bool more = true;
+      if (stage == 3) {
+        sw1 = S->sw1;
+        rh = S->nc;
+        base = bj_sweeps(S, J.tol, more);
+      }
+      sw2 = base + (more ? jacobi_any(FH, t, t, rh, J.tol, J.maxsweep - base, 0, sh, lds, cap) : 0);
     }
-    sw2 = base + (more ? jacobi_any(FH, t, t, rh, J.tol, J.maxsweep - base, 0, sh, lds, cap) : 0);
+    for (int c = tid >> 6; c < t; c += 16) {
+      double s = 0.0;
+      if (c < rh)
+        for (int r = tid & 63; r < t; r += 64) { const double v = FH[(int64_t)c * t + r]; s += v * v; }
+      s = wave_sum(s);
+      if ((tid & 63) == 0) keys[c] = sqrt(s);
+    }
+    __syncthreads();
+    if (stage == 3) {
+      // L Y runs on many workgroups between this launch and stage 4
+      for (int c = tid; c < t; c += 1024) {
+        const double nv = keys[c];
+        J.ycs[c] = (c < rh && nv > 0.0) ? 1.0 / nv : 0.0;
+      }
+      if (tid == 0) S->sw2 = sw2;
+      return;
+    }
+    // ---- 4. L Y (rows of Rcoef), alpha, beta (sorted by alpha)
+    // row r, column c of L Y (column c of Y = column c of FH / its norm)
+    wg_gemm64<false>(Lg, 1, N, FH, 1, t, N, t, t, [&](int r, int c, double v) {
+      const double nv = keys[c];
+      J.Rcoef[(int64_t)c * J.ldr + r] = (c < rh && nv > 0.0) ? v / nv : 0.0;    // unsorted for now
+    });
+    __syncthreads();
   }
-  for (int c = tid >> 6; c < t; c += 16) {
-    double s = 0.0;
-    if (c < rh)
-      for (int r = tid & 63; r < t; r += 64) { const double v = FH[(int64_t)c * t + r]; s += v * v; }
-    s = wave_sum(s);
-    if ((tid & 63) == 0) keys[c] = sqrt(s);
-  }
-  __syncthreads();
-  // ---- 4. L Y (rows of Rcoef), alpha, beta (sorted by alpha)
-  // row r, column c of L Y (column c of Y = column c of FH / its norm)
-  wg_gemm64<false>(Lg, 1, N, FH, 1, t, N, t, t, [&](int r, int c, double v) {
-    const double nv = keys[c];
-    J.Rcoef[(int64_t)c * J.ldr + r] = (c < rh && nv > 0.0) ? v / nv : 0.0;    // unsorted for now
-  });
-  __syncthreads();
   for (int c = tid >> 6; c < t; c += 16) {
     double a = 0.0, b = 0.0;
     for (int r = tid & 63; r < N; r += 64) {

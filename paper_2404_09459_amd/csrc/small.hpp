@@ -30,7 +30,7 @@ constexpr int BJ_THREADS = 512;
 // sweep and round kernels (device memory, one per pair).
 struct BJState {
   int32_t nc, nr, topk, done;       // columns, rows, dominant count, converged flag
-  int32_t sweeps, rank, sw1, pad;   // sweeps started; rank of M; sweeps on M
+  int32_t sweeps, rank, sw1, sw2;   // sweeps started; rank of M; sweeps on M and on H
   int32_t rot[2];                   // rotations seen in the sweep of that parity
   double thr;                       // skip threshold of the sweep (-1: none)
   double trM;                       // trace of M (M is overwritten by its factorisation)
@@ -44,7 +44,10 @@ struct BJState {
 // stage 0 runs the whole step.  With the block Jacobi the step runs in
 // stages: 1 factors M and stops before its Jacobi; 2 finishes that Jacobi,
 // forms H, factors it and stops before its Jacobi when bjh is set (else
-// runs to the end); 3 finishes the Jacobi on H and runs to the end.
+// runs to the end); 3 finishes the Jacobi on H and leaves the reciprocal
+// norms of its factor's columns in ycs, for the product L Y that a
+// multi-workgroup launch (k_ab) writes into Rcoef; 4 runs from there to the
+// end.
 struct SmallJob {
   double* M; int64_t ldm;           // overwritten by the pivoted Cholesky
   int32_t l1, l2, t, maxsweep;
@@ -58,6 +61,7 @@ struct SmallJob {
   double* X2t; int64_t ldx2;        // t x l2
   double* Rcoef; int64_t ldr;       // t x N  ((L Y)^T)
   int32_t* info;
+  double* ycs;                      // t: 1 / ||column c of H's factor|| (0 past its rank), stage 3
 };
 
 // sign convention of one pair: sgn[i] from row i of R (t x n)
