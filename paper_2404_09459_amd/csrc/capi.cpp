@@ -959,6 +959,7 @@ int build(rgsvd_plan_s* P, void* ws) {
       x.Rcoef = (double*)WS(ws, pr.Rcoef); x.ldr = pr.N;
       x.info = info_of((int)pi);
       x.ycs = (double*)WS(ws, pr.bjn);   // free once H's block Jacobi is done
+      x.hgram = bjh(pr) ? 1 : 0;
       return x;
     };
     auto add_small = [&](int stage) {
@@ -966,7 +967,7 @@ int build(rgsvd_plan_s* P, void* ws) {
       for (size_t pi = 0; pi < P->pairs.size(); ++pi) {
         const auto& pr = P->pairs[pi];
         const int st = stage == 1 ? (bjm(pr) ? 1 : 0) : stage;
-        if ((stage == 2 && !bjm(pr)) || (stage >= 3 && !bjh(pr))) continue;
+        if ((stage == 2 && !bjm(pr)) || (stage >= 3 && !bjh(pr))) continue;   // 3, 4, 5: H on the block Jacobi
         sj.push_back(small_job(pi, st)); tl.push_back(1);
       }
       if (!sj.empty()) B.add(K_SMALL, sj, tl).tag = T_SMALL;
@@ -1008,6 +1009,37 @@ int build(rgsvd_plan_s* P, void* ws) {
     add_small(1);
     if (any_m) { add_bj(false); add_small(2); }
     if (any_h) {
+      // H = L1^T L1 on FP64 MFMA across workgroups: the Gram of the rows of
+      // L^T (columns of L, l1 entries each) in up to four chunks of l1, whose
+      // partials go to mpart (free since M's reduction), then their
+      // fixed-order sum into H (t x t)
+      std::vector<GramJob> gj; std::vector<int> gtl;
+      std::vector<RedJob> rj; std::vector<int> rtl;
+      for (size_t pi = 0; pi < P->pairs.size(); ++pi) {
+        auto& pr = P->pairs[pi];
+        if (!bjh(pr)) continue;
+        const int N = pr.l1 + pr.l2, t = pr.t;
+        const int hpad = 64 * ((t + 63) / 64);
+        const int64_t room = (int64_t)pr.gch * pr.Npad * pr.Npad / ((int64_t)hpad * hpad);
+        const int hch = (int)std::max<int64_t>(1, std::min<int64_t>({4, room, (pr.l1 + 31) / 32}));
+        const int hcl = (int)upi((pr.l1 + hch - 1) / hch, 32);
+        double* Lg = (double*)WS(ws, pr.work);
+        GramJob g{};
+        g.X1 = Lg; g.X2 = Lg; g.out = (double*)WS(ws, pr.mpart);
+        g.ld1 = N; g.ld2 = N; g.r1 = t; g.r2 = 0; g.k0 = 0; g.k1 = pr.l1;
+        g.npad = hpad; g.clen = hcl;
+        gj.push_back(g);
+        gtl.push_back(gram_strips(t) * ((pr.l1 + hcl - 1) / hcl));
+        RedJob r{};
+        r.in = WS(ws, pr.mpart); r.out = Lg + (size_t)N * t; r.sq = nullptr;
+        r.stride = (int64_t)hpad * hpad; r.count = (int64_t)t * t;
+        r.nparts = (pr.l1 + hcl - 1) / hcl; r.rows = t; r.cols = t; r.ldo = t; r.ldi = hpad;
+        r.nz = t;
+        rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
+      }
+      Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = 0; gs.tag = T_SMALL;
+      Stage& rs = B.add(K_RED, rj, rtl); rs.sym = true; rs.tag = T_SMALL;
+      add_small(5);
       add_bj(true);
       add_small(3);
       // Rcoef = (L Y)^T = diag(ycs) (H's factor)^T L^T on FP64 MFMA over 64-column

@@ -897,81 +897,91 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
   } else if (S->rank < 0) {
     return;
   }
-  if (stage <= 2) {
-    // ---- 1. eigen-decomposition of M
-    int rank, base = 0;
-    double trM;
-    bool more = true;
-    if (stage <= 1) {
-      // up to order PIVOT_MAX the diagonally pivoted Cholesky: where B has
-      // fewer dominant directions than rows (noise columns in the sketch)
-      // its graded factor settles in up to half the Jacobi sweeps of the
-      // unpivoted one.  Above it the blocked unpivoted form, whose factor
-      // needed as many sweeps on the wide sketches measured, and whose cost
-      // does not grow with one barrier per column; the pivoted form, which
-      // stops at the numerical rank, when a pivot fails
-      const int ldp = 16 * ((N + 15) / 16) + 4;
-      if (N > PIVOT_MAX &&
-          chol_unpivoted(J.M, J.ldm, N, F, sh.diag, lds, ldp, lds + 16 * ldp, &sh.scratch[5], &sh.trace))
-        rank = N;
-      else
-        rank = pivoted_cholesky(J.M, J.ldm, N, F, sh.diag, sh.act, lds, &sh.piv_j, &sh.piv_d, 0.0, &sh.trace);
-      trM = sh.trace;
-      if (stage == 1) {
-        if (tid == 0) { S->rank = rank; S->trM = trM; bj_start(S, rank, N, t < rank ? t : rank); }
+  if (stage <= 2 || stage == 5) {
+    if (stage != 5) {
+      // ---- 1. eigen-decomposition of M
+      int rank, base = 0;
+      double trM;
+      bool more = true;
+      if (stage <= 1) {
+        // up to order PIVOT_MAX the diagonally pivoted Cholesky: where B has
+        // fewer dominant directions than rows (noise columns in the sketch)
+        // its graded factor settles in up to half the Jacobi sweeps of the
+        // unpivoted one.  Above it the blocked unpivoted form, whose factor
+        // needed as many sweeps on the wide sketches measured, and whose cost
+        // does not grow with one barrier per column; the pivoted form, which
+        // stops at the numerical rank, when a pivot fails
+        const int ldp = 16 * ((N + 15) / 16) + 4;
+        if (N > PIVOT_MAX &&
+            chol_unpivoted(J.M, J.ldm, N, F, sh.diag, lds, ldp, lds + 16 * ldp, &sh.scratch[5], &sh.trace))
+          rank = N;
+        else
+          rank = pivoted_cholesky(J.M, J.ldm, N, F, sh.diag, sh.act, lds, &sh.piv_j, &sh.piv_d, 0.0, &sh.trace);
+        trM = sh.trace;
+        if (stage == 1) {
+          if (tid == 0) { S->rank = rank; S->trM = trM; bj_start(S, rank, N, t < rank ? t : rank); }
+          return;
+        }
+      } else {
+        rank = S->rank;
+        trM = S->trM;
+        base = bj_sweeps(S, J.tol, more);
+      }
+      const int tt = t < rank ? t : rank;
+      // above order 256 the block sweeps are the whole budget of the factor:
+      // one that has not settled after them keeps FLAG_JACOBI_M rather than
+      // running single-workgroup sweeps of tens of ms each (20 ms at order
+      // 440); smaller factors finish on the single workgroup
+      if (stage == 2 && more && N > 256) {
+        sw1 = J.maxsweep + 1;
+      } else {
+        sw1 = base + (more ? jacobi_any(F, N, N, rank, J.tol, J.maxsweep - base, tt, sh, lds, cap) : 0);
+      }
+      // column norms of F: one wave per column, lanes striding its rows (one
+      // thread walking a whole column serialises its loads)
+      for (int c = tid >> 6; c < N; c += 16) {
+        double s = 0.0;
+        if (c < rank)
+          for (int r = tid & 63; r < N; r += 64) { const double v = F[(int64_t)c * N + r]; s += v * v; }
+        s = wave_sum(s);
+        if ((tid & 63) == 0) keys[c] = sqrt(s);
+      }
+      __syncthreads();
+      for (int c = tid; c < N; c += 1024) perm[rank_desc(keys, N, c)] = c;
+      __syncthreads();
+      // sigma_B: t dominant singular values of B, then the tail's Frobenius norm
+      if (tid < 64) {
+        double top = 0.0;
+        for (int i = tid; i < t; i += 64) { const double v = keys[perm[i]]; top += v * v; }
+        top = wave_sum(top);
+        if (tid == 0) sh.kth = sqrt(fmax(0.0, trM - top));
+      }
+      __syncthreads();
+      for (int i = tid; i < N; i += 1024)
+        J.sigma[i] = (i < t) ? keys[perm[i]] : (i == t ? sh.kth : 0.0);
+      // ---- 2. L = normalised dominant columns of F (N x t)
+      for (int e = tid; e < N * t; e += 1024) {
+        const int c = e / N, r = e - c * N;
+        const int src = perm[c];
+        const double nv = keys[src];
+        Lg[e] = (c < tt && nv > 0.0) ? F[(int64_t)src * N + r] / nv : 0.0;
+      }
+      __syncthreads();
+      // with hgram set, H comes from the multi-workgroup Gram launches
+      // after this stage, and stage 5 factors it
+      if (J.hgram) {
+        if (tid == 0) S->sw1 = sw1;
         return;
       }
+      // ---- 3. H = L1^T L1 + eps I, its eigenvectors Y (F is free again)
+      wg_gemm64<true>(Lg, N, 1, Lg, 1, N, t, t, l1, [&](int i, int j, double v) {
+        Hg[(int64_t)i * t + j] = v;
+        Hg[(int64_t)j * t + i] = v;
+      });
+      __syncthreads();
     } else {
-      rank = S->rank;
-      trM = S->trM;
-      base = bj_sweeps(S, J.tol, more);
+      sw1 = S->sw1;
     }
-    const int tt = t < rank ? t : rank;
-    // above order 256 the block sweeps are the whole budget of the factor:
-    // one that has not settled after them keeps FLAG_JACOBI_M rather than
-    // running single-workgroup sweeps of tens of ms each (20 ms at order
-    // 440); smaller factors finish on the single workgroup
-    if (stage == 2 && more && N > 256) {
-      sw1 = J.maxsweep + 1;
-    } else {
-      sw1 = base + (more ? jacobi_any(F, N, N, rank, J.tol, J.maxsweep - base, tt, sh, lds, cap) : 0);
-    }
-    // column norms of F: one wave per column, lanes striding its rows (one
-    // thread walking a whole column serialises its loads)
-    for (int c = tid >> 6; c < N; c += 16) {
-      double s = 0.0;
-      if (c < rank)
-        for (int r = tid & 63; r < N; r += 64) { const double v = F[(int64_t)c * N + r]; s += v * v; }
-      s = wave_sum(s);
-      if ((tid & 63) == 0) keys[c] = sqrt(s);
-    }
-    __syncthreads();
-    for (int c = tid; c < N; c += 1024) perm[rank_desc(keys, N, c)] = c;
-    __syncthreads();
-    // sigma_B: t dominant singular values of B, then the tail's Frobenius norm
-    if (tid < 64) {
-      double top = 0.0;
-      for (int i = tid; i < t; i += 64) { const double v = keys[perm[i]]; top += v * v; }
-      top = wave_sum(top);
-      if (tid == 0) sh.kth = sqrt(fmax(0.0, trM - top));
-    }
-    __syncthreads();
-    for (int i = tid; i < N; i += 1024)
-      J.sigma[i] = (i < t) ? keys[perm[i]] : (i == t ? sh.kth : 0.0);
-    // ---- 2. L = normalised dominant columns of F (N x t)
-    for (int e = tid; e < N * t; e += 1024) {
-      const int c = e / N, r = e - c * N;
-      const int src = perm[c];
-      const double nv = keys[src];
-      Lg[e] = (c < tt && nv > 0.0) ? F[(int64_t)src * N + r] / nv : 0.0;
-    }
-    __syncthreads();
-    // ---- 3. H = L1^T L1 + eps I, its eigenvectors Y (F is free again)
-    wg_gemm64<true>(Lg, N, 1, Lg, 1, N, t, t, l1, [&](int i, int j, double v) {
-      Hg[(int64_t)i * t + j] = v;
-      Hg[(int64_t)j * t + i] = v;
-    });
-    __syncthreads();
     // H + 1e-12 I (the shift leaves the eigenvectors and keeps the factor
     // positive definite when L1 has fewer rows than t or some alpha is 0)
     for (int i = tid; i < t; i += 1024) Hg[(int64_t)i * t + i] += 1e-12;

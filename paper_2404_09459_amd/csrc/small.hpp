@@ -47,7 +47,9 @@ struct BJState {
 // runs to the end); 3 finishes the Jacobi on H and leaves the reciprocal
 // norms of its factor's columns in ycs, for the product L Y that a
 // multi-workgroup launch (k_ab) writes into Rcoef; 4 runs from there to the
-// end.
+// end.  With hgram set, stage 2 stops once L is formed, multi-workgroup
+// launches (k_gram, k_reduce) form H = L1^T L1, and stage 5 factors H and
+// stops before its Jacobi.
 struct SmallJob {
   double* M; int64_t ldm;           // overwritten by the pivoted Cholesky
   int32_t l1, l2, t, maxsweep;
@@ -62,6 +64,7 @@ struct SmallJob {
   double* Rcoef; int64_t ldr;       // t x N  ((L Y)^T)
   int32_t* info;
   double* ycs;                      // t: 1 / ||column c of H's factor|| (0 past its rank), stage 3
+  int32_t hgram, pad2;
 };
 
 // sign convention of one pair: sgn[i] from row i of R (t x n)
