@@ -895,6 +895,10 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
       return;
     }
   } else if (S->rank < 0) {
+    // stage 4 clears Rcoef again: the multi-workgroup L Y launch before it
+    // does not read the state
+    if (stage == 4)
+      for (int e = tid; e < t * N; e += 1024) J.Rcoef[(int64_t)(e / N) * J.ldr + e % N] = 0.0;
     return;
   }
   if (stage <= 2 || stage == 5) {

@@ -237,3 +237,26 @@ def test_nonfinite_input_flagged(dev):
     # a clean run on the same plan afterwards is unaffected
     clean = _run(dev, I.small_fp64_pair()["G1"], G2, 20, 10, 1, 1)
     assert "nonfinite" not in _flags(clean) and np.all(np.isfinite(clean["alpha"]))
+
+
+def test_nonfinite_input_flagged_staged(dev):
+    """The same at t = 120, where H's eigenproblem runs on the block Jacobi and
+    H = L1^T L1 and L Y on multi-workgroup launches between the small step's
+    stages: NaN GSVs and the flag, and a clean run on the same plan before and
+    after gives bit-identical results (no state left behind)."""
+    from paper_2404_09459_amd import inputs as I
+    m, p, n, k = 1200, 1000, 400, 120
+    j = np.arange(k)
+    G1, G2 = I.lowrank_pair(m, p, n, k, 0.97 ** j, 0.95 ** j, 77, noise_entry=1e-6, dtype=np.float64)
+    before = _run(dev, G1, G2, k, 10, 1, 3)
+    assert "nonfinite" not in _flags(before) and np.all(np.isfinite(before["alpha"]))
+    G1n = G1.copy()
+    G1n[5, 7] = np.inf
+    _say(f"inf in G1[5, 7] at m={m} p={p} n={n} k={k}: the run must end with FLAG_NONFINITE")
+    got = _run(dev, G1n, G2, k, 10, 1, 3)
+    _say(f"   flags {_flags(got)} info {got['info'].tolist()}")
+    assert "nonfinite" in _flags(got)
+    assert np.all(np.isnan(got["alpha"])) and np.all(np.isnan(got["D"]))
+    after = _run(dev, G1, G2, k, 10, 1, 3)
+    for key in ("alpha", "beta", "theta", "U", "V", "R"):
+        assert np.array_equal(before[key], after[key]), key
