@@ -40,11 +40,12 @@ MFMA_PEAK_TF = {"fp64": 78.6, "fp32": 157.3, "mixed": 2516.6}
 FP64_VEC_PEAK_TF = 78.6
 # HBM bytes per launch from FETCH_SIZE and WRITE_SIZE, each scaled by what it
 # reads for a copy kernel of known size (profiles/hbm_counters_*.md), keyed by
-# workload: the mixed sketch pass (k_nn, BF16) and the block Jacobi launches
-# (k_bjinit + k_bjround, averaged over the launches of a run).  Kernels changed
-# since their counters were taken have no entry (traffic null).
+# workload: the mixed sketch pass (k_nn, BF16), the block Jacobi launches
+# (k_bjinit + k_bjround, averaged over the launches of a run) and the small
+# step's k_small launches (averaged).  Kernels changed since their counters
+# were taken have no entry (traffic null).
 TRAFFIC = {"large": {"sketch": 1.659e9, "bjacobi": 1.956e6},
-           "medium": {"bjacobi": 0.56e6}}
+           "medium": {"sketch": 0.743e9, "bjacobi": 0.56e6, "small": 1.4e6}}
 
 
 def log(*a):
@@ -392,7 +393,7 @@ def roofline_of(dom_tag, dom_ms, dom_cnt, info, m, p, n, k, l, esz, flag, worklo
         sw2 = int(info[6])
         flops = N ** 3 / 3.0 + l * t * (t + 1.0) + t ** 3 / 3.0 + sw2 * 6.0 * t * t * (t - 1) + 2.0 * N * t * t
         roof = {"bound": "alu", "achieved": flops / (dom_ms * 1e-3) / 1e12, "peak": FP64_VEC_PEAK_TF,
-                "unit": "TFLOP/s", "traffic": None}
+                "unit": "TFLOP/s", "traffic": TRAFFIC.get(workload_name, {}).get("small")}
     elif dom_tag == "chol":
         # Cholesky and inverse of the l x l Gram of both sides per launch:
         # l^3 / 3 + l^3 / 3 flops each
@@ -408,7 +409,8 @@ def roofline_of(dom_tag, dom_ms, dom_cnt, info, m, p, n, k, l, esz, flag, worklo
     else:
         roof = {"bound": "alu", "achieved": None, "peak": None, "unit": None, "traffic": None}
     roof["frac"] = roof["achieved"] / roof["peak"] if roof.get("achieved") is not None else None
-    roof["kernel"] = {"small": "k_small", "nn": "k_gw", "tn": "k_gtq", "chol": "k_chol",
+    roof["kernel"] = {"small": "k_small", "nn": "k_nn" if flag == "mixed" else "k_gw",
+                      "tn": "k_tn" if flag == "mixed" else "k_gtq", "chol": "k_chol",
                       "bjacobi": "k_bjinit + k_bjround"}.get(dom_tag, dom_tag)
     roof["avg_launch_ms"] = avg_ms
     roof["launches_per_step"] = dom_cnt
