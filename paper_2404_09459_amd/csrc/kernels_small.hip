@@ -844,16 +844,18 @@ __device__ inline int bj_sweeps(const BJState* S, double tol, bool& more) {
 }
 
 // Per pair (one workgroup):
-//  1. diagonally pivoted Cholesky of M and one-sided Jacobi on its graded
-//     factor F (pairs with a dominant column only): the t dominant
-//     eigenvectors Z of M, i.e. left singular vectors of B, and sigma_B;
+//  1. a Cholesky factor F of M (diagonally pivoted up to order PIVOT_MAX)
+//     and one-sided Jacobi on it: the t dominant eigenvectors Z of M, i.e.
+//     left singular vectors of B, and sigma_B;
 //  2. L = Z (N x t), the joint basis [L1; L2] of Algorithm 2's CS step;
 //  3. Y = eigenvectors of H = L1^T L1 (+ a tiny shift, which leaves them
-//     unchanged), again by pivoted Cholesky + Jacobi;
+//     unchanged), again by a Cholesky factor + Jacobi;
 //  4. L Y: alpha_i = ||L1 y_i||, beta_i = ||L2 y_i|| (beta from L2 as the
 //     column norms, never sqrt(1 - alpha^2)), X1, X2, (L Y)^T, quantities.
 // Stages (SmallJob::stage) split the step around the block Jacobi launches
-// on the factors of M and H.
+// on the factors of M and H and around the multi-workgroup products H and
+// L Y of the larger pairs: 1 | block Jacobi on M | 2 | H Gram | 5 | block
+// Jacobi on H | 3 | L Y | 4.
 // largest order factored by the diagonally pivoted Cholesky in every case
 constexpr int PIVOT_MAX = 128;
 
