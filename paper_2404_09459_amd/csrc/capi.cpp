@@ -973,8 +973,10 @@ int build(rgsvd_plan_s* P, void* ws) {
       if (!sj.empty()) B.add(K_SMALL, sj, tl).tag = T_SMALL;
       return !sj.empty();
     };
-    // sweeps of the block Jacobi: a sweep-start launch, then one launch per
-    // round (jobs with fewer rounds skip the extra ones)
+    // sweeps of the block Jacobi: one launch per round (jobs with fewer
+    // rounds skip the extra ones); the first sweep starts with a launch of
+    // its own (the factor's column norms), later sweeps start inside their
+    // first round
     auto add_bj = [&](bool onH) {
       std::vector<BJJob> bj; std::vector<int> tl, one;
       int rmax = 0;
@@ -997,7 +999,7 @@ int build(rgsvd_plan_s* P, void* ws) {
       P->stages.pop_back();
       for (int sw = 0; sw < BJ_SWEEPS; ++sw) {
         si.sweep = sw;
-        P->stages.push_back(si);
+        if (sw == 0) P->stages.push_back(si);
         for (int r = 0; r < rmax; ++r) {
           sr.sweep = sw; sr.round = r;
           P->stages.push_back(sr);

@@ -824,8 +824,8 @@ jacobi_any(double* A, int lda, int nr, int nc, double tol, int maxsweep, int top
 // (thread 0).
 __device__ inline void bj_start(BJState* S, int nc, int nr, int topk) {
   S->nc = nc; S->nr = nr; S->topk = topk; S->done = 0;
-  S->sweeps = 0; S->rot[0] = 1; S->rot[1] = 1; S->thr = -1.0;
-  S->rel[0] = 0; S->rel[1] = 0;
+  S->sweeps = 0; S->thr = -1.0;
+  for (int i = 0; i < 3; ++i) { S->rot[i] = 1; S->rel[i] = 0; }
 }
 
 // Whether the sweep of parity `par` ended the Jacobi: no turns, or only
@@ -839,7 +839,7 @@ __device__ inline bool bj_converged(const BJState* S, int par, double tol) {
 // sweeps must continue (the last launched sweep still rotated).
 __device__ inline int bj_sweeps(const BJState* S, double tol, bool& more) {
   const int nsw = S->sweeps;
-  more = !(S->done || nsw < 1 || bj_converged(S, (nsw - 1) & 1, tol));
+  more = !(S->done || nsw < 1 || bj_converged(S, (nsw - 1) % 3, tol));
   return nsw;
 }
 
@@ -1132,9 +1132,11 @@ __global__ __launch_bounds__(1024) void k_small(const SmallJob* __restrict__ job
 // blocks.  Each pair of columns is therefore visited once per sweep, as in
 // the single-workgroup sweeps, with the same rotation and skip rules.
 
-// Sweep start: a sweep without rotations ends the run; otherwise the skip
-// threshold (a quarter of the topk-th largest squared column norm; the
-// norms come from the previous sweep's last round, or from A at sweep 0).
+// Sweep start (launched for the first sweep; later sweeps start inside
+// their first round, bj_sweep_start): a sweep without rotations ends the
+// run; otherwise the skip threshold (a quarter of the topk-th largest squared
+// column norm; the norms come from the previous sweep's last round, or from
+// A at sweep 0).
 __global__ __launch_bounds__(1024) void k_bjinit(const BJJob* __restrict__ jobs, int nj, int sweep) {
   __shared__ double n2[SMALL_MAXN];
   __shared__ double kth;
@@ -1142,7 +1144,7 @@ __global__ __launch_bounds__(1024) void k_bjinit(const BJJob* __restrict__ jobs,
   BJState* S = J.st;
   const int tid = threadIdx.x, wave = tid >> 6, ln = tid & 63;
   if (S->done) return;
-  if (sweep > 0 && bj_converged(S, (sweep - 1) & 1, J.tol)) {
+  if (sweep > 0 && bj_converged(S, (sweep - 1) % 3, J.tol)) {
     if (tid == 0) { S->done = 1; S->sweeps = sweep; }
     return;
   }
@@ -1172,14 +1174,50 @@ __global__ __launch_bounds__(1024) void k_bjinit(const BJJob* __restrict__ jobs,
     __syncthreads();
     thr = 0.25 * kth;
   }
-  if (tid == 0) { S->rot[sweep & 1] = 0; S->rel[sweep & 1] = 0; S->sweeps = sweep + 1; S->thr = thr; }
+  if (tid == 0) {
+    S->rot[sweep % 3] = 0; S->rel[sweep % 3] = 0;
+    S->rot[(sweep + 1) % 3] = 0; S->rel[(sweep + 1) % 3] = 0;
+    S->sweeps = sweep + 1; S->thr = thr;
+  }
+}
+
+// The start of sweep s > 0 inside its first round (every workgroup of the
+// round, so no launch of its own): whether sweep s - 1 ended the Jacobi, and
+// otherwise the skip threshold from the squared norms its last round left.
+// Workgroup 0 of the job records the outcome and clears the slot of sweep
+// s + 1.  Returns false when the Jacobi has ended.
+__device__ bool bj_sweep_start(const BJJob& J, BJState* S, int w, int sweep, double& thr, double* n2s,
+                               double* kth_s) {
+  const int tid = threadIdx.x;
+  if (bj_converged(S, (sweep - 1) % 3, J.tol)) {
+    if (w == 0 && tid == 0) { S->done = 1; S->sweeps = sweep; }
+    return false;
+  }
+  const int nc = S->nc, topk = S->topk;
+  thr = -1.0;
+  if (topk > 0 && topk < nc) {
+    for (int c = tid; c < nc; c += BJ_THREADS) n2s[c] = J.nrm2[c];
+    __syncthreads();
+    for (int i = tid; i < nc; i += BJ_THREADS) {
+      const double v = n2s[i];
+      int r = 0;
+      for (int j2 = 0; j2 < nc; ++j2) { const double x = n2s[j2]; r += (x > v) || (x == v && j2 < i); }
+      if (r == topk - 1) *kth_s = v;
+    }
+    __syncthreads();
+    thr = 0.25 * *kth_s;
+  }
+  if (w == 0 && tid == 0) {
+    S->thr = thr; S->sweeps = sweep + 1;
+    S->rot[(sweep + 1) % 3] = 0; S->rel[(sweep + 1) % 3] = 0;
+  }
+  return true;
 }
 
 template <int B, int G, int EM>
 __device__ __attribute__((always_inline)) inline void
-bj_visit(const BJJob& J, BJState* S, int w, int sweep, int round, double* lds, double* n0) {
+bj_visit(const BJJob& J, BJState* S, int w, int sweep, int round, double* lds, double* n0, double thr) {
   const int nr = J.nr, nc = S->nc, tid = threadIdx.x;
-  const double thr = S->thr;
   int bu, bv;
   tournament(w, round, J.nblk - 1, bu, bv);
   const int c0u = bu * B, c0v = bv * B;
@@ -1247,10 +1285,10 @@ bj_visit(const BJJob& J, BJState* S, int w, int sweep, int round, double* lds, d
   }
   for (int o = 32; o > 0; o >>= 1) rel2 = fmax(rel2, __shfl_xor(rel2, o, 64));
   if ((tid & 63) == 0 && rel2 > 0.0)
-    atomicMax((unsigned long long*)&S->rel[sweep & 1], (unsigned long long)__double_as_longlong(rel2));
+    atomicMax((unsigned long long*)&S->rel[sweep % 3], (unsigned long long)__double_as_longlong(rel2));
   // rotations seen: one flag per wave, before the write-back (no barrier
   // after the last step's)
-  if (__any(any) && (tid & 63) == 0) atomicOr(&S->rot[sweep & 1], 1);
+  if (__any(any) && (tid & 63) == 0) atomicOr(&S->rot[sweep % 3], 1);
   // write back; in the last round of the sweep every column passes through
   // exactly one workgroup, which leaves its squared norm for the next sweep
   double n2 = 0.0;
@@ -1280,8 +1318,16 @@ __global__ __launch_bounds__(BJ_THREADS) void k_bjround(const BJJob* __restrict_
   BJState* S = J.st;
   if (S->done || round >= J.nblk - 1) return;
   const int w = blockIdx.x - pre[jb];
-  if (J.nr <= 256) bj_visit<BJ_B, BJ_THREADS / BJ_B, 8>(J, S, w, sweep, round, lds, n0);
-  else bj_visit<BJ_B / 2, 2 * BJ_THREADS / BJ_B, 8>(J, S, w, sweep, round, lds, n0);
+  double thr;
+  if (sweep > 0 && round == 0) {
+    __shared__ double n2s[SMALL_MAXN];
+    __shared__ double kth_s;
+    if (!bj_sweep_start(J, S, w, sweep, thr, n2s, &kth_s)) return;
+  } else {
+    thr = S->thr;
+  }
+  if (J.nr <= 256) bj_visit<BJ_B, BJ_THREADS / BJ_B, 8>(J, S, w, sweep, round, lds, n0, thr);
+  else bj_visit<BJ_B / 2, 2 * BJ_THREADS / BJ_B, 8>(J, S, w, sweep, round, lds, n0, thr);
 }
 
 // ------------------------------------------------------------- k_rowsign --

@@ -31,11 +31,13 @@ constexpr int BJ_THREADS = 512;
 struct BJState {
   int32_t nc, nr, topk, done;       // columns, rows, dominant count, converged flag
   int32_t sweeps, rank, sw1, sw2;   // sweeps started; rank of M; sweeps on M and on H
-  int32_t rot[2];                   // rotations seen in the sweep of that parity
+  int32_t rot[3], pad;              // rotations seen in sweep s (slot s % 3)
   double thr;                       // skip threshold of the sweep (-1: none)
   double trM;                       // trace of M (M is overwritten by its factorisation)
-  uint64_t rel[2];                  // largest gamma^2 / (alpha beta) turned in the sweep of
-                                    // that parity (bits of a non-negative double)
+  uint64_t rel[3];                  // largest gamma^2 / (alpha beta) turned in sweep s (slot
+                                    // s % 3; bits of a non-negative double).  Three slots: the
+                                    // first round of sweep s reads slot s - 1, clears slot s + 1
+                                    // and the rounds of sweep s raise slot s
 };
 
 // One compressed pair: M = B B^T (N x N, ldm), the Gram of the stacked
