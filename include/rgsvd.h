@@ -83,6 +83,14 @@ extern "C" {
                                   adaptive runs return RGSVD_ENOTGMP from rgsvd_run
                                   when the widths they reach fall short)              */
 
+/* options: how the block Jacobi of the small step is launched.  By default
+ * its first sweeps take one launch per round and its last three sweeps (most
+ * often converged or nearly) one launch each, with a barrier between rounds,
+ * when all workgroups of a sweep fit on the device at once (else per round).
+ * Every choice turns the same pairs in the same order: same results. */
+#define RGSVD_OPT_JACOBI_ROUNDS 0x1 /* every sweep one launch per round                */
+#define RGSVD_OPT_JACOBI_SWEEPS 0x2 /* every sweep one launch, when it fits             */
+
 /* info words (int32, device), filled by a run */
 #define RGSVD_INFO_STATUS 0
 #define RGSVD_INFO_L1 1
@@ -117,7 +125,7 @@ typedef struct {
   int32_t precision;        /* RGSVD_PREC_*                                           */
   int32_t sizing;           /* RGSVD_SIZE_*                                           */
   int32_t mode;             /* RGSVD_TRUNCATED | RGSVD_FULL                            */
-  int32_t reserved0;
+  int32_t options;          /* RGSVD_OPT_* bits (0: defaults)                           */
   uint64_t seed;            /* Omega seed                                              */
   double tol;               /* adaptive: eps of Algorithm 1 (absolute Frobenius);
                                learned: the judge's eps (0: no judge)                   */

@@ -48,7 +48,8 @@ inline int ct_of(int L) {
 }
 
 enum Kind { K_ZERO, K_COPY, K_GEN, K_AB, K_GRAM, K_RED, K_CHOL, K_SMALL, K_SIGN, K_SCALE, K_GW, K_GTQ,
-            K_PACK, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP, K_BJINIT, K_BJROUND, K_GW4, K_ZEROG, K_NN, K_PROF, K_TN };
+            K_PACK, K_SUMSQ, K_SUMFIN, K_FEAT, K_MLP, K_BJINIT, K_BJROUND, K_GW4, K_ZEROG, K_NN, K_PROF, K_TN,
+            K_BJSWEEP };
 
 enum Tag { T_ZERO, T_COPY, T_GEN, T_NN, T_TN, T_RED, T_GRAM, T_CHOL, T_SX, T_SMALL, T_RECOVER, T_SIGN,
            T_MGRAM, T_BJAC, T_NTAGS };
@@ -62,7 +63,7 @@ struct Stage {
   int ta = 0, tb = 0, td = 0;
   bool sym = false, f64 = false, split = false;
   size_t zoff = 0, zbytes = 0;  // K_ZERO: workspace range
-  int sweep = 0, round = 0;     // K_BJINIT, K_BJROUND
+  int sweep = 0, round = 0;     // K_BJINIT, K_BJROUND, K_BJSWEEP (round: its first whole sweep)
 };
 
 struct CopyJob { const uint32_t* src; uint32_t* dst; int64_t nwords; };
@@ -979,7 +980,7 @@ int build(rgsvd_plan_s* P, void* ws) {
     // first round
     auto add_bj = [&](bool onH) {
       std::vector<BJJob> bj; std::vector<int> tl, one;
-      int rmax = 0;
+      int rmax = 0, wgs = 0;
       for (auto& pr : P->pairs) {
         if (!(onH ? bjh(pr) : bjm(pr))) continue;
         const int N = pr.l1 + pr.l2, t = pr.t;
@@ -990,16 +991,31 @@ int build(rgsvd_plan_s* P, void* ws) {
         bj.push_back(BJJob{F, (BJState*)WS(ws, pr.bjs), (double*)WS(ws, pr.bjn), 1e-15, nr, nblk});
         tl.push_back(nblk / 2); one.push_back(1);
         rmax = std::max(rmax, nblk - 1);
+        wgs += nblk / 2;
       }
       Stage si = B.add(K_BJINIT, bj, one);
       si.tag = T_BJAC;
       P->stages.pop_back();
+      // sweeps from sw0 on take one launch each when the sweep's workgroups
+      // can all be resident at once (one per CU: the sweep kernel's
+      // registers leave room for one workgroup of 8 waves); earlier ones, or
+      // all when it does not fit, one launch per round.  An active round
+      // costs more behind the barrier than behind a launch, a converged
+      // sweep far less in one launch than in nblk - 1.
+      int sw0 = BJ_SWEEP_WHOLE;
+      if (P->d.options & RGSVD_OPT_JACOBI_SWEEPS) sw0 = 0;
+      if ((P->d.options & RGSVD_OPT_JACOBI_ROUNDS) || wgs > P->wave_slots / 4) sw0 = BJ_SWEEPS;
       Stage sr = B.add(K_BJROUND, bj, tl);
       sr.tag = T_BJAC;
       P->stages.pop_back();
+      P->stages.push_back(si);
       for (int sw = 0; sw < BJ_SWEEPS; ++sw) {
-        si.sweep = sw;
-        if (sw == 0) P->stages.push_back(si);
+        if (sw >= sw0) {
+          Stage ss = sr;
+          ss.kind = K_BJSWEEP; ss.sweep = sw; ss.round = sw0;
+          P->stages.push_back(ss);
+          continue;
+        }
         for (int r = 0; r < rmax; ++r) {
           sr.sweep = sw; sr.round = r;
           P->stages.push_back(sr);
@@ -1301,6 +1317,7 @@ int enqueue_list(rgsvd_plan_s* P, void* ws, hipStream_t st, const std::vector<St
       case K_SMALL: launch_small((const SmallJob*)j, s.nj, st); break;
       case K_BJINIT: launch_bjinit((const BJJob*)j, s.nj, s.sweep, st); break;
       case K_BJROUND: launch_bjround((const BJJob*)j, pre, s.nj, s.tiles, s.sweep, s.round, st); break;
+      case K_BJSWEEP: launch_bjsweep((const BJJob*)j, pre, s.nj, s.tiles, s.sweep, s.round, BJ_SPIN, st); break;
       case K_SIGN: launch_sign((const SignJob*)j, pre, s.nj, s.tiles, st); break;
       case K_SCALE: launch_scale((const SignJob*)j, pre, s.nj, s.tiles, st); break;
       case K_GW: launch_gw(s.prec, s.gdt, s.rt, s.ct, (const NnJob*)j, pre, s.nj, s.tiles, st); break;
@@ -1412,6 +1429,9 @@ int check_desc(const rgsvd_desc* d) {
   if (d->in_dtype != RGSVD_F64 && d->in_dtype != RGSVD_F32) return RGSVD_EINVAL;
   if (d->precision < RGSVD_PREC_FP64 || d->precision > RGSVD_PREC_MIXED) return RGSVD_EINVAL;
   if (d->mode != RGSVD_TRUNCATED && d->mode != RGSVD_FULL) return RGSVD_EINVAL;
+  if ((d->options & ~(RGSVD_OPT_JACOBI_ROUNDS | RGSVD_OPT_JACOBI_SWEEPS)) ||
+      (d->options & RGSVD_OPT_JACOBI_ROUNDS && d->options & RGSVD_OPT_JACOBI_SWEEPS))
+    return RGSVD_EINVAL;
   if (d->m > (1 << 30) || d->p > (1 << 30) || d->n > (1 << 30)) return RGSVD_EINVAL;
   const int64_t l = d->k + d->oversample;
   // Theorem "projector": k + p <= min(m, n) (and <= min(p, n) for G2)
@@ -1965,7 +1985,7 @@ int rgsvd_batch_plan(const rgsvd_desc* shapes, int32_t npairs, rgsvd_plan_t* pla
     int rc = check_desc(&shapes[i]);
     if (rc) return rc;
     if (shapes[i].in_dtype != shapes[0].in_dtype || shapes[i].precision != shapes[0].precision ||
-        shapes[i].mode != shapes[0].mode)
+        shapes[i].mode != shapes[0].mode || shapes[i].options != shapes[0].options)
       return RGSVD_EINVAL;
     // every grouped launch serves all pairs at one step of the subspace
     // iteration, so the pairs of a batch share the power count

@@ -826,6 +826,7 @@ __device__ inline void bj_start(BJState* S, int nc, int nr, int topk) {
   S->nc = nc; S->nr = nr; S->topk = topk; S->done = 0;
   S->sweeps = 0; S->thr = -1.0;
   for (int i = 0; i < 3; ++i) { S->rot[i] = 1; S->rel[i] = 0; }
+  S->bar = 0; S->fail = 0;
 }
 
 // Whether the sweep of parity `par` ended the Jacobi: no turns, or only
@@ -838,6 +839,7 @@ __device__ inline bool bj_converged(const BJState* S, int par, double tol) {
 // Sweeps already run by the block Jacobi, and whether single-workgroup
 // sweeps must continue (the last launched sweep still rotated).
 __device__ inline int bj_sweeps(const BJState* S, double tol, bool& more) {
+  if (S->fail) { more = false; return BJ_TIMEOUT_SWEEPS; }
   const int nsw = S->sweeps;
   more = !(S->done || nsw < 1 || bj_converged(S, (nsw - 1) % 3, tol));
   return nsw;
@@ -1330,6 +1332,73 @@ __global__ __launch_bounds__(BJ_THREADS) void k_bjround(const BJJob* __restrict_
   else bj_visit<BJ_B / 2, 2 * BJ_THREADS / BJ_B, 8>(J, S, w, sweep, round, lds, n0, thr);
 }
 
+// Barrier of the workgroups of one job between two rounds of a one-launch
+// sweep: every workgroup adds one arrival to the job's counter and waits
+// until `target` arrivals are in (the counter only grows during a Jacobi, so
+// no reset between rounds).  The round's columns are released to the device
+// before the arrival and acquired after the wait.  The wait is bounded: after
+// `spin` polls, or when another workgroup of the job has given up, the job is
+// marked failed and ended, and the caller returns.
+__device__ bool bj_barrier(BJState* S, uint32_t target, int spin, int* ok_s) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(&S->bar, 1u);
+    int ok = 1;
+    for (int n = 0; __hip_atomic_load(&S->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++n) {
+      if (n >= spin || __hip_atomic_load(&S->fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+        ok = 0;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
+    if (!ok) {
+      atomicOr(&S->fail, 1);
+      atomicOr(&S->done, 1);
+    }
+    __threadfence();
+    *ok_s = ok;
+  }
+  __syncthreads();
+  return *ok_s != 0;
+}
+
+// All rounds of one sweep for every job in one launch (nblk / 2 workgroups
+// per job, all resident at once: the host takes this kernel only when the
+// launch fits the device).  The visits, their order and the sweep start are
+// those of the per-round launches; the launch boundary between rounds is
+// replaced by the job's barrier.  Sweeps sw0, sw0 + 1, ... are launched this
+// way (earlier ones one launch per round, which do not count arrivals).
+__global__ __launch_bounds__(BJ_THREADS) void k_bjsweep(const BJJob* __restrict__ jobs,
+                                                        const int* __restrict__ pre, int nj, int sweep,
+                                                        int sw0, int spin) {
+  extern __shared__ double lds[];
+  __shared__ double n0[2 * BJ_B];
+  __shared__ double n2s[SMALL_MAXN];
+  __shared__ double kth_s;
+  __shared__ int ok_s;
+  const int jb = find_side(pre, nj, blockIdx.x);
+  const BJJob J = jobs[jb];
+  BJState* S = J.st;
+  if (S->done) return;
+  const int w = blockIdx.x - pre[jb];
+  double thr;
+  if (sweep > 0) {
+    if (!bj_sweep_start(J, S, w, sweep, thr, n2s, &kth_s)) return;
+  } else {
+    thr = S->thr;
+  }
+  const int nround = J.nblk - 1, nwg = J.nblk / 2;
+  for (int round = 0; round < nround; ++round) {
+    if (round > 0) {
+      const uint32_t target = (uint32_t)(((sweep - sw0) * (nround - 1) + round) * nwg);
+      if (!bj_barrier(S, target, spin, &ok_s)) return;
+    }
+    if (J.nr <= 256) bj_visit<BJ_B, BJ_THREADS / BJ_B, 8>(J, S, w, sweep, round, lds, n0, thr);
+    else bj_visit<BJ_B / 2, 2 * BJ_THREADS / BJ_B, 8>(J, S, w, sweep, round, lds, n0, thr);
+  }
+}
+
 // ------------------------------------------------------------- k_rowsign --
 // s_i = sign of the largest-magnitude entry of row i of R (first on ties)
 __global__ __launch_bounds__(256) void k_rowsign(const SignJob* __restrict__ jobs,
@@ -1402,6 +1471,17 @@ void launch_bjround(const BJJob* j, const int* pre, int nj, int tiles, int sweep
     attr_set = true;
   }
   hipLaunchKernelGGL(k_bjround, dim3(tiles), dim3(BJ_THREADS), bytes, st, j, pre, nj, sweep, round);
+}
+
+void launch_bjsweep(const BJJob* j, const int* pre, int nj, int tiles, int sweep, int sw0, int spin,
+                    hipStream_t st) {
+  static bool attr_set = false;
+  const size_t bytes = (size_t)2 * BJ_B * 256 * sizeof(double);
+  if (!attr_set) {
+    hipFuncSetAttribute((const void*)k_bjsweep, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_bjsweep, dim3(tiles), dim3(BJ_THREADS), bytes, st, j, pre, nj, sweep, sw0, spin);
 }
 
 void launch_sign(const SignJob* j, const int* pre, int nj, int tiles, hipStream_t st) {

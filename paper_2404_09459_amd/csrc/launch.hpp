@@ -18,6 +18,8 @@ void launch_chol(const CholJob* j, int nj, hipStream_t st);
 void launch_small(const SmallJob* j, int nj, hipStream_t st);
 void launch_bjinit(const BJJob* j, int nj, int sweep, hipStream_t st);
 void launch_bjround(const BJJob* j, const int* pre, int nj, int tiles, int sweep, int round, hipStream_t st);
+void launch_bjsweep(const BJJob* j, const int* pre, int nj, int tiles, int sweep, int sw0, int spin,
+                    hipStream_t st);
 void launch_sign(const SignJob* j, const int* pre, int nj, int tiles, hipStream_t st);
 void launch_scale(const SignJob* j, const int* pre, int nj, int tiles, hipStream_t st);
 

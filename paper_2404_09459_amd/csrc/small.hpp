@@ -19,11 +19,14 @@ constexpr int FLAG_NONFINITE = 0x80;
 
 // Block one-sided Jacobi for factors too large for k_small's LDS (order^2 >
 // SMALL_LDS_BYTES / 8): columns in blocks of BJ_B (order <= 256) or BJ_B / 2
-// (order <= 512); one workgroup per block pair and one launch per round; at
+// (order <= 512); one workgroup per block pair and one launch per round
+// (sweeps from BJ_SWEEP_WHOLE on: one launch per sweep with a barrier between
+// rounds, when every workgroup of the launch fits on the device at once); at
 // most BJ_SWEEPS sweeps are launched, the single-workgroup sweeps finish a
 // factor that has not converged by then.
 constexpr int BJ_B = 16;
 constexpr int BJ_SWEEPS = 10;
+constexpr int BJ_SWEEP_WHOLE = 7;   // default: sweeps from this one on take one launch each
 constexpr int BJ_THREADS = 512;
 
 // State of a block Jacobi run, shared by the staged small kernel and the
@@ -38,7 +41,17 @@ struct BJState {
                                     // s % 3; bits of a non-negative double).  Three slots: the
                                     // first round of sweep s reads slot s - 1, clears slot s + 1
                                     // and the rounds of sweep s raise slot s
+  uint32_t bar;                     // one-launch sweeps: workgroup arrivals at the barriers
+                                    // between rounds since the start of the Jacobi
+  int32_t fail;                     // a barrier wait ran out (the Jacobi ended unconverged)
 };
+
+// Sweeps reported for a block Jacobi whose barrier wait ran out: above any
+// sweep limit, so the pair carries the sweep-limit flag.
+constexpr int BJ_TIMEOUT_SWEEPS = 1 << 20;
+// Polls of the barrier counter before a one-launch sweep gives up (each poll
+// is a device-scope load and a short sleep, about a microsecond or more).
+constexpr int BJ_SPIN = 1 << 20;
 
 // One compressed pair: M = B B^T (N x N, ldm), the Gram of the stacked
 // compressed pair B = [Q1^T G1; Q2^T G2], N = l1 + l2.

@@ -14,6 +14,8 @@ OK, EINVAL, ENOTGMP, EHIP, ENOMEM, EWORKSPACE, ENOMODEL, EUNSUPPORTED, ETOOBIG =
 STATIC_SCRATCH_BYTES = 64 << 20
 F64, F32 = 0, 1
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
+OPT_JACOBI_ROUNDS = 0x1   # block Jacobi: every sweep one launch per round
+OPT_JACOBI_SWEEPS = 0x2   # block Jacobi: every sweep one launch (a barrier between rounds) when it fits
 SIZING = {"fixed": 0, "adaptive": 1, "learned": 2}
 MODE = {"truncated": 0, "full": 1}
 INFO_WORDS = 8
@@ -36,7 +38,7 @@ class Desc(ctypes.Structure):
                 ("k", ctypes.c_int64), ("oversample", ctypes.c_int64),
                 ("power_iters", ctypes.c_int32), ("in_dtype", ctypes.c_int32),
                 ("precision", ctypes.c_int32), ("sizing", ctypes.c_int32),
-                ("mode", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("mode", ctypes.c_int32), ("options", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("tol", ctypes.c_double),
                 ("block", ctypes.c_int64), ("lmax", ctypes.c_int64)]
 
@@ -149,9 +151,9 @@ def _stream(device):
 
 
 def make_desc(m, p, n, k, oversample, q, seed, in_dtype, precision="fp64", sizing="fixed",
-              mode="truncated", tol=0.0, block=0, lmax=0):
+              mode="truncated", tol=0.0, block=0, lmax=0, options=0):
     return Desc(m=m, p=p, n=n, k=k, oversample=oversample, power_iters=q, in_dtype=in_dtype,
-                precision=PREC[precision], sizing=SIZING[sizing], mode=MODE[mode], reserved0=0,
+                precision=PREC[precision], sizing=SIZING[sizing], mode=MODE[mode], options=options,
                 seed=seed, tol=tol, block=block, lmax=lmax)
 
 

@@ -56,6 +56,10 @@ def test_plan_validation_on_host():
     assert _plan(in_dtype=7)[0] == R.EINVAL
     assert _plan(mode="full")[0] == R.ENOTGMP                  # l1 + l2 < n
     assert _plan(n=50, k=20, oversample=10, mode="full")[0] == 0
+    assert _plan(options=R.OPT_JACOBI_ROUNDS)[0] == 0
+    assert _plan(options=R.OPT_JACOBI_SWEEPS)[0] == 0
+    assert _plan(options=R.OPT_JACOBI_ROUNDS | R.OPT_JACOBI_SWEEPS)[0] == R.EINVAL
+    assert _plan(options=0x4)[0] == R.EINVAL                   # unknown option bit
     assert R.lib().rgsvd_strerror(R.ENOTGMP).decode().startswith("full mode")
 
 

@@ -260,3 +260,43 @@ def test_nonfinite_input_flagged_staged(dev):
     after = _run(dev, G1, G2, k, 10, 1, 3)
     for key in ("alpha", "beta", "theta", "U", "V", "R"):
         assert np.array_equal(before[key], after[key]), key
+
+
+@pytest.mark.parametrize("m,p,n,k,o,precision", [
+    (1200, 1000, 400, 120, 10, "fp64"),    # M's factor order 260 (blocks of 8), H's 120: both on the block Jacobi
+    (2000, 1600, 600, 100, 20, "mixed"),   # M's factor order 240 (blocks of 16)
+])
+def test_jacobi_sweep_launches_match_round_launches(dev, m, p, n, k, o, precision):
+    """The block Jacobi's one-launch sweeps (a barrier between rounds; every
+    sweep, or the default's last three) turn the same pairs in the same order
+    as one launch per round: every output bit-identical, on two runs in a row
+    of each plan (the barrier counter starts again with each run)."""
+    from paper_2404_09459_amd import inputs as I
+    from paper_2404_09459_amd import rgsvd as R
+    j = np.arange(k)
+    G1, G2 = I.lowrank_pair(m, p, n, k, 0.97 ** j, 0.96 ** j, 91, noise_entry=1e-6, dtype=np.float64)
+    dt = R.F64 if precision == "fp64" else R.F32
+    npdt = np.float64 if precision == "fp64" else np.float32
+    g1 = torch.from_numpy(np.ascontiguousarray(G1.astype(npdt))).to(dev)
+    g2 = torch.from_numpy(np.ascontiguousarray(G2.astype(npdt))).to(dev)
+    res, counts = {}, {}
+    for name, opt in (("sweep", R.OPT_JACOBI_SWEEPS), ("round", R.OPT_JACOBI_ROUNDS), ("default", 0)):
+        _say(f"block Jacobi launches per {name}: m={m} p={p} n={n} k={k} o={o} {precision}")
+        plan = R.Plan(R.make_desc(m, p, n, k, o, 2, 5, dt, precision, options=opt), dev)
+        runs = []
+        for rep in range(2):
+            R.lib().rgsvd_profile(plan.h, 1 if rep == 1 else 0)
+            out = R.alloc_outputs(plan.t, m, p, n, plan.l1 + plan.l2, dev)
+            R.run(plan, g1, g2, out)
+            torch.cuda.synchronize()
+            runs.append({kk: v.cpu().numpy() for kk, v in out.items()})
+        counts[name] = sum(1 for tg, _ in R.profile_read(plan) if tg == "bjacobi")
+        for key in runs[0]:
+            assert np.array_equal(runs[0][key], runs[1][key], equal_nan=True), (name, key)
+        res[name] = runs[0]
+        _say(f"   info {runs[0]['info'].tolist()} block Jacobi launches {counts[name]}")
+    assert "jacobi_m" not in _flags(res["sweep"]) and int(res["sweep"]["info"][5]) >= 2
+    assert counts["sweep"] < counts["default"] < counts["round"]
+    for name in ("sweep", "default"):
+        for key in res["round"]:
+            assert np.array_equal(res[name][key], res["round"][key], equal_nan=True), (name, key)
