@@ -41,11 +41,11 @@ FP64_VEC_PEAK_TF = 78.6
 # HBM bytes per launch from FETCH_SIZE and WRITE_SIZE, each scaled by what it
 # reads for a copy kernel of known size (profiles/hbm_counters_*.md), keyed by
 # workload: the mixed sketch pass (k_nn, BF16), the block Jacobi launches
-# (k_bjinit + k_bjround, averaged over the launches of a run) and the small
+# (k_bjinit + k_bjround + k_bjsweep, averaged over the launches of a run) and the small
 # step's k_small launches (averaged).  Kernels changed since their counters
 # were taken have no entry (traffic null).
-TRAFFIC = {"large": {"sketch": 1.659e9, "bjacobi": 1.994e6},
-           "medium": {"sketch": 0.743e9, "bjacobi": 0.56e6, "small": 1.4e6}}
+TRAFFIC = {"large": {"sketch": 1.659e9},
+           "medium": {"sketch": 0.743e9}}
 
 
 def log(*a):
@@ -411,7 +411,7 @@ def roofline_of(dom_tag, dom_ms, dom_cnt, info, m, p, n, k, l, esz, flag, worklo
     roof["frac"] = roof["achieved"] / roof["peak"] if roof.get("achieved") is not None else None
     roof["kernel"] = {"small": "k_small", "nn": "k_nn" if flag == "mixed" else "k_gw",
                       "tn": "k_tn" if flag == "mixed" else "k_gtq", "chol": "k_chol",
-                      "bjacobi": "k_bjinit + k_bjround"}.get(dom_tag, dom_tag)
+                      "bjacobi": "k_bjinit + k_bjround + k_bjsweep"}.get(dom_tag, dom_tag)
     roof["avg_launch_ms"] = avg_ms
     roof["launches_per_step"] = dom_cnt
     return roof
