@@ -1332,17 +1332,28 @@ __global__ __launch_bounds__(BJ_THREADS) void k_bjround(const BJJob* __restrict_
   else bj_visit<BJ_B / 2, 2 * BJ_THREADS / BJ_B, 8>(J, S, w, sweep, round, lds, n0, thr);
 }
 
+// Device-wide visibility of a round's columns.  The XCDs' L2 caches are not
+// coherent with each other for ordinary device memory: the writer's L2 must
+// write its dirty lines back, and the reader's L1 and L2 must drop theirs,
+// each finished (vmcnt) before the next step.  Written out here because the
+// compiler's fence may drop the wait after the write-back when the issuing
+// wave has no store outstanding of its own.
+__device__ __forceinline__ void l2_writeback() { asm volatile("buffer_wbl2 sc1\n\ts_waitcnt vmcnt(0)" ::: "memory"); }
+__device__ __forceinline__ void l2_invalidate() { asm volatile("buffer_inv sc1\n\ts_waitcnt vmcnt(0)" ::: "memory"); }
+
 // Barrier of the workgroups of one job between two rounds of a one-launch
 // sweep: every workgroup adds one arrival to the job's counter and waits
 // until `target` arrivals are in (the counter only grows during a Jacobi, so
-// no reset between rounds).  The round's columns are released to the device
-// before the arrival and acquired after the wait.  The wait is bounded: after
-// `spin` polls, or when another workgroup of the job has given up, the job is
+// no reset between rounds).  Every wave's stores of the round reach L2 before
+// the workgroup barrier; thread 0 then writes L2 back before the arrival and
+// invalidates the caches after the wait.  The wait is bounded: after `spin`
+// polls, or when another workgroup of the job has given up, the job is
 // marked failed and ended, and the caller returns.
 __device__ bool bj_barrier(BJState* S, uint32_t target, int spin, int* ok_s) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
-    __threadfence();
+    l2_writeback();
     atomicAdd(&S->bar, 1u);
     int ok = 1;
     for (int n = 0; __hip_atomic_load(&S->bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++n) {
@@ -1356,7 +1367,7 @@ __device__ bool bj_barrier(BJState* S, uint32_t target, int spin, int* ok_s) {
       atomicOr(&S->fail, 1);
       atomicOr(&S->done, 1);
     }
-    __threadfence();
+    l2_invalidate();
     *ok_s = ok;
   }
   __syncthreads();
