@@ -90,6 +90,10 @@ extern "C" {
  * Every choice turns the same pairs in the same order: same results. */
 #define RGSVD_OPT_JACOBI_ROUNDS 0x1 /* every sweep one launch per round                */
 #define RGSVD_OPT_JACOBI_SWEEPS 0x2 /* every sweep one launch, when it fits             */
+#define RGSVD_OPT_JACOBI_NOWAIT 0x4 /* for tests of the failure path: the barrier of a
+                                       one-launch sweep gives up at its first poll; the
+                                       Jacobi ends there and the pair carries the
+                                       sweep-limit flag (RGSVD_FLAG_JACOBI_M / _L1)    */
 
 /* info words (int32, device), filled by a run */
 #define RGSVD_INFO_STATUS 0

@@ -64,6 +64,7 @@ struct Stage {
   bool sym = false, f64 = false, split = false;
   size_t zoff = 0, zbytes = 0;  // K_ZERO: workspace range
   int sweep = 0, round = 0;     // K_BJINIT, K_BJROUND, K_BJSWEEP (round: its first whole sweep)
+  int spin = 0;                 // K_BJSWEEP: polls of its barrier before it gives up
 };
 
 struct CopyJob { const uint32_t* src; uint32_t* dst; int64_t nwords; };
@@ -1013,6 +1014,7 @@ int build(rgsvd_plan_s* P, void* ws) {
         if (sw >= sw0) {
           Stage ss = sr;
           ss.kind = K_BJSWEEP; ss.sweep = sw; ss.round = sw0;
+          ss.spin = (P->d.options & RGSVD_OPT_JACOBI_NOWAIT) ? 0 : BJ_SPIN;
           P->stages.push_back(ss);
           continue;
         }
@@ -1317,7 +1319,7 @@ int enqueue_list(rgsvd_plan_s* P, void* ws, hipStream_t st, const std::vector<St
       case K_SMALL: launch_small((const SmallJob*)j, s.nj, st); break;
       case K_BJINIT: launch_bjinit((const BJJob*)j, s.nj, s.sweep, st); break;
       case K_BJROUND: launch_bjround((const BJJob*)j, pre, s.nj, s.tiles, s.sweep, s.round, st); break;
-      case K_BJSWEEP: launch_bjsweep((const BJJob*)j, pre, s.nj, s.tiles, s.sweep, s.round, BJ_SPIN, st); break;
+      case K_BJSWEEP: launch_bjsweep((const BJJob*)j, pre, s.nj, s.tiles, s.sweep, s.round, s.spin, st); break;
       case K_SIGN: launch_sign((const SignJob*)j, pre, s.nj, s.tiles, st); break;
       case K_SCALE: launch_scale((const SignJob*)j, pre, s.nj, s.tiles, st); break;
       case K_GW: launch_gw(s.prec, s.gdt, s.rt, s.ct, (const NnJob*)j, pre, s.nj, s.tiles, st); break;
@@ -1429,7 +1431,7 @@ int check_desc(const rgsvd_desc* d) {
   if (d->in_dtype != RGSVD_F64 && d->in_dtype != RGSVD_F32) return RGSVD_EINVAL;
   if (d->precision < RGSVD_PREC_FP64 || d->precision > RGSVD_PREC_MIXED) return RGSVD_EINVAL;
   if (d->mode != RGSVD_TRUNCATED && d->mode != RGSVD_FULL) return RGSVD_EINVAL;
-  if ((d->options & ~(RGSVD_OPT_JACOBI_ROUNDS | RGSVD_OPT_JACOBI_SWEEPS)) ||
+  if ((d->options & ~(RGSVD_OPT_JACOBI_ROUNDS | RGSVD_OPT_JACOBI_SWEEPS | RGSVD_OPT_JACOBI_NOWAIT)) ||
       (d->options & RGSVD_OPT_JACOBI_ROUNDS && d->options & RGSVD_OPT_JACOBI_SWEEPS))
     return RGSVD_EINVAL;
   if (d->m > (1 << 30) || d->p > (1 << 30) || d->n > (1 << 30)) return RGSVD_EINVAL;

@@ -16,6 +16,7 @@ F64, F32 = 0, 1
 PREC = {"fp64": 0, "fp32": 1, "mixed": 2}
 OPT_JACOBI_ROUNDS = 0x1   # block Jacobi: every sweep one launch per round
 OPT_JACOBI_SWEEPS = 0x2   # block Jacobi: every sweep one launch (a barrier between rounds) when it fits
+OPT_JACOBI_NOWAIT = 0x4   # tests: the one-launch sweep barrier gives up at once (sweep-limit flag)
 SIZING = {"fixed": 0, "adaptive": 1, "learned": 2}
 MODE = {"truncated": 0, "full": 1}
 INFO_WORDS = 8

@@ -59,7 +59,8 @@ def test_plan_validation_on_host():
     assert _plan(options=R.OPT_JACOBI_ROUNDS)[0] == 0
     assert _plan(options=R.OPT_JACOBI_SWEEPS)[0] == 0
     assert _plan(options=R.OPT_JACOBI_ROUNDS | R.OPT_JACOBI_SWEEPS)[0] == R.EINVAL
-    assert _plan(options=0x4)[0] == R.EINVAL                   # unknown option bit
+    assert _plan(options=R.OPT_JACOBI_SWEEPS | R.OPT_JACOBI_NOWAIT)[0] == 0
+    assert _plan(options=0x8)[0] == R.EINVAL                   # unknown option bit
     assert R.lib().rgsvd_strerror(R.ENOTGMP).decode().startswith("full mode")
 
 

@@ -300,3 +300,30 @@ def test_jacobi_sweep_launches_match_round_launches(dev, m, p, n, k, o, precisio
     for name in ("sweep", "default"):
         for key in res["round"]:
             assert np.array_equal(res[name][key], res["round"][key], equal_nan=True), (name, key)
+
+
+def test_jacobi_sweep_barrier_gives_up_and_flags(dev):
+    """The failure path of the one-launch sweeps, forced from the host: with
+    the barrier told to give up at its first poll, every workgroup leaves the
+    launch at once (no wait left behind), the Jacobi of both factors ends
+    there, and the pair carries the sweep-limit flags with finite outputs."""
+    from paper_2404_09459_amd import inputs as I
+    from paper_2404_09459_amd import rgsvd as R
+    m, p, n, k, o = 1200, 1000, 400, 120, 10
+    j = np.arange(k)
+    G1, G2 = I.lowrank_pair(m, p, n, k, 0.97 ** j, 0.96 ** j, 91, noise_entry=1e-6, dtype=np.float64)
+    g1 = torch.from_numpy(np.ascontiguousarray(G1)).to(dev)
+    g2 = torch.from_numpy(np.ascontiguousarray(G2)).to(dev)
+    _say(f"barrier gives up at once: m={m} p={p} n={n} k={k} o={o} fp64, every sweep one launch")
+    plan = R.Plan(R.make_desc(m, p, n, k, o, 2, 5, R.F64, "fp64",
+                              options=R.OPT_JACOBI_SWEEPS | R.OPT_JACOBI_NOWAIT), dev)
+    for rep in range(2):
+        out = R.alloc_outputs(plan.t, m, p, n, plan.l1 + plan.l2, dev)
+        R.run(plan, g1, g2, out)
+        torch.cuda.synchronize()
+        got = {kk: v.cpu().numpy() for kk, v in out.items()}
+        _say(f"   run {rep}: flags {_flags(got)} info {got['info'].tolist()}")
+        assert "jacobi_m" in _flags(got) and "jacobi_l1" in _flags(got)
+        assert int(got["info"][5]) > 40 and int(got["info"][6]) > 40
+        for key in ("alpha", "beta", "theta"):
+            assert np.all(np.isfinite(got[key])), key
