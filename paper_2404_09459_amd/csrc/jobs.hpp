@@ -34,12 +34,13 @@ struct GramJob {
   int32_t r1, r2, k0, k1, npad, clen;
 };
 
-// Strips of a Gram over R rows: row group rg (16 rows) meets the 64-column
-// blocks from rg / 4 to the last one that starts below R.
+// Strips of a Gram over R rows: row pair rp (row groups 2 rp and 2 rp + 1,
+// 16 rows each) meets the 64-column blocks from rp / 2 to the last one that
+// starts below R.
 __host__ __device__ inline int gram_strips(int R) {
-  const int ngr = (R + 15) / 16, ncb = (R + 63) / 64;
+  const int npr = (R + 31) / 32, ncb = (R + 63) / 64;
   int s = 0;
-  for (int rg = 0; rg < ngr; ++rg) s += ncb - rg / 4;
+  for (int rp = 0; rp < npr; ++rp) s += ncb - rp / 2;
   return s;
 }
 

@@ -194,17 +194,20 @@ __global__ __launch_bounds__(256) void k_ab(const AbJob* __restrict__ jobs,
 
 // --------------------------------------------------------------- k_gram --
 // Partial Gram X[:, k0:k1] X[:, k0:k1]^T in fp64 MFMA over the R = r1 + r2
-// rows of X (X1's rows, then X2's).  One single-wave workgroup per strip: a
-// group of 16 rows against the NQ (1..4) groups of 16 columns of one 64-column
-// block that lie on or above the diagonal and start below R.  Only those
-// 16 x 16 groups are written; the reduction mirrors them into the lower
-// triangle and zeroes rows and columns at and past R.
-// No LDS: lane (g, li) reads 4 consecutive k of its A row and of its NQ B
-// rows straight from L2 (16 or 32 bytes per row), NB steps of 16 k ahead.
+// rows of X (X1's rows, then X2's).  One single-wave workgroup per strip: two
+// groups of 16 rows against the NQ (1..4) groups of 16 columns of one
+// 64-column block that start at or after the first row group's diagonal
+// group and below R (each B fragment serves both row groups).  The groups on
+// or above the diagonal are the Gram's; the one group of the second row
+// group that falls below it is written to the lower triangle, which the
+// reduction does not read (it mirrors the upper groups and zeroes rows and
+// columns at and past R).
+// No LDS: lane (g, li) reads 4 consecutive k of its two A rows and of its NQ
+// B rows straight from L2 (16 or 32 bytes per row), NB steps of 16 k ahead.
 // The 4-wide loads need k0, clen, ld1 and ld2 to be multiples of 4 (the
 // plans pad leading dimensions to 64 and chunk lengths to 32).
 template <typename TX, int NB, int NQ>
-__device__ __forceinline__ void gram_strip(const GramJob& J, int chunk, int rg, int cb, int q0) {
+__device__ __forceinline__ void gram_strip(const GramJob& J, int chunk, int rp, int cb, int q0) {
   const int ln = threadIdx.x & 63, g = ln >> 4, li = ln & 15;
   const int kb = J.k0 + chunk * J.clen;
   const int ke = min(J.k1, kb + J.clen);
@@ -216,9 +219,14 @@ __device__ __forceinline__ void gram_strip(const GramJob& J, int chunk, int rg, 
     return nullptr;
   };
   // rows past R read row 0 of X1 scaled by zero (loads stay unconditional)
-  const TX* pa = rowptr(rg * 16 + li);
-  const double wa = pa ? 1.0 : 0.0;
-  if (!pa) pa = X1;
+  const TX* pa[2];
+  double wa[2];
+#pragma unroll
+  for (int r = 0; r < 2; ++r) {
+    pa[r] = rowptr((2 * rp + r) * 16 + li);
+    wa[r] = pa[r] ? 1.0 : 0.0;
+    if (!pa[r]) pa[r] = X1;
+  }
   const TX* pb[NQ];
   double wb[NQ];
 #pragma unroll
@@ -227,10 +235,12 @@ __device__ __forceinline__ void gram_strip(const GramJob& J, int chunk, int rg, 
     wb[q] = pb[q] ? 1.0 : 0.0;
     if (!pb[q]) pb[q] = X1;
   }
-  d4 acc[NQ];
+  d4 acc[2][NQ];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) acc[q] = d4{0, 0, 0, 0};
-  double ra[NB][4], rbv[NB][NQ][4];
+  for (int r = 0; r < 2; ++r)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[r][q] = d4{0, 0, 0, 0};
+  double ra[NB][2][4], rbv[NB][NQ][4];
   // 4 consecutive k from kx (kx % 4 == 0, kx < ke <= ld), zero at and past ke
   auto ld4 = [&](double* o, const TX* p, int kx, double w) {
     if constexpr (sizeof(TX) == 4) {
@@ -249,13 +259,15 @@ __device__ __forceinline__ void gram_strip(const GramJob& J, int chunk, int rg, 
   auto load = [&](int buf, int st) {
     const int kx = kb + st * 16 + g * 4;
     if (kx < ke) {
-      ld4(ra[buf], pa, kx, wa);
+#pragma unroll
+      for (int r = 0; r < 2; ++r) ld4(ra[buf][r], pa[r], kx, wa[r]);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) ld4(rbv[buf][q], pb[q], kx, wb[q]);
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        ra[buf][e] = 0.0;
+        ra[buf][0][e] = 0.0;
+        ra[buf][1][e] = 0.0;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) rbv[buf][q][e] = 0.0;
       }
@@ -273,24 +285,29 @@ __device__ __forceinline__ void gram_strip(const GramJob& J, int chunk, int rg, 
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[q] = mma64(ra[u][e], rbv[u][q][e], acc[q]);
+        for (int r = 0; r < 2; ++r)
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) acc[r][q] = mma64(ra[u][r][e], rbv[u][q][e], acc[r][q]);
     }
   }
-  // lane holds D[out_row(g, ii)][li] of column group q0 + q
+  // lane holds D[out_row(g, ii)][li] of row group 2 rp + r, column group
+  // q0 + q (rows up to 32 npr - 1 < npad: npad is a multiple of 64)
   double* out = J.out + (int64_t)chunk * J.npad * J.npad;
 #pragma unroll
-  for (int q = 0; q < NQ; ++q)
+  for (int r = 0; r < 2; ++r)
 #pragma unroll
-    for (int ii = 0; ii < 4; ++ii) {
-      const int r = rg * 16 + out_row<P64>(g, ii);
-      const int c = cb * 64 + (q0 + q) * 16 + li;
-      out[(int64_t)r * J.npad + c] = acc[q][ii];
-    }
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int ii = 0; ii < 4; ++ii) {
+        const int row = (2 * rp + r) * 16 + out_row<P64>(g, ii);
+        const int c = cb * 64 + (q0 + q) * 16 + li;
+        out[(int64_t)row * J.npad + c] = acc[r][q][ii];
+      }
 }
 
 // Strips run in XCD order, so the strips of one chunk (which share its rows)
 // run on one XCD and share its L2.
-template <typename TX, int NB = 4>
+template <typename TX, int NB = 2>
 __global__ __launch_bounds__(64) void k_gram(const GramJob* __restrict__ jobs,
                                              const int* __restrict__ pre, int nj, int ntiles) {
   const int t = xcd_tile(blockIdx.x, gridDim.x);
@@ -301,18 +318,18 @@ __global__ __launch_bounds__(64) void k_gram(const GramJob* __restrict__ jobs,
   const int tile = t - pre[jb];
   const int chunk = tile / gram_strips(R);
   int s = tile - chunk * gram_strips(R);
-  // strip s -> (row group rg, column block cb), in the order gram_strips counts
+  // strip s -> (row pair rp, column block cb), in the order gram_strips counts
   const int ncb = (R + 63) / 64;
-  int rg = 0;
-  while (s >= ncb - rg / 4) { s -= ncb - rg / 4; ++rg; }
-  const int cb = rg / 4 + s;
-  const int q0 = (cb == rg / 4) ? (rg & 3) : 0;
+  int rp = 0;
+  while (s >= ncb - rp / 2) { s -= ncb - rp / 2; ++rp; }
+  const int cb = rp / 2 + s;
+  const int q0 = (cb == rp / 2) ? ((2 * rp) & 3) : 0;
   const int q1 = min(4, (R - cb * 64 + 15) / 16);
   switch (q1 - q0) {
-    case 1: gram_strip<TX, NB, 1>(J, chunk, rg, cb, q0); break;
-    case 2: gram_strip<TX, NB, 2>(J, chunk, rg, cb, q0); break;
-    case 3: gram_strip<TX, NB, 3>(J, chunk, rg, cb, q0); break;
-    default: gram_strip<TX, NB, 4>(J, chunk, rg, cb, q0); break;
+    case 1: gram_strip<TX, NB, 1>(J, chunk, rp, cb, q0); break;
+    case 2: gram_strip<TX, NB, 2>(J, chunk, rp, cb, q0); break;
+    case 3: gram_strip<TX, NB, 3>(J, chunk, rp, cb, q0); break;
+    default: gram_strip<TX, NB, 4>(J, chunk, rp, cb, q0); break;
   }
 }
 
