@@ -533,7 +533,8 @@ int build(rgsvd_plan_s* P, void* ws) {
         g.X1 = X; g.X2 = nullptr; g.out = (double*)WS(ws, s.gpart);
         g.ld1 = ld; g.ld2 = 0; g.r1 = s.L; g.r2 = 0; g.k0 = 0; g.k1 = len;
         g.npad = P->npadG; g.clen = gcl;
-        gj.push_back(g); gtl.push_back(gram_strips(s.L) * gch);
+        g.rgs = gram_rgs(s.L, gch);
+        gj.push_back(g); gtl.push_back(gram_strips(s.L, g.rgs) * gch);
         RedJob r{};
         r.in = WS(ws, s.gpart); r.out = WS(ws, s.gram); r.sq = nullptr;
         r.stride = (int64_t)P->npadG * P->npadG; r.count = r.stride;
@@ -553,7 +554,8 @@ int build(rgsvd_plan_s* P, void* ws) {
         int js = (sxp == P64) ? 2 : 1;
         atl.push_back((len + 64 * js - 1) / (64 * js));
       }
-      Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = wt; gs.tag = T_GRAM;
+      const int rgs = gram_uniform(gj, gtl);
+      Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = wt; gs.rt = rgs; gs.tag = T_GRAM;
       Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.ta = 0; r.td = 0; r.tag = T_RED;
       Stage& c = B.add(K_CHOL, cj, ctl); c.tag = T_CHOL;
       if (mixed) {
@@ -712,7 +714,8 @@ int build(rgsvd_plan_s* P, void* ws) {
       GramJob g{};
       g.X1 = WS(ws, s.Yt); g.X2 = nullptr; g.out = (double*)WS(ws, s.gpart);
       g.ld1 = s.ldy; g.ld2 = 0; g.r1 = 16; g.r2 = 0; g.k0 = 0; g.k1 = s.m; g.npad = 64; g.clen = s.gcl_m;
-      gj.push_back(g); gtl.push_back(gram_strips(16) * s.gch_m);
+      g.rgs = gram_rgs(16, s.gch_m);
+      gj.push_back(g); gtl.push_back(gram_strips(16, g.rgs) * s.gch_m);
       RedJob r{};
       r.in = WS(ws, s.gpart); r.out = WS(ws, s.gram); r.sq = nullptr;
       r.stride = 64 * 64; r.count = r.stride;
@@ -721,7 +724,8 @@ int build(rgsvd_plan_s* P, void* ws) {
       fj.push_back(FeatJob{(const double*)WS(ws, s.gram), (float*)WS(ws, P->off_feat) + 16 * i, 64, 0});
       ftl.push_back(1);
     }
-    Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = wt; gs.tag = T_GRAM;
+    const int rgs = gram_uniform(gj, gtl);
+      Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = wt; gs.rt = rgs; gs.tag = T_GRAM;
     Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.ta = 0; r.td = 0; r.tag = T_RED;
     B.add(K_FEAT, fj, ftl).tag = T_SMALL;
     add_orth(true, 1);
@@ -835,7 +839,8 @@ int build(rgsvd_plan_s* P, void* ws) {
         g.X1 = WS(ws, s->Yt); g.X2 = nullptr; g.out = (double*)WS(ws, s->gpart);
         g.ld1 = s->ldy; g.ld2 = 0; g.r1 = N; g.r2 = 0; g.k0 = 0; g.k1 = s->m;
         g.npad = P->npadG; g.clen = s->gcl_m;
-        gj.push_back(g); gtl.push_back(gram_strips(N) * s->gch_m);
+        g.rgs = gram_rgs(N, s->gch_m);
+        gj.push_back(g); gtl.push_back(gram_strips(N, g.rgs) * s->gch_m);
         RedJob r{};
         r.in = WS(ws, s->gpart); r.out = WS(ws, s->gram); r.sq = nullptr;
         r.stride = (int64_t)P->npadG * P->npadG; r.count = r.stride;
@@ -857,7 +862,8 @@ int build(rgsvd_plan_s* P, void* ws) {
         aj.push_back(a);
         atl.push_back((s->m + 64 * 2 - 1) / (64 * 2));
       }
-      Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = 0; gs.tag = T_GRAM;
+      const int rgs = gram_uniform(gj, gtl);
+      Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = 0; gs.rt = rgs; gs.tag = T_GRAM;
       Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.ta = 0; r.td = 0; r.tag = T_RED;
       Stage& c = B.add(K_CHOL, cj, ctl); c.tag = T_CHOL;
       Stage& a = B.add(K_AB, aj, atl);
@@ -921,7 +927,8 @@ int build(rgsvd_plan_s* P, void* ws) {
       g.X1 = WS(ws, s1.Wt); g.X2 = WS(ws, s2.Wt); g.out = (double*)WS(ws, pr.mpart);
       g.ld1 = s1.ldw; g.ld2 = s2.ldw; g.r1 = pr.l1; g.r2 = pr.l2; g.k0 = 0; g.k1 = (int)pr.n;
       g.npad = pr.Npad; g.clen = pr.gcl;
-      gj.push_back(g); gtl.push_back(gram_strips(pr.l1 + pr.l2) * pr.gch);
+      g.rgs = gram_rgs(pr.l1 + pr.l2, pr.gch);
+      gj.push_back(g); gtl.push_back(gram_strips(pr.l1 + pr.l2, g.rgs) * pr.gch);
       RedJob r{};
       r.in = WS(ws, pr.mpart); r.out = WS(ws, pr.M); r.sq = nullptr;
       r.stride = (int64_t)pr.Npad * pr.Npad; r.count = r.stride;
@@ -929,7 +936,8 @@ int build(rgsvd_plan_s* P, void* ws) {
       r.nz = pr.l1 + pr.l2;
       rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
     }
-    Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = wt; gs.tag = T_MGRAM;
+    const int rgs = gram_uniform(gj, gtl);
+      Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = wt; gs.rt = rgs; gs.tag = T_MGRAM;
     Stage& r = B.add(K_RED, rj, rtl); r.sym = true; r.tag = T_RED;
   }
   // small step: one launch, or stages around the block Jacobi sweeps on the
@@ -1048,8 +1056,10 @@ int build(rgsvd_plan_s* P, void* ws) {
         g.X1 = Lg; g.X2 = Lg; g.out = (double*)WS(ws, pr.mpart);
         g.ld1 = N; g.ld2 = N; g.r1 = t; g.r2 = 0; g.k0 = 0; g.k1 = pr.l1;
         g.npad = hpad; g.clen = hcl;
+        const int hparts = (pr.l1 + hcl - 1) / hcl;
+        g.rgs = gram_rgs(t, hparts);
         gj.push_back(g);
-        gtl.push_back(gram_strips(t) * ((pr.l1 + hcl - 1) / hcl));
+        gtl.push_back(gram_strips(t, g.rgs) * hparts);
         RedJob r{};
         r.in = WS(ws, pr.mpart); r.out = Lg + (size_t)N * t; r.sq = nullptr;
         r.stride = (int64_t)hpad * hpad; r.count = (int64_t)t * t;
@@ -1057,7 +1067,8 @@ int build(rgsvd_plan_s* P, void* ws) {
         r.nz = t;
         rj.push_back(r); rtl.push_back((int)((r.count + 255) / 256));
       }
-      Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = 0; gs.tag = T_SMALL;
+      const int rgs = gram_uniform(gj, gtl);
+      Stage& gs = B.add(K_GRAM, gj, gtl); gs.ta = 0; gs.rt = rgs; gs.tag = T_SMALL;
       Stage& rs = B.add(K_RED, rj, rtl); rs.sym = true; rs.tag = T_SMALL;
       add_small(5);
       add_bj(true);
@@ -1313,7 +1324,7 @@ int enqueue_list(rgsvd_plan_s* P, void* ws, hipStream_t st, const std::vector<St
       case K_COPY: hipLaunchKernelGGL(k_copy, dim3(s.tiles), dim3(64), 0, st, (const CopyJob*)j, pre, s.nj); break;
       case K_GEN: launch_gen(s.f64, (const GenJob*)j, pre, s.nj, s.tiles, st); break;
       case K_AB: launch_ab(s.prec, s.ta, s.tb, s.td, s.ct, s.js, (const AbJob*)j, pre, s.nj, s.tiles, st); break;
-      case K_GRAM: launch_gram(s.ta, (const GramJob*)j, pre, s.nj, s.tiles, st); break;
+      case K_GRAM: launch_gram(s.ta, s.rt, (const GramJob*)j, pre, s.nj, s.tiles, st); break;
       case K_RED: launch_reduce(s.ta, s.td, s.sym, (const RedJob*)j, pre, s.nj, s.tiles, st); break;
       case K_CHOL: launch_chol((const CholJob*)j, s.nj, st); break;
       case K_SMALL: launch_small((const SmallJob*)j, s.nj, st); break;

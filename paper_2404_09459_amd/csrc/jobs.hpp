@@ -3,6 +3,7 @@
 // counts maps blockIdx.x to (job, tile).  One launch thus serves both
 // matrices of a pair, or every matrix of a batch.
 #pragma once
+#include <vector>
 #include <stdint.h>
 
 namespace rg {
@@ -32,16 +33,37 @@ struct GramJob {
   const void* X1; const void* X2; double* out;
   int64_t ld1, ld2;
   int32_t r1, r2, k0, k1, npad, clen;
+  int32_t rgs, pad;   // row groups per strip (1 or 2, gram_rgs)
 };
 
-// Strips of a Gram over R rows: row pair rp (row groups 2 rp and 2 rp + 1,
-// 16 rows each) meets the 64-column blocks from rp / 2 to the last one that
-// starts below R.
-__host__ __device__ inline int gram_strips(int R) {
-  const int npr = (R + 31) / 32, ncb = (R + 63) / 64;
+// Strips of a Gram over R rows: strip row rp (row groups rgs rp ...
+// rgs rp + rgs - 1, 16 rows each) meets the 64-column blocks from
+// rgs rp / 4 to the last one that starts below R.
+__host__ __device__ inline int gram_strips(int R, int rgs) {
+  const int npr = (R + 16 * rgs - 1) / (16 * rgs), ncb = (R + 63) / 64;
   int s = 0;
-  for (int rp = 0; rp < npr; ++rp) s += ncb - rp / 2;
+  for (int rp = 0; rp < npr; ++rp) s += ncb - rp * rgs / 4;
   return s;
+}
+
+// Row groups per strip for a Gram over R rows in `chunks` row chunks: two
+// (each column fragment serves both, half the column reads) while that
+// still leaves 1024 single-wave strips to fill the device, else one.
+inline int gram_rgs(int R, int chunks) { return gram_strips(R, 2) * chunks >= 1024 ? 2 : 1; }
+
+// One strip height per launch (the two heights are separate kernels): two
+// row groups only when every job of the launch takes them; the tile counts
+// follow.  Returns the launch's rgs.
+inline int gram_uniform(std::vector<GramJob>& gj, std::vector<int>& gtl) {
+  int rgs = 2;
+  for (auto& g : gj) rgs = g.rgs < rgs ? g.rgs : rgs;
+  for (size_t i = 0; i < gj.size(); ++i) {
+    const int R = gj[i].r1 + gj[i].r2;
+    const int chunks = gtl[i] / gram_strips(R, gj[i].rgs);
+    gj[i].rgs = rgs;
+    gtl[i] = gram_strips(R, rgs) * chunks;
+  }
+  return rgs;
 }
 
 // out[r][c] = sum_{p < nparts} in[p*stride + r*ldi + c] in fixed order,

@@ -194,19 +194,19 @@ __global__ __launch_bounds__(256) void k_ab(const AbJob* __restrict__ jobs,
 
 // --------------------------------------------------------------- k_gram --
 // Partial Gram X[:, k0:k1] X[:, k0:k1]^T in fp64 MFMA over the R = r1 + r2
-// rows of X (X1's rows, then X2's).  One single-wave workgroup per strip: two
-// groups of 16 rows against the NQ (1..4) groups of 16 columns of one
-// 64-column block that start at or after the first row group's diagonal
-// group and below R (each B fragment serves both row groups).  The groups on
-// or above the diagonal are the Gram's; the one group of the second row
-// group that falls below it is written to the lower triangle, which the
-// reduction does not read (it mirrors the upper groups and zeroes rows and
-// columns at and past R).
-// No LDS: lane (g, li) reads 4 consecutive k of its two A rows and of its NQ
-// B rows straight from L2 (16 or 32 bytes per row), NB steps of 16 k ahead.
+// rows of X (X1's rows, then X2's).  One single-wave workgroup per strip: RG
+// (1 or 2) groups of 16 rows against the NQ (1..4) groups of 16 columns of
+// one 64-column block that start at or after the first row group's diagonal
+// group and below R (with RG = 2 each B fragment serves both row groups).
+// The groups on or above the diagonal are the Gram's; the one group of the
+// second row group that falls below it is written to the lower triangle,
+// which the reduction does not read (it mirrors the upper groups and zeroes
+// rows and columns at and past R).
+// No LDS: lane (g, li) reads 4 consecutive k of its A rows and of its NQ B
+// rows straight from L2 (16 or 32 bytes per row), NB steps of 16 k ahead.
 // The 4-wide loads need k0, clen, ld1 and ld2 to be multiples of 4 (the
 // plans pad leading dimensions to 64 and chunk lengths to 32).
-template <typename TX, int NB, int NQ>
+template <typename TX, int NB, int NQ, int RG>
 __device__ __forceinline__ void gram_strip(const GramJob& J, int chunk, int rp, int cb, int q0) {
   const int ln = threadIdx.x & 63, g = ln >> 4, li = ln & 15;
   const int kb = J.k0 + chunk * J.clen;
@@ -219,11 +219,11 @@ __device__ __forceinline__ void gram_strip(const GramJob& J, int chunk, int rp, 
     return nullptr;
   };
   // rows past R read row 0 of X1 scaled by zero (loads stay unconditional)
-  const TX* pa[2];
-  double wa[2];
+  const TX* pa[RG];
+  double wa[RG];
 #pragma unroll
-  for (int r = 0; r < 2; ++r) {
-    pa[r] = rowptr((2 * rp + r) * 16 + li);
+  for (int r = 0; r < RG; ++r) {
+    pa[r] = rowptr((RG * rp + r) * 16 + li);
     wa[r] = pa[r] ? 1.0 : 0.0;
     if (!pa[r]) pa[r] = X1;
   }
@@ -235,12 +235,12 @@ __device__ __forceinline__ void gram_strip(const GramJob& J, int chunk, int rp, 
     wb[q] = pb[q] ? 1.0 : 0.0;
     if (!pb[q]) pb[q] = X1;
   }
-  d4 acc[2][NQ];
+  d4 acc[RG][NQ];
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
+  for (int r = 0; r < RG; ++r)
 #pragma unroll
     for (int q = 0; q < NQ; ++q) acc[r][q] = d4{0, 0, 0, 0};
-  double ra[NB][2][4], rbv[NB][NQ][4];
+  double ra[NB][RG][4], rbv[NB][NQ][4];
   // 4 consecutive k from kx (kx % 4 == 0, kx < ke <= ld), zero at and past ke
   auto ld4 = [&](double* o, const TX* p, int kx, double w) {
     if constexpr (sizeof(TX) == 4) {
@@ -260,14 +260,14 @@ __device__ __forceinline__ void gram_strip(const GramJob& J, int chunk, int rp, 
     const int kx = kb + st * 16 + g * 4;
     if (kx < ke) {
 #pragma unroll
-      for (int r = 0; r < 2; ++r) ld4(ra[buf][r], pa[r], kx, wa[r]);
+      for (int r = 0; r < RG; ++r) ld4(ra[buf][r], pa[r], kx, wa[r]);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) ld4(rbv[buf][q], pb[q], kx, wb[q]);
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        ra[buf][0][e] = 0.0;
-        ra[buf][1][e] = 0.0;
+#pragma unroll
+        for (int r = 0; r < RG; ++r) ra[buf][r][e] = 0.0;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) rbv[buf][q][e] = 0.0;
       }
@@ -285,52 +285,58 @@ __device__ __forceinline__ void gram_strip(const GramJob& J, int chunk, int rp, 
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int r = 0; r < 2; ++r)
+        for (int r = 0; r < RG; ++r)
 #pragma unroll
           for (int q = 0; q < NQ; ++q) acc[r][q] = mma64(ra[u][r][e], rbv[u][q][e], acc[r][q]);
     }
   }
-  // lane holds D[out_row(g, ii)][li] of row group 2 rp + r, column group
-  // q0 + q (rows up to 32 npr - 1 < npad: npad is a multiple of 64)
+  // lane holds D[out_row(g, ii)][li] of row group RG rp + r, column group
+  // q0 + q (rows below 16 RG npr <= npad: npad is a multiple of 64)
   double* out = J.out + (int64_t)chunk * J.npad * J.npad;
 #pragma unroll
-  for (int r = 0; r < 2; ++r)
+  for (int r = 0; r < RG; ++r)
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
 #pragma unroll
       for (int ii = 0; ii < 4; ++ii) {
-        const int row = (2 * rp + r) * 16 + out_row<P64>(g, ii);
+        const int row = (RG * rp + r) * 16 + out_row<P64>(g, ii);
         const int c = cb * 64 + (q0 + q) * 16 + li;
         out[(int64_t)row * J.npad + c] = acc[r][q][ii];
       }
 }
 
+template <typename TX, int RG>
+__device__ __forceinline__ void gram_tile(const GramJob& J, int R, int tile) {
+  constexpr int NB = RG == 1 ? 4 : 2;   // loads in flight: two waves per SIMD either way
+  const int chunk = tile / gram_strips(R, RG);
+  int s = tile - chunk * gram_strips(R, RG);
+  // strip s -> (strip row rp, column block cb), in the order gram_strips counts
+  const int ncb = (R + 63) / 64;
+  int rp = 0;
+  while (s >= ncb - rp * RG / 4) { s -= ncb - rp * RG / 4; ++rp; }
+  const int cb = rp * RG / 4 + s;
+  const int q0 = (cb == rp * RG / 4) ? ((rp * RG) & 3) : 0;
+  const int q1 = min(4, (R - cb * 64 + 15) / 16);
+  switch (q1 - q0) {
+    case 1: gram_strip<TX, NB, 1, RG>(J, chunk, rp, cb, q0); break;
+    case 2: gram_strip<TX, NB, 2, RG>(J, chunk, rp, cb, q0); break;
+    case 3: gram_strip<TX, NB, 3, RG>(J, chunk, rp, cb, q0); break;
+    default: gram_strip<TX, NB, 4, RG>(J, chunk, rp, cb, q0); break;
+  }
+}
+
 // Strips run in XCD order, so the strips of one chunk (which share its rows)
 // run on one XCD and share its L2.
-template <typename TX, int NB = 2>
+// One strip height per kernel (the host gives every job of a launch the
+// same rgs), so each keeps its own register budget.
+template <typename TX, int RG>
 __global__ __launch_bounds__(64) void k_gram(const GramJob* __restrict__ jobs,
                                              const int* __restrict__ pre, int nj, int ntiles) {
   const int t = xcd_tile(blockIdx.x, gridDim.x);
   if (t >= ntiles) return;
   const int jb = find_side(pre, nj, t);
   const GramJob J = jobs[jb];
-  const int R = J.r1 + J.r2;
-  const int tile = t - pre[jb];
-  const int chunk = tile / gram_strips(R);
-  int s = tile - chunk * gram_strips(R);
-  // strip s -> (row pair rp, column block cb), in the order gram_strips counts
-  const int ncb = (R + 63) / 64;
-  int rp = 0;
-  while (s >= ncb - rp / 2) { s -= ncb - rp / 2; ++rp; }
-  const int cb = rp / 2 + s;
-  const int q0 = (cb == rp / 2) ? ((2 * rp) & 3) : 0;
-  const int q1 = min(4, (R - cb * 64 + 15) / 16);
-  switch (q1 - q0) {
-    case 1: gram_strip<TX, NB, 1>(J, chunk, rp, cb, q0); break;
-    case 2: gram_strip<TX, NB, 2>(J, chunk, rp, cb, q0); break;
-    case 3: gram_strip<TX, NB, 3>(J, chunk, rp, cb, q0); break;
-    default: gram_strip<TX, NB, 4>(J, chunk, rp, cb, q0); break;
-  }
+  gram_tile<TX, RG>(J, J.r1 + J.r2, t - pre[jb]);
 }
 
 // ------------------------------------------------------------- k_reduce --
@@ -398,10 +404,12 @@ void launch_gen(bool f64, const GenJob* j, const int* pre, int nj, int tiles, hi
   else hipLaunchKernelGGL((k_gen<float, false>), dim3(tiles), dim3(256), 0, st, j, pre, nj);
 }
 
-void launch_gram(int tx, const GramJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
+void launch_gram(int tx, int rgs, const GramJob* j, const int* pre, int nj, int tiles, hipStream_t st) {
   const dim3 grid(xcd_grid(tiles));
-  if (tx == 0) hipLaunchKernelGGL((k_gram<double>), grid, dim3(64), 0, st, j, pre, nj, tiles);
-  else hipLaunchKernelGGL((k_gram<float>), grid, dim3(64), 0, st, j, pre, nj, tiles);
+  if (tx == 0 && rgs == 2) hipLaunchKernelGGL((k_gram<double, 2>), grid, dim3(64), 0, st, j, pre, nj, tiles);
+  else if (tx == 0) hipLaunchKernelGGL((k_gram<double, 1>), grid, dim3(64), 0, st, j, pre, nj, tiles);
+  else if (rgs == 2) hipLaunchKernelGGL((k_gram<float, 2>), grid, dim3(64), 0, st, j, pre, nj, tiles);
+  else hipLaunchKernelGGL((k_gram<float, 1>), grid, dim3(64), 0, st, j, pre, nj, tiles);
 }
 
 void launch_reduce(int ti, int to, bool sym, const RedJob* j, const int* pre, int nj, int tiles,

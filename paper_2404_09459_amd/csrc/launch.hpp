@@ -11,7 +11,7 @@ void launch_zerog(const ZeroJob* j, const int* pre, int nj, int tiles, hipStream
 void launch_gen(bool f64, const GenJob* j, const int* pre, int nj, int tiles, hipStream_t st);
 void launch_ab(int prec, int ta, int tb, int td, int ct, int js, const AbJob* j, const int* pre,
                int nj, int tiles, hipStream_t st);
-void launch_gram(int tx, const GramJob* j, const int* pre, int nj, int tiles, hipStream_t st);
+void launch_gram(int tx, int rgs, const GramJob* j, const int* pre, int nj, int tiles, hipStream_t st);
 void launch_reduce(int ti, int to, bool sym, const RedJob* j, const int* pre, int nj, int tiles,
                    hipStream_t st);
 void launch_chol(const CholJob* j, int nj, hipStream_t st);
