@@ -357,8 +357,18 @@ __global__ __launch_bounds__(256) void k_reduce(const RedJob* __restrict__ jobs,
     else src = (int64_t)r * J.ldi + c;
     const TI* in = (const TI*)J.in;
     double s = 0.0;
-    if (!SYM || (r < J.nz && c < J.nz))
-      for (int p = 0; p < J.nparts; ++p) s += (double)in[p * J.stride + src];
+    if (!SYM || (r < J.nz && c < J.nz)) {
+      // eight loads in flight, then their sum in the same fixed order
+      int p = 0;
+      for (; p + 8 <= J.nparts; p += 8) {
+        TI v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = in[(int64_t)(p + u) * J.stride + src];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += (double)v[u];
+      }
+      for (; p < J.nparts; ++p) s += (double)in[(int64_t)p * J.stride + src];
+    }
     ((TO*)J.out)[(int64_t)r * J.ldo + c] = (TO)s;
   }
 }
