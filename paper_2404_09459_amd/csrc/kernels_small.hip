@@ -31,6 +31,31 @@ __device__ __forceinline__ void gram_diag_stats(const CholJob& J, int N, int np,
   }
 }
 
+// Lane ln's part of the sum of squares of a column of n <= SMALL_MAXN entries
+// in global memory (rows ln, ln + 64, ...), for a wave to reduce: all of the
+// lane's loads are issued before the first add (a loop over a runtime count
+// waits for each load in turn); the adds keep row order (the zeros past n add
+// nothing).  Rows below `split` go to *lo, the rest to *hi.
+static_assert(SMALL_MAXN <= 8 * 64, "a lane holds at most eight rows of a column");
+__device__ __forceinline__ void col_sumsq2(const double* col, int n, int split, int ln, double* lo, double* hi) {
+  double v[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int r = ln + 64 * u;
+    v[u] = r < n ? col[r] : 0.0;
+  }
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    if (ln + 64 * u < split) *lo += v[u] * v[u];
+    else *hi += v[u] * v[u];
+  }
+}
+__device__ __forceinline__ double col_sumsq(const double* col, int n, int ln) {
+  double s = 0.0, none = 0.0;
+  col_sumsq2(col, n, n, ln, &s, &none);
+  return s;
+}
+
 __device__ __forceinline__ double readlane_f64(double v, int lane) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)b, lane);
@@ -949,8 +974,7 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
       // thread walking a whole column serialises its loads)
       for (int c = tid >> 6; c < N; c += 16) {
         double s = 0.0;
-        if (c < rank)
-          for (int r = tid & 63; r < N; r += 64) { const double v = F[(int64_t)c * N + r]; s += v * v; }
+        if (c < rank) s = col_sumsq(F + (int64_t)c * N, N, tid & 63);
         s = wave_sum(s);
         if ((tid & 63) == 0) keys[c] = sqrt(s);
       }
@@ -1024,8 +1048,7 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
     }
     for (int c = tid >> 6; c < t; c += 16) {
       double s = 0.0;
-      if (c < rh)
-        for (int r = tid & 63; r < t; r += 64) { const double v = FH[(int64_t)c * t + r]; s += v * v; }
+      if (c < rh) s = col_sumsq(FH + (int64_t)c * t, t, tid & 63);
       s = wave_sum(s);
       if ((tid & 63) == 0) keys[c] = sqrt(s);
     }
@@ -1049,10 +1072,7 @@ __device__ __attribute__((always_inline)) inline void small_pair(const SmallJob&
   }
   for (int c = tid >> 6; c < t; c += 16) {
     double a = 0.0, b = 0.0;
-    for (int r = tid & 63; r < N; r += 64) {
-      const double v = J.Rcoef[(int64_t)c * J.ldr + r];
-      if (r < l1) a += v * v; else b += v * v;
-    }
+    col_sumsq2(J.Rcoef + (int64_t)c * J.ldr, N, l1, tid & 63, &a, &b);
     a = wave_sum(a);
     b = wave_sum(b);
     if ((tid & 63) == 0) { keys[c] = sqrt(a); sh.frow[c] = sqrt(b); }
@@ -1154,7 +1174,7 @@ __global__ __launch_bounds__(1024) void k_bjinit(const BJJob* __restrict__ jobs,
   if (sweep == 0) {
     for (int c = wave; c < nc; c += 16) {
       double v2 = 0.0;
-      for (int i = ln; i < nr; i += 64) { const double v = J.A[(int64_t)c * nr + i]; v2 += v * v; }
+      v2 = col_sumsq(J.A + (int64_t)c * nr, nr, ln);
       v2 = wave_sum(v2);
       if (ln == 0) n2[c] = v2;
     }
