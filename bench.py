@@ -44,8 +44,8 @@ FP64_VEC_PEAK_TF = 78.6
 # (k_bjinit + k_bjround + k_bjsweep, averaged over the launches of a run) and the small
 # step's k_small launches (averaged).  Kernels changed since their counters
 # were taken have no entry (traffic null).
-TRAFFIC = {"large": {"sketch": 1.659e9, "bjacobi": 2.808e6},
-           "medium": {"sketch": 0.743e9, "bjacobi": 0.777e6, "small": 1.394e6}}
+TRAFFIC = {"large": {"sketch": 1.659e9, "bjacobi": 2.805e6},
+           "medium": {"sketch": 0.743e9, "bjacobi": 0.776e6, "small": 1.397e6}}
 
 
 def log(*a):
