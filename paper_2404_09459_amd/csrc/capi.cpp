@@ -59,7 +59,7 @@ struct Stage {
   int tag = 0;
   size_t joff = 0, poff = 0;  // byte offsets of job array and prefix table in the job area
   int nj = 0, tiles = 0;
-  int prec = 0, gdt = 0, rt = 1, ct = 1, js = 1;
+  int prec = 0, gdt = 0, rt = 1, ct = 1, js = 1;   // rt: rows per tile (K_GRAM: row groups per strip)
   int ta = 0, tb = 0, td = 0;
   bool sym = false, f64 = false, split = false;
   size_t zoff = 0, zbytes = 0;  // K_ZERO: workspace range
