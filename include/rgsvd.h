@@ -87,7 +87,11 @@ extern "C" {
  * its first sweeps take one launch per round and its last three sweeps (most
  * often converged or nearly) one launch each, with a barrier between rounds,
  * when all workgroups of a sweep fit on the device at once (else per round).
- * Every choice turns the same pairs in the same order: same results. */
+ * Every choice turns the same pairs in the same order: same results.  The
+ * barrier's wait is bounded (about a second): if other work sharing the
+ * device keeps a sweep's workgroups from running together that long, the
+ * Jacobi ends there and the pair carries the sweep-limit flag; callers that
+ * share the device with long kernels can set RGSVD_OPT_JACOBI_ROUNDS. */
 #define RGSVD_OPT_JACOBI_ROUNDS 0x1 /* every sweep one launch per round                */
 #define RGSVD_OPT_JACOBI_SWEEPS 0x2 /* every sweep one launch, when it fits             */
 #define RGSVD_OPT_JACOBI_NOWAIT 0x4 /* for tests of the failure path: the barrier of a
